@@ -1,0 +1,193 @@
+/*
+ * mrs.h - C ABI of the MI355X (gfx950) library for the Method of Regularized
+ * Stokeslets (MRS) on Kirchhoff-rod filaments (arxiv 2604.12083).
+ *
+ * The library evaluates, for every point of an ensemble of filaments, the
+ * linear velocity U and angular velocity Omega induced by point forces f and
+ * torques n at all points (Sec. II.C, Eqs. velocity_field,
+ * angular_velocity_field, superposition), the discrete rod forces and torques
+ * with the half-angle mid frame (Sec. II.B, Eqs. discrete_f, discrete_n,
+ * F_comp_discrete, N_comp_discrete, mid_triad; Alg. 1; Sec. III.B.1), and
+ * explicit time steps that move positions and rotate frames (Sec. III.B.3,
+ * Eqs. newx, newD; Sec. III.A for the Runge-Kutta fine propagator).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Layout.  Positions, forces, torques, U and Omega are row-major n x 3
+ *   float64 arrays (point k at [3k .. 3k+2]).  Frames are n x 9 float64 with
+ *   D[9k + 3i + c] = component c of director D^{i+1} at point k (orthonormal,
+ *   right-handed, D^3 the tangent).  Filaments are concatenated; `offsets`
+ *   is a CSR array of n_fil + 1 int32 values, offsets[0] = 0, strictly
+ *   increasing, offsets[n_fil] = n.
+ * Physics.  f and n are the point force and torque exerted ON THE FLUID.
+ *   Every point is a target and a source; the sum includes j = i.  eps > 0
+ *   is the blob radius, mu > 0 the viscosity.  The kernel functions are those
+ *   of the blob phi_eps(r) = 15 eps^4 / (8 pi (r^2 + eps^2)^{7/2}).
+ * Precision.  MRS_FP64 does every operation in double precision.  MRS_FP32C
+ *   evaluates each pair in single precision on hi/lo-split positions and
+ *   sums with compensated single-precision accumulation per source block;
+ *   the per-target sum over blocks, the rod forces, the matrix square root,
+ *   the frame update and its re-orthonormalisation stay in double precision.
+ * Ownership.  The caller owns every array it passes; the library copies
+ *   host inputs and never keeps caller pointers past the call, except the
+ *   device pointers of the *_device calls until the work queued on the
+ *   given stream has finished.  The library owns the handles it returns;
+ *   free them with the matching destroy call.
+ * Errors.  Every call returns an mrs_status and never aborts the process.
+ *   MRS_EINVAL: a null handle or pointer, n < 0, eps <= 0, mu <= 0, a
+ *   non-finite scalar, a bad offsets array or an unknown enum value.
+ *   MRS_ENOMEM: a device or host allocation failed.  MRS_EDEVICE: a HIP
+ *   call failed (the context should then be destroyed).  MRS_ENUMERIC: a
+ *   result that was checked came out non-finite.  mrs_last_error gives a
+ *   message for the last failing call on the context.
+ * Threads and streams.  A context is not thread-safe.  Calls taking a
+ *   `stream` (a hipStream_t passed as void*, NULL = the context stream)
+ *   are asynchronous with respect to the host; all other calls return after
+ *   the device work they queued has finished unless stated otherwise.
+ */
+#ifndef MRS_H
+#define MRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MRS_OK = 0,
+    MRS_EINVAL = -1,
+    MRS_ENOMEM = -2,
+    MRS_EDEVICE = -3,
+    MRS_ENOTREADY = -4,
+    MRS_EBUSY = -5,
+    MRS_ENUMERIC = -6
+} mrs_status;
+
+typedef enum { MRS_FP64 = 0, MRS_FP32C = 1 } mrs_precision;
+
+/* Forward Euler (Eqs. newx, newD) and the classical four-stage Runge-Kutta
+ * method with Rodrigues frame updates. */
+typedef enum { MRS_EULER = 1, MRS_RK4 = 4 } mrs_integrator;
+
+/* Rod moduli (Sec. II.A, Eq. constitutive_N_F): a = bending, bending, twist;
+ * b = shear, shear, stretch; omega0 = intrinsic strain-twist vector;
+ * ds = arclength spacing of the discretisation (Sec. II.B). */
+typedef struct {
+    double a[3];
+    double b[3];
+    double omega0[3];
+    double ds;
+} mrs_rod_params;
+
+typedef struct mrs_context mrs_context;
+typedef struct mrs_ensemble mrs_ensemble;
+typedef struct mrs_server mrs_server;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device` with its own non-blocking stream
+ * (default priority).  *out receives the handle. */
+mrs_status mrs_context_create(int device, mrs_context **out);
+void mrs_context_destroy(mrs_context *ctx);
+/* Message of the last failing call on ctx; valid until the next call. */
+const char *mrs_last_error(const mrs_context *ctx);
+/* Make `stream` (a hipStream_t, NULL = the context's own) the stream every
+ * later call on ctx queues its work on. */
+mrs_status mrs_context_set_stream(mrs_context *ctx, void *stream);
+/* Wait until all work queued on the context stream has finished. */
+mrs_status mrs_context_synchronize(mrs_context *ctx);
+
+/* ---- one-shot MRS evaluation (Eqs. velocity_field, angular_velocity_field,
+ *      superposition; Alg. 2 is the paper's GPU form of it) -------------- */
+
+/* U, Omega at all n points from f, torque at the same points.  Host arrays
+ * (n x 3), synchronous.  n = 0 is allowed and does nothing. */
+mrs_status mrs_eval_host(mrs_context *ctx, int64_t n, const double *X, const double *f,
+                         const double *torque, double eps, double mu, mrs_precision prec,
+                         double *U, double *Omega);
+
+/* Same on caller-owned device arrays (n x 3 each), queued on `stream`. */
+mrs_status mrs_eval_device(mrs_context *ctx, int64_t n, const double *dX, const double *df,
+                           const double *dtorque, double eps, double mu, mrs_precision prec,
+                           double *dU, double *dOmega, void *stream);
+
+/* ---- rod mechanics (Sec. II.B, Alg. 1, Sec. III.B.1) ------------------- */
+
+/* Point force g and torque m exerted on the fluid by every node:
+ * g_k = F_{k+1/2} - F_{k-1/2} + fext_k,
+ * m_k = N_{k+1/2} - N_{k-1/2} + (dX_{k+1/2} x F_{k+1/2} + dX_{k-1/2} x F_{k-1/2})/2 + next_k,
+ * i.e. -ds times the paper's fluid-on-rod densities f_k, n_k, with F, N of
+ * the absent end segments zero (free ends).  `offsets` is a host array;
+ * dX (n x 3), dD (n x 9), dfext, dnext (n x 3, may be NULL = zero), dg, dm
+ * (n x 3) are device arrays.  Queued on `stream`. */
+mrs_status mrs_rod_forces_device(mrs_context *ctx, int32_t n_fil, const int32_t *offsets,
+                                 const double *dX, const double *dD, const mrs_rod_params *rod,
+                                 const double *dfext, const double *dnext, double *dg, double *dm,
+                                 void *stream);
+
+/* Principal square roots S (rotation by half the angle about the same axis,
+ * Eq. halfangle) of `count` proper rotations R.  dR, dS: device arrays of
+ * count row-major 3x3 float64 matrices.  At an angle of exactly pi either
+ * root may be returned.  Queued on `stream`. */
+mrs_status mrs_rotsqrt_device(mrs_context *ctx, int64_t count, const double *dR, double *dS,
+                              void *stream);
+
+/* ---- device-resident ensembles ---------------------------------------- */
+
+/* Copy a filament ensemble to the device: offsets (n_fil + 1), X (n x 3),
+ * D (n x 9), external point loads f_ext, n_ext (n x 3, NULL = zero; held
+ * constant during steps), eps, mu and the rod moduli. */
+mrs_status mrs_ensemble_create(mrs_context *ctx, int32_t n_fil, const int32_t *offsets,
+                               const double *X, const double *D, const double *f_ext,
+                               const double *n_ext, double eps, double mu,
+                               const mrs_rod_params *rod, mrs_ensemble **out);
+/* Replace the state (host arrays; either may be NULL to keep it). */
+mrs_status mrs_ensemble_set_state(mrs_ensemble *ens, const double *X, const double *D);
+/* Number of points. */
+mrs_status mrs_ensemble_size(const mrs_ensemble *ens, int64_t *n);
+/* U, Omega at the current state from the rod forces (if include_elastic)
+ * plus the external loads. */
+mrs_status mrs_ensemble_eval(mrs_ensemble *ens, mrs_precision prec, int include_elastic);
+/* nsteps explicit steps of size dt.  Every step ends with the frame
+ * re-orthonormalisation D3 <- D3/|D3|, D1 <- unit(D1 - (D1.D3) D3),
+ * D2 <- D3 x D1.  After the call U, Omega hold the first-stage velocities
+ * of the last step. */
+mrs_status mrs_ensemble_step(mrs_ensemble *ens, mrs_integrator integ, double dt, int32_t nsteps,
+                             mrs_precision prec, int include_elastic);
+/* Copy state and last velocities to host arrays (any may be NULL). */
+mrs_status mrs_ensemble_get(mrs_ensemble *ens, double *X, double *D, double *U, double *Omega);
+void mrs_ensemble_destroy(mrs_ensemble *ens);
+
+/* ---- batching --------------------------------------------------------- */
+
+/* Advance n_ens independent ensembles (e.g. the fine-propagator time slices
+ * of one Parareal iteration, Sec. II.D) together: every kernel of a stage
+ * covers all of them, and with use_graph != 0 the nsteps x stages launch
+ * sequence is captured once into a HIP graph and replayed.  Ensembles never
+ * interact; each result equals the one of mrs_ensemble_step on it alone.
+ * All ensembles must belong to ctx and be distinct. */
+mrs_status mrs_batch_step(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *ens,
+                          mrs_integrator integ, double dt, int32_t nsteps, mrs_precision prec,
+                          int include_elastic, int use_graph);
+/* One U, Omega evaluation of every listed ensemble in one launch sequence. */
+mrs_status mrs_batch_eval(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *ens,
+                          mrs_precision prec, int include_elastic);
+
+/* ---- kernel timing ---------------------------------------------------- */
+
+/* When enabled, every kernel launch of the context is bracketed by HIP events
+ * on the stream it is launched on.  mrs_profile_query waits for the recorded
+ * events and returns the launch count and summed duration (milliseconds) of
+ * the kernels whose name contains `kernel` (NULL or "" = all). */
+mrs_status mrs_profile_enable(mrs_context *ctx, int on);
+mrs_status mrs_profile_reset(mrs_context *ctx);
+mrs_status mrs_profile_query(mrs_context *ctx, const char *kernel, int64_t *launches,
+                             double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRS_H */

@@ -1,0 +1,268 @@
+"""Python binding of libmrs.so, the MI355X (gfx950) MRS filament library.
+
+Argument marshalling only: every function forwards to the C entry point of
+the same name declared in include/mrs.h, and every step of the computation
+runs in the library's HIP kernels.  torch is imported first so that the
+library shares torch's HIP runtime; torch tensors may be passed where the C
+call takes device pointers (their data_ptr is used) and the current torch
+stream may be passed as `stream`.
+
+The library must be built (``python -m paper_2604_12083_amd.build`` or
+``__graft_entry__.build()``); importing this package without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+try:  # share torch's HIP runtime when torch is present
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover - torch is part of the image
+    torch = None
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrs.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mrs.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_12083_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MRS_OK, MRS_EINVAL, MRS_ENOMEM, MRS_EDEVICE, MRS_ENOTREADY, MRS_EBUSY, MRS_ENUMERIC = 0, -1, -2, -3, -4, -5, -6
+MRS_FP64, MRS_FP32C = 0, 1
+MRS_EULER, MRS_RK4 = 1, 4
+STATUS_NAMES = {0: "MRS_OK", -1: "MRS_EINVAL", -2: "MRS_ENOMEM", -3: "MRS_EDEVICE", -4: "MRS_ENOTREADY",
+                -5: "MRS_EBUSY", -6: "MRS_ENUMERIC"}
+
+
+class mrs_rod_params(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double * 3), ("b", ctypes.c_double * 3), ("omega0", ctypes.c_double * 3),
+                ("ds", ctypes.c_double)]
+
+
+class MrsError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_vp = ctypes.c_void_p
+_d = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+_dbl = ctypes.c_double
+
+_SIGS = {
+    "mrs_context_create": (_int, [_int, ctypes.POINTER(_vp)]),
+    "mrs_context_destroy": (None, [_vp]),
+    "mrs_last_error": (ctypes.c_char_p, [_vp]),
+    "mrs_context_set_stream": (_int, [_vp, _vp]),
+    "mrs_context_synchronize": (_int, [_vp]),
+    "mrs_eval_host": (_int, [_vp, _i64, _vp, _vp, _vp, _dbl, _dbl, _int, _vp, _vp]),
+    "mrs_eval_device": (_int, [_vp, _i64, _vp, _vp, _vp, _dbl, _dbl, _int, _vp, _vp, _vp]),
+    "mrs_rod_forces_device": (_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.POINTER(mrs_rod_params), _vp, _vp,
+                                     _vp, _vp, _vp]),
+    "mrs_rotsqrt_device": (_int, [_vp, _i64, _vp, _vp, _vp]),
+    "mrs_ensemble_create": (_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl,
+                                   ctypes.POINTER(mrs_rod_params), ctypes.POINTER(_vp)]),
+    "mrs_ensemble_set_state": (_int, [_vp, _vp, _vp]),
+    "mrs_ensemble_size": (_int, [_vp, ctypes.POINTER(_i64)]),
+    "mrs_ensemble_eval": (_int, [_vp, _int, _int]),
+    "mrs_ensemble_step": (_int, [_vp, _int, _dbl, ctypes.c_int32, _int, _int]),
+    "mrs_ensemble_get": (_int, [_vp, _vp, _vp, _vp, _vp]),
+    "mrs_ensemble_destroy": (None, [_vp]),
+    "mrs_batch_step": (_int, [_vp, ctypes.c_int32, _vp, _int, _dbl, ctypes.c_int32, _int, _int, _int]),
+    "mrs_batch_eval": (_int, [_vp, ctypes.c_int32, _vp, _int, _int]),
+    "mrs_profile_enable": (_int, [_vp, _int]),
+    "mrs_profile_reset": (_int, [_vp]),
+    "mrs_profile_query": (_int, [_vp, ctypes.c_char_p, ctypes.POINTER(_i64), ctypes.POINTER(_dbl)]),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    if hasattr(_lib, _name):
+        _f = getattr(_lib, _name)
+        _f.restype = _res
+        _f.argtypes = _args
+
+
+def declared_functions(header: str = HEADER):
+    """Names of the functions include/mrs.h declares."""
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mrs_[a-z0-9_]+)\s*\(", text)))
+
+
+def _ptr(x):
+    """Address of a host numpy array, a torch tensor (device or host), an int or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return x.ctypes.data
+    if torch is not None and isinstance(x, torch.Tensor):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr()
+    if isinstance(x, ctypes.c_void_p):
+        return x.value
+    raise TypeError(f"cannot pass {type(x)} as a pointer")
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    if torch is not None and isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    raise TypeError("stream must be None, an int handle or a torch.cuda.Stream")
+
+
+def _check(status, ctx=None):
+    if status != MRS_OK:
+        msg = _lib.mrs_last_error(ctx).decode() if ctx else ""
+        raise MrsError(status, msg)
+
+
+def _f64(a, cols):
+    return np.ascontiguousarray(a, dtype=np.float64).reshape(-1, cols)
+
+
+def rod_params(a=(1e-4, 1e-4, 1e-4), b=(1.0, 1.0, 1.0), omega0=(0.0, 0.0, 0.0), ds=1.0 / 64) -> mrs_rod_params:
+    p = mrs_rod_params()
+    p.a[:] = [float(v) for v in a]
+    p.b[:] = [float(v) for v in b]
+    p.omega0[:] = [float(v) for v in omega0]
+    p.ds = float(ds)
+    return p
+
+
+# ---- thin wrappers with the C names ------------------------------------
+
+
+def mrs_context_create(device: int = 0):
+    h = _vp()
+    _check(_lib.mrs_context_create(int(device), ctypes.byref(h)))
+    return h
+
+
+def mrs_context_destroy(ctx) -> None:
+    _lib.mrs_context_destroy(ctx)
+
+
+def mrs_last_error(ctx) -> str:
+    return _lib.mrs_last_error(ctx).decode()
+
+
+def mrs_context_set_stream(ctx, stream=None) -> None:
+    _check(_lib.mrs_context_set_stream(ctx, _stream(stream)), ctx)
+
+
+def mrs_context_synchronize(ctx) -> None:
+    _check(_lib.mrs_context_synchronize(ctx), ctx)
+
+
+def mrs_eval_host(ctx, X, f, n, eps, mu=1.0, prec=MRS_FP64):
+    X, f, n = _f64(X, 3), _f64(f, 3), _f64(n, 3)
+    U = np.empty_like(X)
+    W = np.empty_like(X)
+    _check(_lib.mrs_eval_host(ctx, X.shape[0], _ptr(X), _ptr(f), _ptr(n), float(eps), float(mu), int(prec),
+                              _ptr(U), _ptr(W)), ctx)
+    return U, W
+
+
+def mrs_eval_device(ctx, n_points, dX, df, dn, eps, mu, prec, dU, dW, stream=None) -> None:
+    _check(_lib.mrs_eval_device(ctx, int(n_points), _ptr(dX), _ptr(df), _ptr(dn), float(eps), float(mu), int(prec),
+                                _ptr(dU), _ptr(dW), _stream(stream)), ctx)
+
+
+def mrs_rod_forces_device(ctx, offsets, dX, dD, rod, dfext, dnext, dg, dm, stream=None) -> None:
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    _check(_lib.mrs_rod_forces_device(ctx, len(off) - 1, _ptr(off), _ptr(dX), _ptr(dD), ctypes.byref(rod),
+                                      _ptr(dfext), _ptr(dnext), _ptr(dg), _ptr(dm), _stream(stream)), ctx)
+
+
+def mrs_rotsqrt_device(ctx, count, dR, dS, stream=None) -> None:
+    _check(_lib.mrs_rotsqrt_device(ctx, int(count), _ptr(dR), _ptr(dS), _stream(stream)), ctx)
+
+
+def mrs_ensemble_create(ctx, offsets, X, D, f_ext, n_ext, eps, mu, rod):
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    X, D = _f64(X, 3), _f64(D, 9)
+    fe = None if f_ext is None else _f64(f_ext, 3)
+    ne = None if n_ext is None else _f64(n_ext, 3)
+    h = _vp()
+    _check(_lib.mrs_ensemble_create(ctx, len(off) - 1, _ptr(off), _ptr(X), _ptr(D), _ptr(fe), _ptr(ne), float(eps),
+                                    float(mu), ctypes.byref(rod), ctypes.byref(h)), ctx)
+    return h
+
+
+def mrs_ensemble_set_state(ctx, ens, X=None, D=None) -> None:
+    X = None if X is None else _f64(X, 3)
+    D = None if D is None else _f64(D, 9)
+    _check(_lib.mrs_ensemble_set_state(ens, _ptr(X), _ptr(D)), ctx)
+
+
+def mrs_ensemble_size(ens) -> int:
+    n = _i64()
+    _check(_lib.mrs_ensemble_size(ens, ctypes.byref(n)))
+    return int(n.value)
+
+
+def mrs_ensemble_eval(ctx, ens, prec=MRS_FP64, include_elastic=True) -> None:
+    _check(_lib.mrs_ensemble_eval(ens, int(prec), int(bool(include_elastic))), ctx)
+
+
+def mrs_ensemble_step(ctx, ens, integ, dt, nsteps, prec=MRS_FP64, include_elastic=True) -> None:
+    _check(_lib.mrs_ensemble_step(ens, int(integ), float(dt), int(nsteps), int(prec), int(bool(include_elastic))),
+           ctx)
+
+
+def mrs_ensemble_get(ctx, ens):
+    n = mrs_ensemble_size(ens)
+    X, D, U, W = np.empty((n, 3)), np.empty((n, 9)), np.empty((n, 3)), np.empty((n, 3))
+    _check(_lib.mrs_ensemble_get(ens, _ptr(X), _ptr(D), _ptr(U), _ptr(W)), ctx)
+    return X, D, U, W
+
+
+def mrs_ensemble_destroy(ens) -> None:
+    _lib.mrs_ensemble_destroy(ens)
+
+
+def _ens_array(ens_list):
+    arr = (_vp * len(ens_list))(*[e.value if isinstance(e, _vp) else e for e in ens_list])
+    return arr
+
+
+def mrs_batch_step(ctx, ens_list, integ, dt, nsteps, prec=MRS_FP32C, include_elastic=True, use_graph=True) -> None:
+    arr = _ens_array(ens_list)
+    _check(_lib.mrs_batch_step(ctx, len(ens_list), ctypes.cast(arr, _vp), int(integ), float(dt), int(nsteps),
+                               int(prec), int(bool(include_elastic)), int(bool(use_graph))), ctx)
+
+
+def mrs_batch_eval(ctx, ens_list, prec=MRS_FP32C, include_elastic=True) -> None:
+    arr = _ens_array(ens_list)
+    _check(_lib.mrs_batch_eval(ctx, len(ens_list), ctypes.cast(arr, _vp), int(prec), int(bool(include_elastic))), ctx)
+
+
+def mrs_profile_enable(ctx, on=True) -> None:
+    _check(_lib.mrs_profile_enable(ctx, int(bool(on))), ctx)
+
+
+def mrs_profile_reset(ctx) -> None:
+    _check(_lib.mrs_profile_reset(ctx), ctx)
+
+
+def mrs_profile_query(ctx, kernel=""):
+    n = _i64()
+    ms = _dbl()
+    _check(_lib.mrs_profile_query(ctx, kernel.encode() if kernel else None, ctypes.byref(n), ctypes.byref(ms)), ctx)
+    return int(n.value), float(ms.value)

@@ -1,0 +1,92 @@
+// Internal types shared by the HIP kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrs {
+
+// Threads per block of every kernel on the path (4 wave64s).
+constexpr int kBlock = 256;
+// Sources staged in LDS per tile of the tiled pair kernel.
+constexpr int kSrcTile = 256;
+// Sources summed in plain FP32 before one compensated (Kahan) update.
+constexpr int kKahanBlock = 64;
+// Targets per wave in the small-N pair kernel (lanes split the sources).
+constexpr int kSplitTargetsPerWave = 4;
+constexpr int kSplitTargetsPerBlock = kSplitTargetsPerWave * (kBlock / 64);
+
+// Source record of the FP32C pair kernel, 48 bytes, read as three float4:
+//   a = (xh, yh, zh, fx)  b = (xl, yl, zl, fy)  c = (fz, nx, ny, nz)
+// with positions scaled by 1/eps and split hi + lo, forces scaled by 1/eps
+// and torques by 1/eps^2.
+struct alignas(16) RecF32 {
+    float4 a, b, c;
+};
+
+// Source record of the FP64 pair kernel, 80 bytes (five 16-byte words).
+struct alignas(16) RecF64 {
+    double x, y, z, fx, fy, fz, nx, ny, nz, pad;
+};
+
+// Everything a kernel needs to know about one ensemble.  Arrays are SoA:
+// component c of point i of an N-point vector field lives at [c * N + i];
+// director i, component c of point k at [(3 i + c) * N + k].
+struct EnsDesc {
+    int32_t N;
+    int32_t n_fil;
+    int32_t K;         // source chunks of the split-K pair kernel
+    int32_t aos_io;    // 1: X/f/n inputs and U/W outputs are n x 3 row-major
+    const int32_t *off;
+    double *X, *D;     // state (SoA)
+    double *Xs, *Ds;   // RK stage state (SoA)
+    double *U, *W;     // velocities (SoA, or AoS when aos_io)
+    double *Ua, *Wa;   // RK weighted sums (SoA)
+    const double *fext, *next;  // external loads (SoA, or AoS when aos_io), may be null
+    const double *Xin_aos;      // AoS positions when aos_io
+    void *rec;         // source records (RecF32 or RecF64), N entries
+    double *part;      // split-K partial sums [K][6][N]
+    double *g_out, *m_out;  // optional AoS copies of the rod loads (tests)
+    double eps, inv_eps, mu;
+    double cU, cW;     // 1/(8 pi mu) and the Omega scale of the record form
+    double a[3], b[3], om0[3], ds;
+};
+
+// One block of a pair kernel: targets [tgt0, tgt0 + ntgt) against sources
+// [src0, src0 + nsrc) of ensemble `ens`, written to split-K chunk `chunk`.
+struct PairItem {
+    int32_t ens, tgt0, ntgt, src0, nsrc, chunk;
+};
+
+// One block of the rod-force kernel: filament `fil` of ensemble `ens`.
+struct RodItem {
+    int32_t ens, fil;
+};
+
+// One block of the reduction/epilogue kernel: points [p0, p0 + kBlock).
+struct PointItem {
+    int32_t ens, p0;
+};
+
+enum Epilogue : int {
+    EPI_WRITE = 0,     // U, W only
+    EPI_EULER = 1,     // U, W and a forward Euler step
+    EPI_RK4_STAGE = 2, // accumulate stage s, build stage state s + 1
+    EPI_RK4_FINAL = 3, // accumulate last stage, finish the step
+};
+
+// Launch wrappers (mrs_kernels.hip).  All return the launch's hipError_t.
+hipError_t launch_pack_aos(int prec, const EnsDesc *d_desc, const EnsDesc &h_desc,
+                           hipStream_t s);
+hipError_t launch_rod_forces(int prec, int stage_state, int elastic, const EnsDesc *d_desc,
+                             const RodItem *d_items, int n_items, hipStream_t s);
+hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, const PairItem *d_items,
+                        int n_items, hipStream_t s);
+hipError_t launch_reduce(int epi, int stage, double dt, const EnsDesc *d_desc,
+                         const PointItem *d_items, int n_items, hipStream_t s);
+hipError_t launch_rotsqrt(int64_t count, const double *R, double *S, hipStream_t s);
+
+// Pair-kernel modes.
+enum PairMode : int { PAIR_TILE = 0, PAIR_SPLIT = 1 };
+
+}  // namespace mrs

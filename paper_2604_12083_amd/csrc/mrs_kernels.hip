@@ -1,0 +1,706 @@
+// HIP kernels (gfx950) of the MRS filament path.
+//
+//   k_pack_aos        n x 3 caller arrays -> source records
+//   k_rod_forces      per segment: A = sum_j D^j_{k+1} (D^j_k)^T, its principal
+//                     square root, mid frame, F and N (Sec. II.B, Eqs.
+//                     mid_triad, F_comp_discrete, N_comp_discrete; Alg. 1);
+//                     per node: the point force and torque on the fluid
+//                     (Eqs. discrete_f, discrete_n) written straight into the
+//                     pair kernel's source records
+//   k_pairs_tile_*    all-pairs MRS sum (Eqs. velocity_field,
+//                     angular_velocity_field, superposition): one lane per
+//                     target (T targets per lane), sources staged through LDS
+//                     and broadcast to the wave, split-K over source chunks
+//   k_pairs_split     small-ensemble form: a wave owns a few targets, its lanes
+//                     stride over the sources and the sums are combined with
+//                     wave shuffles
+//   k_reduce<EPI>     fixed-order FP64 sum of the split-K partials, scaling,
+//                     and the element-wise step epilogue (Eqs. newx, newD)
+//   k_rotsqrt         batched principal 3x3 rotation square root
+//
+// Kernel functions.  With R^2 = r^2 + eps^2, Q = 1/R and H_i the kernel
+// functions of the blob phi_eps (Sec. II.C), 8 pi H_i are
+//   H1: Q + eps^2 Q^3            H2: Q^3
+//   H3: Q^3 + 1.5 eps^2 Q^5      H4: 3.75 eps^4 Q^7 - 0.75 eps^2 Q^5 - 0.5 Q^3
+//   H5: 1.5 Q^5 + 3.75 eps^2 Q^7
+// The FP32C form works in units of eps (rho = r/eps, f~ = f/eps,
+// n~ = n/eps^2), where the same expressions hold with eps = 1 and
+// U = sum/(8 pi mu), Omega = sum/(8 pi mu eps); this keeps every FP32
+// intermediate far from overflow and folds all constants into one FP64
+// scale per target.
+#include <hip/hip_runtime.h>
+
+#include "mrs_internal.h"
+
+namespace mrs {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ float rsq_f32(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Hardware reciprocal square root refined by one third-order step
+// q <- q (1 + e/2 + 3 e^2/8), e = 1 - x q^2, which takes the hardware
+// estimate to double precision.
+__device__ __forceinline__ double rsq_f64(double x) {
+    double q = __builtin_amdgcn_rsq(x);
+    double e = fma(-x, q * q, 1.0);
+    double p = fma(0.375, e, 0.5);
+    return fma(q * e, p, q);
+}
+
+__device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
+    float y = x - c;
+    float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Contribution of one source to p[0..5] = (8 pi mu U, 8 pi mu eps Omega) of one
+// target, in units of eps.  Target position = th + tl (hi/lo split).
+__device__ __forceinline__ void pair_f32(float thx, float thy, float thz, float tlx, float tly,
+                                         float tlz, const float4 A, const float4 B,
+                                         const float4 C, float *p) {
+    const float rx = (thx - A.x) + (tlx - B.x);
+    const float ry = (thy - A.y) + (tly - B.y);
+    const float rz = (thz - A.z) + (tlz - B.z);
+    const float fx = A.w, fy = B.w, fz = C.x, nx = C.y, ny = C.z, nz = C.w;
+    const float R2 = fmaf(rz, rz, fmaf(ry, ry, fmaf(rx, rx, 1.0f)));
+    const float q = rsq_f32(R2);
+    const float q2 = q * q, q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
+    const float h1 = q + q3;
+    const float t = 1.5f * q5;
+    const float h3 = q3 + t;
+    const float u = 3.75f * q7;
+    const float h5 = u + t;
+    const float h4 = fmaf(-0.5f, h3, u);
+    const float fr = fmaf(fz, rz, fmaf(fy, ry, fx * rx));
+    const float nr = fmaf(nz, rz, fmaf(ny, ry, nx * rx));
+    const float a = q3 * fr, b = h5 * nr;
+    const float cx = fmaf(ny, rz, -nz * ry), cy = fmaf(nz, rx, -nx * rz), cz = fmaf(nx, ry, -ny * rx);
+    const float dx = fmaf(fy, rz, -fz * ry), dy = fmaf(fz, rx, -fx * rz), dz = fmaf(fx, ry, -fy * rx);
+    p[0] = fmaf(h3, cx, fmaf(a, rx, fmaf(h1, fx, p[0])));
+    p[1] = fmaf(h3, cy, fmaf(a, ry, fmaf(h1, fy, p[1])));
+    p[2] = fmaf(h3, cz, fmaf(a, rz, fmaf(h1, fz, p[2])));
+    p[3] = fmaf(b, rx, fmaf(h4, nx, fmaf(h3, dx, p[3])));
+    p[4] = fmaf(b, ry, fmaf(h4, ny, fmaf(h3, dy, p[4])));
+    p[5] = fmaf(b, rz, fmaf(h4, nz, fmaf(h3, dz, p[5])));
+}
+
+// Same in FP64 and unscaled units: p = (8 pi mu U, 8 pi mu Omega).
+__device__ __forceinline__ void pair_f64(double tx, double ty, double tz, double x, double y,
+                                         double z, double fx, double fy, double fz, double nx,
+                                         double ny, double nz, double e2, double c375e2,
+                                         double *p) {
+    const double rx = tx - x, ry = ty - y, rz = tz - z;
+    const double R2 = fma(rz, rz, fma(ry, ry, fma(rx, rx, e2)));
+    const double q = rsq_f64(R2);
+    const double q2 = q * q, q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
+    const double h1 = fma(e2, q3, q);
+    const double t = 1.5 * q5;
+    const double h3 = fma(e2, t, q3);
+    const double u = c375e2 * q7;
+    const double h5 = t + u;
+    const double h4 = fma(-0.5, h3, e2 * u);
+    const double fr = fma(fz, rz, fma(fy, ry, fx * rx));
+    const double nr = fma(nz, rz, fma(ny, ry, nx * rx));
+    const double a = q3 * fr, b = h5 * nr;
+    const double cx = fma(ny, rz, -nz * ry), cy = fma(nz, rx, -nx * rz), cz = fma(nx, ry, -ny * rx);
+    const double dx = fma(fy, rz, -fz * ry), dy = fma(fz, rx, -fx * rz), dz = fma(fx, ry, -fy * rx);
+    p[0] = fma(h3, cx, fma(a, rx, fma(h1, fx, p[0])));
+    p[1] = fma(h3, cy, fma(a, ry, fma(h1, fy, p[1])));
+    p[2] = fma(h3, cz, fma(a, rz, fma(h1, fz, p[2])));
+    p[3] = fma(b, rx, fma(h4, nx, fma(h3, dx, p[3])));
+    p[4] = fma(b, ry, fma(h4, ny, fma(h3, dy, p[4])));
+    p[5] = fma(b, rz, fma(h4, nz, fma(h3, dz, p[5])));
+}
+
+__device__ __forceinline__ RecF32 make_rec_f32(double x, double y, double z, double fx, double fy,
+                                               double fz, double nx, double ny, double nz,
+                                               double inv_eps) {
+    const double sx = x * inv_eps, sy = y * inv_eps, sz = z * inv_eps;
+    const float hx = (float)sx, hy = (float)sy, hz = (float)sz;
+    const float lx = (float)(sx - (double)hx), ly = (float)(sy - (double)hy), lz = (float)(sz - (double)hz);
+    const double ie2 = inv_eps * inv_eps;
+    RecF32 r;
+    r.a = make_float4(hx, hy, hz, (float)(fx * inv_eps));
+    r.b = make_float4(lx, ly, lz, (float)(fy * inv_eps));
+    r.c = make_float4((float)(fz * inv_eps), (float)(nx * ie2), (float)(ny * ie2), (float)(nz * ie2));
+    return r;
+}
+
+__device__ __forceinline__ void store_rec(int prec, void *rec, int i, double x, double y, double z,
+                                          double fx, double fy, double fz, double nx, double ny,
+                                          double nz, double inv_eps) {
+    if (prec == 1) {
+        reinterpret_cast<RecF32 *>(rec)[i] = make_rec_f32(x, y, z, fx, fy, fz, nx, ny, nz, inv_eps);
+    } else {
+        RecF64 r;
+        r.x = x; r.y = y; r.z = z;
+        r.fx = fx; r.fy = fy; r.fz = fz;
+        r.nx = nx; r.ny = ny; r.nz = nz;
+        r.pad = 0.0;
+        reinterpret_cast<RecF64 *>(rec)[i] = r;
+    }
+}
+
+// ------------------------------------------------------------- rotations
+
+// Unit quaternion (w, x, y, z), w >= 0, of a proper rotation A (row-major),
+// by Shepperd's choice of the largest of 4w^2 = 1 + tr A, 4x^2 = 1 + A00 - A11
+// - A22, and so on, which keeps the division well conditioned at every angle.
+__device__ __forceinline__ void rot_to_quat(const double *A, double *q) {
+    const double tr = A[0] + A[4] + A[8];
+    double w, x, y, z;
+    if (tr >= A[0] && tr >= A[4] && tr >= A[8]) {
+        w = 0.5 * sqrt(1.0 + tr);
+        const double s = 0.25 / w;
+        x = (A[7] - A[5]) * s;
+        y = (A[2] - A[6]) * s;
+        z = (A[3] - A[1]) * s;
+    } else if (A[0] >= A[4] && A[0] >= A[8]) {
+        x = 0.5 * sqrt(fmax(1.0 + A[0] - A[4] - A[8], 0.0));
+        const double s = 0.25 / x;
+        w = (A[7] - A[5]) * s;
+        y = (A[1] + A[3]) * s;
+        z = (A[2] + A[6]) * s;
+    } else if (A[4] >= A[8]) {
+        y = 0.5 * sqrt(fmax(1.0 - A[0] + A[4] - A[8], 0.0));
+        const double s = 0.25 / y;
+        w = (A[2] - A[6]) * s;
+        x = (A[1] + A[3]) * s;
+        z = (A[5] + A[7]) * s;
+    } else {
+        z = 0.5 * sqrt(fmax(1.0 - A[0] - A[4] + A[8], 0.0));
+        const double s = 0.25 / z;
+        w = (A[3] - A[1]) * s;
+        x = (A[2] + A[6]) * s;
+        y = (A[5] + A[7]) * s;
+    }
+    if (w < 0.0) { w = -w; x = -x; y = -y; z = -z; }
+    q[0] = w; q[1] = x; q[2] = y; q[3] = z;
+}
+
+// Quaternion of the principal square root: rotation by half the angle about
+// the same axis, (1 + w, x, y, z) normalised.
+__device__ __forceinline__ void quat_half(const double *q, double *h) {
+    const double w = 1.0 + q[0];
+    const double inv = 1.0 / sqrt(w * w + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    h[0] = w * inv; h[1] = q[1] * inv; h[2] = q[2] * inv; h[3] = q[3] * inv;
+}
+
+// v <- q v q*, for a unit quaternion q = (w, u): t = 2 u x v, v' = v + w t + u x t.
+__device__ __forceinline__ void quat_rotate(const double *q, const double *v, double *o) {
+    const double tx = 2.0 * (q[2] * v[2] - q[3] * v[1]);
+    const double ty = 2.0 * (q[3] * v[0] - q[1] * v[2]);
+    const double tz = 2.0 * (q[1] * v[1] - q[2] * v[0]);
+    o[0] = v[0] + q[0] * tx + (q[2] * tz - q[3] * ty);
+    o[1] = v[1] + q[0] * ty + (q[3] * tx - q[1] * tz);
+    o[2] = v[2] + q[0] * tz + (q[1] * ty - q[2] * tx);
+}
+
+// Rotation quaternion of the rotation vector v (angle |v| about v/|v|).
+__device__ __forceinline__ void quat_from_rotvec(double vx, double vy, double vz, double *q) {
+    const double th = sqrt(vx * vx + vy * vy + vz * vz);
+    double s, c;
+    sincos(0.5 * th, &s, &c);
+    const double k = th > 0.0 ? s / th : 0.5;
+    q[0] = c; q[1] = k * vx; q[2] = k * vy; q[3] = k * vz;
+}
+
+__device__ __forceinline__ void quat_to_matrix(const double *q, double *S) {
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    S[0] = 1.0 - 2.0 * (y * y + z * z); S[1] = 2.0 * (x * y - w * z);       S[2] = 2.0 * (x * z + w * y);
+    S[3] = 2.0 * (x * y + w * z);       S[4] = 1.0 - 2.0 * (x * x + z * z); S[5] = 2.0 * (y * z - w * x);
+    S[6] = 2.0 * (x * z - w * y);       S[7] = 2.0 * (y * z + w * x);       S[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// Frame re-orthonormalisation: D3 <- D3/|D3|, D1 <- unit(D1 - (D1.D3) D3), D2 <- D3 x D1.
+__device__ __forceinline__ void reorthonormalize(double *d) {
+    double *d1 = d, *d2 = d + 3, *d3 = d + 6;
+    const double i3 = 1.0 / sqrt(d3[0] * d3[0] + d3[1] * d3[1] + d3[2] * d3[2]);
+    d3[0] *= i3; d3[1] *= i3; d3[2] *= i3;
+    const double p = d1[0] * d3[0] + d1[1] * d3[1] + d1[2] * d3[2];
+    d1[0] -= p * d3[0]; d1[1] -= p * d3[1]; d1[2] -= p * d3[2];
+    const double i1 = 1.0 / sqrt(d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2]);
+    d1[0] *= i1; d1[1] *= i1; d1[2] *= i1;
+    d2[0] = d3[1] * d1[2] - d3[2] * d1[1];
+    d2[1] = d3[2] * d1[0] - d3[0] * d1[2];
+    d2[2] = d3[0] * d1[1] - d3[1] * d1[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_rotsqrt(int64_t count, const double *__restrict__ R,
+                                                    double *__restrict__ S) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= count) return;
+    double A[9], q[4], h[4], o[9];
+    for (int k = 0; k < 9; k++) A[k] = R[9 * i + k];
+    rot_to_quat(A, q);
+    quat_half(q, h);
+    quat_to_matrix(h, o);
+    for (int k = 0; k < 9; k++) S[9 * i + k] = o[k];
+}
+
+// ------------------------------------------------------------ pack / rod
+
+__global__ __launch_bounds__(kBlock) void k_pack_aos(int prec, const EnsDesc *__restrict__ desc) {
+    const EnsDesc &E = desc[0];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= E.N) return;
+    const double *X = E.Xin_aos, *f = E.fext, *n = E.next;
+    store_rec(prec, E.rec, i, X[3 * i], X[3 * i + 1], X[3 * i + 2], f[3 * i], f[3 * i + 1],
+              f[3 * i + 2], n[3 * i], n[3 * i + 1], n[3 * i + 2], E.inv_eps);
+}
+
+// F and N of the segment between nodes ka and kb = ka + 1 (SoA state of N points).
+__device__ __forceinline__ void rod_segment(const EnsDesc &E, const double *__restrict__ X,
+                                            const double *__restrict__ D, int N, int ka, int kb,
+                                            double *F, double *Nv, double *dX) {
+    double Da[9], Db[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        Da[k] = D[(size_t)k * N + ka];
+        Db[k] = D[(size_t)k * N + kb];
+    }
+    // A = sum_j D^j_b (D^j_a)^T maps frame a onto frame b.
+    double A[9];
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+            A[3 * r + c] = Db[r] * Da[c] + Db[3 + r] * Da[3 + c] + Db[6 + r] * Da[6 + c];
+    double q[4], h[4], Dh[9];
+    rot_to_quat(A, q);
+    quat_half(q, h);
+#pragma unroll
+    for (int i = 0; i < 3; i++) quat_rotate(h, Da + 3 * i, Dh + 3 * i);
+#pragma unroll
+    for (int c = 0; c < 3; c++) dX[c] = X[(size_t)c * N + kb] - X[(size_t)c * N + ka];
+    const double ids = 1.0 / E.ds;
+    F[0] = F[1] = F[2] = 0.0;
+    Nv[0] = Nv[1] = Nv[2] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        const double str = (dX[0] * Dh[3 * j] + dX[1] * Dh[3 * j + 1] + dX[2] * Dh[3 * j + 2]) * ids -
+                           (j == 2 ? 1.0 : 0.0);
+        const double Fj = E.b[j] * str;
+        F[0] += Fj * Dh[3 * j]; F[1] += Fj * Dh[3 * j + 1]; F[2] += Fj * Dh[3 * j + 2];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        const int j = (i + 1) % 3, l = (i + 2) % 3;
+        const double kap = ((Db[3 * j] - Da[3 * j]) * Dh[3 * l] + (Db[3 * j + 1] - Da[3 * j + 1]) * Dh[3 * l + 1] +
+                            (Db[3 * j + 2] - Da[3 * j + 2]) * Dh[3 * l + 2]) * ids - E.om0[i];
+        const double Ni = E.a[i] * kap;
+        Nv[0] += Ni * Dh[3 * i]; Nv[1] += Ni * Dh[3 * i + 1]; Nv[2] += Ni * Dh[3 * i + 2];
+    }
+}
+
+// One block per filament; the filament is walked in chunks of kBlock - 1
+// nodes.  Thread t computes segment c0 - 1 + t into LDS, then node c0 + t
+// combines its two neighbouring segments.
+__global__ __launch_bounds__(kBlock) void k_rod_forces(int prec, int stage_state, int elastic,
+                                                       const EnsDesc *__restrict__ desc,
+                                                       const RodItem *__restrict__ items) {
+    __shared__ double sF[3][kBlock], sN[3][kBlock], sX[3][kBlock];
+    const RodItem it = items[blockIdx.x];
+    const EnsDesc &E = desc[it.ens];
+    const int N = E.N;
+    const double *__restrict__ X = stage_state ? E.Xs : E.X;
+    const double *__restrict__ D = stage_state ? E.Ds : E.D;
+    const int k0 = E.off[it.fil];
+    const int M = E.off[it.fil + 1] - k0;
+    const int tid = threadIdx.x;
+    for (int c0 = 0; c0 < M; c0 += kBlock - 1) {
+        if (elastic) {
+            const int s = c0 - 1 + tid;
+            double F[3] = {0.0, 0.0, 0.0}, Nv[3] = {0.0, 0.0, 0.0}, dX[3] = {0.0, 0.0, 0.0};
+            if (s >= 0 && s <= M - 2) rod_segment(E, X, D, N, k0 + s, k0 + s + 1, F, Nv, dX);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                sF[c][tid] = F[c];
+                sN[c][tid] = Nv[c];
+                sX[c][tid] = dX[c];
+            }
+            __syncthreads();
+        }
+        const int k = c0 + tid;
+        if (tid < kBlock - 1 && k < M) {
+            const int p = k0 + k;
+            double g[3], m[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                g[c] = E.fext ? E.fext[(size_t)c * N + p] : 0.0;
+                m[c] = E.next ? E.next[(size_t)c * N + p] : 0.0;
+            }
+            if (elastic) {
+                // segment k+1/2 sits at LDS slot tid + 1, segment k-1/2 at slot tid
+                const double Fp[3] = {sF[0][tid + 1], sF[1][tid + 1], sF[2][tid + 1]};
+                const double Fm[3] = {sF[0][tid], sF[1][tid], sF[2][tid]};
+                const double Xp[3] = {sX[0][tid + 1], sX[1][tid + 1], sX[2][tid + 1]};
+                const double Xm[3] = {sX[0][tid], sX[1][tid], sX[2][tid]};
+                const double cp[3] = {Xp[1] * Fp[2] - Xp[2] * Fp[1], Xp[2] * Fp[0] - Xp[0] * Fp[2],
+                                      Xp[0] * Fp[1] - Xp[1] * Fp[0]};
+                const double cm[3] = {Xm[1] * Fm[2] - Xm[2] * Fm[1], Xm[2] * Fm[0] - Xm[0] * Fm[2],
+                                      Xm[0] * Fm[1] - Xm[1] * Fm[0]};
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    g[c] += Fp[c] - Fm[c];
+                    m[c] += (sN[c][tid + 1] - sN[c][tid]) + 0.5 * (cp[c] + cm[c]);
+                }
+            }
+            store_rec(prec, E.rec, p, X[p], X[(size_t)N + p], X[(size_t)2 * N + p], g[0], g[1],
+                      g[2], m[0], m[1], m[2], E.inv_eps);
+            if (E.g_out) {
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    E.g_out[3 * (size_t)p + c] = g[c];
+                    E.m_out[3 * (size_t)p + c] = m[c];
+                }
+            }
+        }
+        if (elastic) __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------- pairs
+
+template <int T>
+__global__ __launch_bounds__(kBlock) void k_pairs_tile_f32(const EnsDesc *__restrict__ desc,
+                                                           const PairItem *__restrict__ items) {
+    __shared__ float4 sA[kSrcTile], sB[kSrcTile], sC[kSrcTile];
+    const PairItem it = items[blockIdx.x];
+    const EnsDesc &E = desc[it.ens];
+    const RecF32 *__restrict__ rec = reinterpret_cast<const RecF32 *>(E.rec);
+    const int tid = threadIdx.x;
+    float thx[T], thy[T], thz[T], tlx[T], tly[T], tlz[T];
+    float s[T][6], c[T][6];
+#pragma unroll
+    for (int t = 0; t < T; t++) {
+        const int li = min(tid + t * kBlock, it.ntgt - 1);
+        const RecF32 r = rec[it.tgt0 + li];
+        thx[t] = r.a.x; thy[t] = r.a.y; thz[t] = r.a.z;
+        tlx[t] = r.b.x; tly[t] = r.b.y; tlz[t] = r.b.z;
+#pragma unroll
+        for (int k = 0; k < 6; k++) { s[t][k] = 0.0f; c[t][k] = 0.0f; }
+    }
+    for (int base = 0; base < it.nsrc; base += kSrcTile) {
+        __syncthreads();
+        const int j = base + tid;
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, cc = a;
+        if (j < it.nsrc) {
+            const RecF32 r = rec[it.src0 + j];
+            a = r.a; b = r.b; cc = r.c;
+        }
+        sA[tid] = a; sB[tid] = b; sC[tid] = cc;
+        __syncthreads();
+        const int cnt = min(kSrcTile, it.nsrc - base);
+        for (int sb = 0; sb < cnt; sb += kKahanBlock) {
+            float p[T][6];
+#pragma unroll
+            for (int t = 0; t < T; t++)
+#pragma unroll
+                for (int k = 0; k < 6; k++) p[t][k] = 0.0f;
+#pragma unroll 2
+            for (int jj = sb; jj < sb + kKahanBlock; jj++) {
+                const float4 A = sA[jj], B = sB[jj], C = sC[jj];
+#pragma unroll
+                for (int t = 0; t < T; t++) pair_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], A, B, C, p[t]);
+            }
+#pragma unroll
+            for (int t = 0; t < T; t++)
+#pragma unroll
+                for (int k = 0; k < 6; k++) kahan_add(s[t][k], c[t][k], p[t][k]);
+        }
+    }
+    const int N = E.N;
+#pragma unroll
+    for (int t = 0; t < T; t++) {
+        const int li = tid + t * kBlock;
+        if (li < it.ntgt) {
+#pragma unroll
+            for (int k = 0; k < 6; k++)
+                E.part[((size_t)it.chunk * 6 + k) * N + it.tgt0 + li] = (double)s[t][k] - (double)c[t][k];
+        }
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(kBlock) void k_pairs_tile_f64(const EnsDesc *__restrict__ desc,
+                                                           const PairItem *__restrict__ items) {
+    __shared__ double2 s0[kSrcTile], s1[kSrcTile], s2[kSrcTile], s3[kSrcTile], s4[kSrcTile];
+    const PairItem it = items[blockIdx.x];
+    const EnsDesc &E = desc[it.ens];
+    const RecF64 *__restrict__ rec = reinterpret_cast<const RecF64 *>(E.rec);
+    const int tid = threadIdx.x;
+    const double e2 = E.eps * E.eps, c375e2 = 3.75 * e2;
+    double tx[T], ty[T], tz[T], acc[T][6];
+#pragma unroll
+    for (int t = 0; t < T; t++) {
+        const int li = min(tid + t * kBlock, it.ntgt - 1);
+        const RecF64 &r = rec[it.tgt0 + li];
+        tx[t] = r.x; ty[t] = r.y; tz[t] = r.z;
+#pragma unroll
+        for (int k = 0; k < 6; k++) acc[t][k] = 0.0;
+    }
+    const double2 *__restrict__ rw = reinterpret_cast<const double2 *>(rec);
+    for (int base = 0; base < it.nsrc; base += kSrcTile) {
+        __syncthreads();
+        const int j = base + tid;
+        double2 w0 = make_double2(0.0, 0.0), w1 = w0, w2 = w0, w3 = w0, w4 = w0;
+        if (j < it.nsrc) {
+            const double2 *src = rw + (size_t)(it.src0 + j) * 5;
+            w0 = src[0]; w1 = src[1]; w2 = src[2]; w3 = src[3]; w4 = src[4];
+        }
+        s0[tid] = w0; s1[tid] = w1; s2[tid] = w2; s3[tid] = w3; s4[tid] = w4;
+        __syncthreads();
+        const int cnt = min(kSrcTile, it.nsrc - base);
+#pragma unroll 2
+        for (int jj = 0; jj < cnt; jj++) {
+            const double2 a = s0[jj], b = s1[jj], cc = s2[jj], d = s3[jj], e = s4[jj];
+#pragma unroll
+            for (int t = 0; t < T; t++)
+                pair_f64(tx[t], ty[t], tz[t], a.x, a.y, b.x, b.y, cc.x, cc.y, d.x, d.y, e.x, e2, c375e2, acc[t]);
+        }
+    }
+    const int N = E.N;
+#pragma unroll
+    for (int t = 0; t < T; t++) {
+        const int li = tid + t * kBlock;
+        if (li < it.ntgt) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) E.part[((size_t)it.chunk * 6 + k) * N + it.tgt0 + li] = acc[t][k];
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Small-ensemble pair kernel: each wave owns kSplitTargetsPerWave targets and
+// its 64 lanes stride over the item's sources; per-lane sums are combined in
+// FP64 with a butterfly of wave shuffles in a fixed order.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restrict__ desc,
+                                                        const PairItem *__restrict__ items) {
+    constexpr int TW = kSplitTargetsPerWave;
+    const PairItem it = items[blockIdx.x];
+    const EnsDesc &E = desc[it.ens];
+    const int lane = threadIdx.x & 63;
+    const int tb = (threadIdx.x >> 6) * TW;
+    if (tb >= it.ntgt) return;  // whole wave idle (wave-uniform)
+    double out[TW][6];
+    if (PREC == 1) {
+        const RecF32 *__restrict__ rec = reinterpret_cast<const RecF32 *>(E.rec);
+        float thx[TW], thy[TW], thz[TW], tlx[TW], tly[TW], tlz[TW], s[TW][6], c[TW][6];
+#pragma unroll
+        for (int t = 0; t < TW; t++) {
+            const RecF32 r = rec[it.tgt0 + min(tb + t, it.ntgt - 1)];
+            thx[t] = r.a.x; thy[t] = r.a.y; thz[t] = r.a.z;
+            tlx[t] = r.b.x; tly[t] = r.b.y; tlz[t] = r.b.z;
+#pragma unroll
+            for (int k = 0; k < 6; k++) { s[t][k] = 0.f; c[t][k] = 0.f; }
+        }
+        constexpr int kPerLane = 16;  // sources per lane between compensated updates
+        for (int j0 = 0; j0 < it.nsrc; j0 += 64 * kPerLane) {
+            float p[TW][6];
+#pragma unroll
+            for (int t = 0; t < TW; t++)
+#pragma unroll
+                for (int k = 0; k < 6; k++) p[t][k] = 0.f;
+            const int jend = min(j0 + 64 * kPerLane, it.nsrc);
+            for (int j = j0 + lane; j < jend; j += 64) {
+                const RecF32 r = rec[it.src0 + j];
+#pragma unroll
+                for (int t = 0; t < TW; t++) pair_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a, r.b, r.c, p[t]);
+            }
+#pragma unroll
+            for (int t = 0; t < TW; t++)
+#pragma unroll
+                for (int k = 0; k < 6; k++) kahan_add(s[t][k], c[t][k], p[t][k]);
+        }
+#pragma unroll
+        for (int t = 0; t < TW; t++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) out[t][k] = wave_sum((double)s[t][k] - (double)c[t][k]);
+    } else {
+        const RecF64 *__restrict__ rec = reinterpret_cast<const RecF64 *>(E.rec);
+        const double e2 = E.eps * E.eps, c375e2 = 3.75 * e2;
+        double tx[TW], ty[TW], tz[TW], acc[TW][6];
+#pragma unroll
+        for (int t = 0; t < TW; t++) {
+            const RecF64 &r = rec[it.tgt0 + min(tb + t, it.ntgt - 1)];
+            tx[t] = r.x; ty[t] = r.y; tz[t] = r.z;
+#pragma unroll
+            for (int k = 0; k < 6; k++) acc[t][k] = 0.0;
+        }
+        for (int j = lane; j < it.nsrc; j += 64) {
+            const RecF64 &r = rec[it.src0 + j];
+            const double x = r.x, y = r.y, z = r.z, fx = r.fx, fy = r.fy, fz = r.fz, nx = r.nx,
+                         ny = r.ny, nz = r.nz;
+#pragma unroll
+            for (int t = 0; t < TW; t++) pair_f64(tx[t], ty[t], tz[t], x, y, z, fx, fy, fz, nx, ny, nz, e2, c375e2, acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < TW; t++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) out[t][k] = wave_sum(acc[t][k]);
+    }
+    if (lane < 6) {
+        const int N = E.N;
+#pragma unroll
+        for (int t = 0; t < TW; t++) {
+            if (tb + t < it.ntgt) {
+                double v = out[t][0];
+#pragma unroll
+                for (int k = 1; k < 6; k++) v = (lane == k) ? out[t][k] : v;
+                E.part[((size_t)it.chunk * 6 + lane) * N + it.tgt0 + tb + t] = v;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------- reduce + epilogue
+
+__constant__ double kRkWeight[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
+__constant__ double kRkNextNode[3] = {0.5, 0.5, 1.0};
+
+__device__ __forceinline__ void rotate_frame(const double *__restrict__ Din, double *__restrict__ Dout,
+                                             int N, int i, double vx, double vy, double vz,
+                                             bool reorth) {
+    double q[4], d[9];
+    quat_from_rotvec(vx, vy, vz, q);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const double v[3] = {Din[(size_t)(3 * k) * N + i], Din[(size_t)(3 * k + 1) * N + i],
+                             Din[(size_t)(3 * k + 2) * N + i]};
+        quat_rotate(q, v, d + 3 * k);
+    }
+    if (reorth) reorthonormalize(d);
+#pragma unroll
+    for (int k = 0; k < 9; k++) Dout[(size_t)k * N + i] = d[k];
+}
+
+template <int EPI>
+__global__ __launch_bounds__(kBlock) void k_reduce(int stage, double dt, const EnsDesc *__restrict__ desc,
+                                                   const PointItem *__restrict__ items) {
+    const PointItem it = items[blockIdx.x];
+    const EnsDesc &E = desc[it.ens];
+    const int N = E.N;
+    const int i = it.p0 + threadIdx.x;
+    if (i >= N) return;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double *__restrict__ part = E.part;
+    for (int k = 0; k < E.K; k++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[c] += part[((size_t)k * 6 + c) * N + i];
+    const double U[3] = {acc[0] * E.cU, acc[1] * E.cU, acc[2] * E.cU};
+    const double W[3] = {acc[3] * E.cW, acc[4] * E.cW, acc[5] * E.cW};
+    if (EPI == EPI_WRITE) {
+        if (E.aos_io) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) { E.U[3 * (size_t)i + c] = U[c]; E.W[3 * (size_t)i + c] = W[c]; }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; c++) { E.U[(size_t)c * N + i] = U[c]; E.W[(size_t)c * N + i] = W[c]; }
+        }
+        return;
+    }
+    if (EPI == EPI_EULER) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            E.U[(size_t)c * N + i] = U[c];
+            E.W[(size_t)c * N + i] = W[c];
+            E.X[(size_t)c * N + i] += dt * U[c];
+        }
+        rotate_frame(E.D, E.D, N, i, dt * W[0], dt * W[1], dt * W[2], true);
+        return;
+    }
+    // RK4: stage s in 0..3 evaluated at the stage state.
+    const double w = kRkWeight[stage];
+    double ua[3], wa[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if (stage == 0) {
+            E.U[(size_t)c * N + i] = U[c];
+            E.W[(size_t)c * N + i] = W[c];
+            ua[c] = w * U[c];
+            wa[c] = w * W[c];
+        } else {
+            ua[c] = E.Ua[(size_t)c * N + i] + w * U[c];
+            wa[c] = E.Wa[(size_t)c * N + i] + w * W[c];
+        }
+    }
+    if (EPI == EPI_RK4_STAGE) {
+        const double h = kRkNextNode[stage] * dt;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            E.Ua[(size_t)c * N + i] = ua[c];
+            E.Wa[(size_t)c * N + i] = wa[c];
+            E.Xs[(size_t)c * N + i] = E.X[(size_t)c * N + i] + h * U[c];
+        }
+        rotate_frame(E.D, E.Ds, N, i, h * W[0], h * W[1], h * W[2], false);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; c++) E.X[(size_t)c * N + i] += dt * ua[c];
+        rotate_frame(E.D, E.D, N, i, dt * wa[0], dt * wa[1], dt * wa[2], true);
+    }
+}
+
+// --------------------------------------------------------- launch wrappers
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_pack_aos(int prec, const EnsDesc *d_desc, const EnsDesc &h_desc, hipStream_t s) {
+    if (h_desc.N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_aos, dim3(blocks_for(h_desc.N)), dim3(kBlock), 0, s, prec, d_desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_rod_forces(int prec, int stage_state, int elastic, const EnsDesc *d_desc,
+                             const RodItem *d_items, int n_items, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rod_forces, dim3(n_items), dim3(kBlock), 0, s, prec, stage_state, elastic,
+                       d_desc, d_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, const PairItem *d_items,
+                        int n_items, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const dim3 g(n_items), b(kBlock);
+    if (mode == PAIR_SPLIT) {
+        if (prec == 1) hipLaunchKernelGGL(k_pairs_split<1>, g, b, 0, s, d_desc, d_items);
+        else hipLaunchKernelGGL(k_pairs_split<0>, g, b, 0, s, d_desc, d_items);
+    } else if (prec == 1) {
+        if (tpl == 2) hipLaunchKernelGGL(k_pairs_tile_f32<2>, g, b, 0, s, d_desc, d_items);
+        else hipLaunchKernelGGL(k_pairs_tile_f32<1>, g, b, 0, s, d_desc, d_items);
+    } else {
+        if (tpl == 2) hipLaunchKernelGGL(k_pairs_tile_f64<2>, g, b, 0, s, d_desc, d_items);
+        else hipLaunchKernelGGL(k_pairs_tile_f64<1>, g, b, 0, s, d_desc, d_items);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(int epi, int stage, double dt, const EnsDesc *d_desc,
+                         const PointItem *d_items, int n_items, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const dim3 g(n_items), b(kBlock);
+    switch (epi) {
+        case EPI_EULER: hipLaunchKernelGGL(k_reduce<EPI_EULER>, g, b, 0, s, stage, dt, d_desc, d_items); break;
+        case EPI_RK4_STAGE: hipLaunchKernelGGL(k_reduce<EPI_RK4_STAGE>, g, b, 0, s, stage, dt, d_desc, d_items); break;
+        case EPI_RK4_FINAL: hipLaunchKernelGGL(k_reduce<EPI_RK4_FINAL>, g, b, 0, s, stage, dt, d_desc, d_items); break;
+        default: hipLaunchKernelGGL(k_reduce<EPI_WRITE>, g, b, 0, s, stage, dt, d_desc, d_items); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rotsqrt(int64_t count, const double *R, double *S, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rotsqrt, dim3(blocks_for(count)), dim3(kBlock), 0, s, count, R, S);
+    return hipGetLastError();
+}
+
+}  // namespace mrs

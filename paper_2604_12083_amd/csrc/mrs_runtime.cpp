@@ -1,0 +1,872 @@
+// Host runtime and C ABI of the MRS filament library.
+#include "mrs_runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <tuple>
+
+using namespace mrs;
+
+namespace mrs {
+
+static constexpr double kPi = 3.14159265358979323846264338327950288;
+
+mrs_status fail(mrs_context *ctx, mrs_status st, const char *fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+Plan::~Plan() {
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+}
+
+static int ilog2_bucket(int64_t N) {
+    int b = 0;
+    while ((int64_t(1) << (b + 1)) <= N) b++;
+    return b;
+}
+
+// Default pair-kernel configuration for an ensemble of N points.  Small
+// ensembles use the wave-split kernel; larger ones the LDS-tiled kernel with
+// enough source chunks that the grid holds several blocks per compute unit.
+PairCfg choose_cfg(mrs_context *ctx, int64_t N, int prec) {
+    PairCfg c;
+    auto it = ctx->tune.find({prec, ilog2_bucket(std::max<int64_t>(N, 1))});
+    if (it != ctx->tune.end()) c = it->second;
+    else {
+        c.mode = N <= 1024 ? PAIR_SPLIT : PAIR_TILE;
+        c.tpl = (prec == MRS_FP32C) ? 2 : 1;
+        c.K = 0;
+    }
+    if (c.mode == PAIR_SPLIT) {
+        c.K = 1;
+        c.chunk = (int)N;
+        return c;
+    }
+    const int64_t tile = (int64_t)kBlock * c.tpl;
+    const int64_t tiles = (N + tile - 1) / tile;
+    int64_t K = c.K;
+    if (K <= 0) {
+        const int64_t want_blocks = (int64_t)ctx->n_cu * 8;
+        K = (want_blocks + tiles - 1) / tiles;
+    }
+    const int64_t maxK = std::max<int64_t>(1, (N + kKahanBlock - 1) / kKahanBlock);
+    K = std::min(std::max<int64_t>(K, 1), maxK);
+    int64_t chunk = (N + K - 1) / K;
+    chunk = ((chunk + kKahanBlock - 1) / kKahanBlock) * kKahanBlock;
+    c.chunk = (int)std::max<int64_t>(chunk, kKahanBlock);
+    c.K = (int)((N + c.chunk - 1) / c.chunk);
+    if (c.K < 1) c.K = 1;
+    return c;
+}
+
+static void add_items(Plan &P, int e, int64_t N, int n_fil, const PairCfg &c) {
+    if (c.mode == PAIR_SPLIT) {
+        for (int64_t t0 = 0; t0 < N; t0 += kSplitTargetsPerBlock)
+            P.split.push_back({e, (int)t0, (int)std::min<int64_t>(kSplitTargetsPerBlock, N - t0), 0, (int)N, 0});
+    } else {
+        const int64_t tile = (int64_t)kBlock * c.tpl;
+        auto &dst = c.tpl == 2 ? P.tile2 : P.tile1;
+        for (int64_t t0 = 0; t0 < N; t0 += tile)
+            for (int k = 0; k < c.K; k++) {
+                const int64_t s0 = (int64_t)k * c.chunk;
+                if (s0 >= N) break;
+                dst.push_back({e, (int)t0, (int)std::min<int64_t>(tile, N - t0), (int)s0,
+                               (int)std::min<int64_t>(c.chunk, N - s0), k});
+            }
+    }
+    for (int f = 0; f < n_fil; f++) P.rods.push_back({e, f});
+    for (int64_t p0 = 0; p0 < N; p0 += kBlock) P.pts.push_back({e, (int)p0});
+    P.pairs_per_eval += N * N;
+}
+
+template <class T>
+static hipError_t upload_vec(DevBuf &d, const std::vector<T> &v) {
+    if (v.empty()) return hipSuccess;
+    hipError_t e = d.reserve(v.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+static hipError_t finalize_plan(Plan &P) {
+    hipError_t e;
+    if ((e = upload_vec(P.d_desc, P.h_desc)) != hipSuccess) return e;
+    if ((e = upload_vec(P.d_split, P.split)) != hipSuccess) return e;
+    if ((e = upload_vec(P.d_tile1, P.tile1)) != hipSuccess) return e;
+    if ((e = upload_vec(P.d_tile2, P.tile2)) != hipSuccess) return e;
+    if ((e = upload_vec(P.d_rods, P.rods)) != hipSuccess) return e;
+    return upload_vec(P.d_pts, P.pts);
+}
+
+static EnsDesc ensemble_desc(mrs_ensemble *E, int prec, const PairCfg &c) {
+    EnsDesc d{};
+    d.N = (int32_t)E->N;
+    d.n_fil = E->n_fil;
+    d.K = c.K;
+    d.aos_io = 0;
+    d.off = E->off.as<int32_t>();
+    d.X = E->X.as<double>();
+    d.D = E->D.as<double>();
+    d.Xs = E->Xs.as<double>();
+    d.Ds = E->Ds.as<double>();
+    d.U = E->U.as<double>();
+    d.W = E->W.as<double>();
+    d.Ua = E->Ua.as<double>();
+    d.Wa = E->Wa.as<double>();
+    d.fext = E->has_ext ? E->fext.as<double>() : nullptr;
+    d.next = E->has_ext ? E->next.as<double>() : nullptr;
+    d.Xin_aos = nullptr;
+    d.rec = E->rec.p;
+    d.part = E->part.as<double>();
+    d.g_out = d.m_out = nullptr;
+    d.eps = E->eps;
+    d.inv_eps = 1.0 / E->eps;
+    d.mu = E->mu;
+    d.cU = 1.0 / (8.0 * kPi * E->mu);
+    d.cW = prec == MRS_FP32C ? 1.0 / (8.0 * kPi * E->mu * E->eps) : d.cU;
+    for (int i = 0; i < 3; i++) {
+        d.a[i] = E->rod.a[i];
+        d.b[i] = E->rod.b[i];
+        d.om0[i] = E->rod.omega0[i];
+    }
+    d.ds = E->rod.ds;
+    return d;
+}
+
+// Plan of one ensemble for one precision (built once, reused).
+static mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out) {
+    mrs_context *ctx = E->ctx;
+    if (!E->plan[prec]) {
+        auto P = std::make_unique<Plan>();
+        P->prec = prec;
+        P->n_ens = 1;
+        PairCfg c = choose_cfg(ctx, E->N, prec);
+        size_t need = (size_t)c.K * 6 * (size_t)E->N * sizeof(double);
+        if (E->part.reserve(need) != hipSuccess) return fail(ctx, MRS_ENOMEM, "partial buffer (%zu bytes)", need);
+        P->h_desc.push_back(ensemble_desc(E, prec, c));
+        add_items(*P, 0, E->N, E->n_fil, c);
+        hipError_t e = finalize_plan(*P);
+        if (e != hipSuccess) return fail(ctx, MRS_EDEVICE, "plan upload: %s", hipGetErrorString(e));
+        E->plan[prec] = std::move(P);
+    }
+    *out = E->plan[prec].get();
+    return MRS_OK;
+}
+
+static hipEvent_t take_event(mrs_context *ctx) {
+    hipEvent_t ev = nullptr;
+    if (!ctx->event_pool.empty()) {
+        ev = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+    } else if (hipEventCreate(&ev) != hipSuccess) {
+        ev = nullptr;
+    }
+    return ev;
+}
+
+template <class F>
+static hipError_t timed(mrs_context *ctx, const char *name, hipStream_t s, F &&launch) {
+    if (!ctx->prof_on) return launch();
+    hipEvent_t a = take_event(ctx), b = take_event(ctx);
+    if (a) (void)hipEventRecord(a, s);
+    hipError_t e = launch();
+    if (b) (void)hipEventRecord(b, s);
+    if (a && b) ctx->prof.push_back({name, a, b});
+    return e;
+}
+
+static const char *pair_name(int prec, int mode) {
+    if (mode == PAIR_SPLIT) return prec == MRS_FP32C ? "pairs_split_f32c" : "pairs_split_f64";
+    return prec == MRS_FP32C ? "pairs_tile_f32c" : "pairs_tile_f64";
+}
+
+static hipError_t run_pairs(mrs_context *ctx, Plan &P, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (!P.split.empty())
+        e = timed(ctx, pair_name(P.prec, PAIR_SPLIT), s, [&] {
+            return launch_pairs(P.prec, PAIR_SPLIT, 1, P.d_desc.as<EnsDesc>(), P.d_split.as<PairItem>(),
+                                (int)P.split.size(), s);
+        });
+    if (e == hipSuccess && !P.tile1.empty())
+        e = timed(ctx, pair_name(P.prec, PAIR_TILE), s, [&] {
+            return launch_pairs(P.prec, PAIR_TILE, 1, P.d_desc.as<EnsDesc>(), P.d_tile1.as<PairItem>(),
+                                (int)P.tile1.size(), s);
+        });
+    if (e == hipSuccess && !P.tile2.empty())
+        e = timed(ctx, pair_name(P.prec, PAIR_TILE), s, [&] {
+            return launch_pairs(P.prec, PAIR_TILE, 2, P.d_desc.as<EnsDesc>(), P.d_tile2.as<PairItem>(),
+                                (int)P.tile2.size(), s);
+        });
+    return e;
+}
+
+static const char *epi_name(int epi) {
+    switch (epi) {
+        case EPI_EULER: return "reduce_euler";
+        case EPI_RK4_STAGE: return "reduce_rk4_stage";
+        case EPI_RK4_FINAL: return "reduce_rk4_final";
+        default: return "reduce_write";
+    }
+}
+
+hipError_t run_stage(mrs_context *ctx, Plan &P, int stage_state, int elastic, int epi, int stage,
+                     double dt, hipStream_t s) {
+    hipError_t e = timed(ctx, "rod_forces", s, [&] {
+        return launch_rod_forces(P.prec, stage_state, elastic, P.d_desc.as<EnsDesc>(), P.d_rods.as<RodItem>(),
+                                 (int)P.rods.size(), s);
+    });
+    if (e != hipSuccess) return e;
+    if ((e = run_pairs(ctx, P, s)) != hipSuccess) return e;
+    return timed(ctx, epi_name(epi), s, [&] {
+        return launch_reduce(epi, stage, dt, P.d_desc.as<EnsDesc>(), P.d_pts.as<PointItem>(), (int)P.pts.size(), s);
+    });
+}
+
+// Queue nsteps steps of plan P on stream s (no synchronisation).
+static hipError_t queue_steps(mrs_context *ctx, Plan &P, int integ, double dt, int nsteps, int elastic,
+                              hipStream_t s) {
+    for (int step = 0; step < nsteps; step++) {
+        hipError_t e;
+        if (integ == MRS_EULER) {
+            if ((e = run_stage(ctx, P, 0, elastic, EPI_EULER, 0, dt, s)) != hipSuccess) return e;
+        } else {
+            for (int st = 0; st < 4; st++) {
+                e = run_stage(ctx, P, st > 0, elastic, st < 3 ? EPI_RK4_STAGE : EPI_RK4_FINAL, st, dt, s);
+                if (e != hipSuccess) return e;
+            }
+        }
+    }
+    return hipSuccess;
+}
+
+// Steps through cached HIP graphs of up to kGraphSteps steps each.
+static constexpr int kGraphSteps = 50;
+
+static hipError_t graph_steps(mrs_context *ctx, Plan &P, int integ, double dt, int nsteps, int elastic,
+                              hipStream_t s) {
+    uint64_t dtbits;
+    std::memcpy(&dtbits, &dt, sizeof dtbits);
+    int left = nsteps;
+    while (left > 0) {
+        const int n = std::min(left, kGraphSteps);
+        auto key = std::make_tuple(integ, dtbits, n, elastic);
+        auto it = P.graphs.find(key);
+        if (it == P.graphs.end()) {
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return e;
+            hipError_t eq = queue_steps(ctx, P, integ, dt, n, elastic, s);
+            e = hipStreamEndCapture(s, &g);
+            if (eq != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return eq;
+            }
+            if (e != hipSuccess) return e;
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return e;
+            it = P.graphs.emplace(key, ex).first;
+        }
+        hipError_t e = hipGraphLaunch(it->second, s);
+        if (e != hipSuccess) return e;
+        left -= n;
+    }
+    return hipSuccess;
+}
+
+hipError_t upload(mrs_context *ctx, void *dst, const void *src, size_t bytes, hipStream_t s) {
+    hipError_t e;
+    if (ctx->stage_pending) {
+        if ((e = hipEventSynchronize(ctx->stage_event)) != hipSuccess) return e;
+        ctx->stage_pending = false;
+    }
+    if (bytes > ctx->stage_bytes) {
+        if (ctx->stage_host) (void)hipHostFree(ctx->stage_host);
+        ctx->stage_host = nullptr;
+        ctx->stage_bytes = 0;
+        size_t nb = std::max<size_t>(bytes, 1 << 16);
+        if ((e = hipHostMalloc(&ctx->stage_host, nb, hipHostMallocDefault)) != hipSuccess) return e;
+        ctx->stage_bytes = nb;
+    }
+    std::memcpy(ctx->stage_host, src, bytes);
+    if ((e = hipMemcpyAsync(dst, ctx->stage_host, bytes, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ctx->stage_event, s)) != hipSuccess) return e;
+    ctx->stage_pending = true;
+    return hipSuccess;
+}
+
+size_t ensemble_bytes(int64_t N, int n_fil, bool has_ext, int K64, int K32) {
+    size_t per = (3 + 9 + 3 + 3 + 3 + 9 + 3 + 3) * sizeof(double) + sizeof(RecF64);
+    if (has_ext) per += 6 * sizeof(double);
+    per += (size_t)std::max(K64, K32) * 6 * sizeof(double);
+    return per * (size_t)N + (size_t)(n_fil + 1) * sizeof(int32_t);
+}
+
+}  // namespace mrs
+
+// ------------------------------------------------------------------ C ABI
+
+#define CHECK_CTX(ctx)                                   \
+    do {                                                 \
+        if (!(ctx)) return MRS_EINVAL;                   \
+    } while (0)
+
+#define HIPCHK(ctx, expr)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail((ctx), MRS_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+static hipStream_t pick_stream(mrs_context *ctx, void *stream) {
+    return stream ? reinterpret_cast<hipStream_t>(stream) : ctx->stream;
+}
+
+extern "C" {
+
+mrs_status mrs_context_create(int device, mrs_context **out) {
+    if (!out) return MRS_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return MRS_EDEVICE;
+    if (device < 0 || device >= ndev) return MRS_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return MRS_EDEVICE;
+    auto *ctx = new (std::nothrow) mrs_context();
+    if (!ctx) return MRS_ENOMEM;
+    ctx->device = device;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        ctx->n_cu = ncu;
+    if (hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->stage_event, hipEventDisableTiming) != hipSuccess) {
+        delete ctx;
+        return MRS_EDEVICE;
+    }
+    ctx->stream = ctx->own_stream;
+    *out = ctx;
+    return MRS_OK;
+}
+
+void mrs_context_destroy(mrs_context *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamSynchronize(ctx->own_stream);
+    auto ens = ctx->ensembles;
+    for (auto *e : ens) mrs_ensemble_destroy(e);
+    ctx->batch_plans.clear();
+    for (auto &r : ctx->prof) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    for (auto ev : ctx->event_pool) (void)hipEventDestroy(ev);
+    if (ctx->stage_host) (void)hipHostFree(ctx->stage_host);
+    if (ctx->stage_event) (void)hipEventDestroy(ctx->stage_event);
+    ctx->eval_rec.release();
+    ctx->eval_part.release();
+    ctx->eval_desc.release();
+    ctx->eval_items.release();
+    ctx->eval_rod.release();
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+    delete ctx;
+}
+
+const char *mrs_last_error(const mrs_context *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+mrs_status mrs_context_set_stream(mrs_context *ctx, void *stream) {
+    CHECK_CTX(ctx);
+    ctx->stream = stream ? reinterpret_cast<hipStream_t>(stream) : ctx->own_stream;
+    return MRS_OK;
+}
+
+mrs_status mrs_context_synchronize(mrs_context *ctx) {
+    CHECK_CTX(ctx);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MRS_OK;
+}
+
+// One-shot evaluation on caller device arrays (AoS n x 3).
+mrs_status mrs_eval_device(mrs_context *ctx, int64_t n, const double *dX, const double *df,
+                           const double *dt, double eps, double mu, mrs_precision prec, double *dU,
+                           double *dW, void *stream) {
+    CHECK_CTX(ctx);
+    if (n < 0 || n > INT32_MAX / 8) return fail(ctx, MRS_EINVAL, "n out of range (%lld)", (long long)n);
+    if (!finite_pos(eps) || !finite_pos(mu)) return fail(ctx, MRS_EINVAL, "eps and mu must be finite and > 0");
+    if (prec != MRS_FP64 && prec != MRS_FP32C) return fail(ctx, MRS_EINVAL, "unknown precision %d", (int)prec);
+    if (n == 0) return MRS_OK;
+    if (!dX || !df || !dt || !dU || !dW) return fail(ctx, MRS_EINVAL, "null array");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    hipStream_t s = pick_stream(ctx, stream);
+    const int p = (int)prec;
+    PairCfg c = choose_cfg(ctx, n, p);
+    HIPCHK(ctx, ctx->eval_rec.reserve((size_t)n * sizeof(RecF64)));
+    HIPCHK(ctx, ctx->eval_part.reserve((size_t)c.K * 6 * (size_t)n * sizeof(double)));
+    EnsDesc d{};
+    d.N = (int32_t)n;
+    d.K = c.K;
+    d.aos_io = 1;
+    d.Xin_aos = dX;
+    d.fext = df;
+    d.next = dt;
+    d.U = dU;
+    d.W = dW;
+    d.rec = ctx->eval_rec.p;
+    d.part = ctx->eval_part.as<double>();
+    d.eps = eps;
+    d.inv_eps = 1.0 / eps;
+    d.mu = mu;
+    d.cU = 1.0 / (8.0 * kPi * mu);
+    d.cW = p == MRS_FP32C ? 1.0 / (8.0 * kPi * mu * eps) : d.cU;
+    Plan P;
+    P.prec = p;
+    add_items(P, 0, n, 0, c);
+    // desc + items in one upload: [desc][split][tile1][tile2][pts]
+    std::vector<char> blob;
+    auto put = [&](const void *src, size_t bytes) {
+        size_t off = (blob.size() + 255) & ~size_t(255);
+        blob.resize(off + bytes);
+        if (bytes) std::memcpy(blob.data() + off, src, bytes);
+        return off;
+    };
+    size_t o_desc = put(&d, sizeof d);
+    size_t o_split = put(P.split.data(), P.split.size() * sizeof(PairItem));
+    size_t o_t1 = put(P.tile1.data(), P.tile1.size() * sizeof(PairItem));
+    size_t o_t2 = put(P.tile2.data(), P.tile2.size() * sizeof(PairItem));
+    size_t o_pts = put(P.pts.data(), P.pts.size() * sizeof(PointItem));
+    HIPCHK(ctx, ctx->eval_items.reserve(blob.size()));
+    HIPCHK(ctx, upload(ctx, ctx->eval_items.p, blob.data(), blob.size(), s));
+    char *base = ctx->eval_items.as<char>();
+    const EnsDesc *dd = reinterpret_cast<const EnsDesc *>(base + o_desc);
+    HIPCHK(ctx, timed(ctx, "pack_aos", s, [&] { return launch_pack_aos(p, dd, d, s); }));
+    if (!P.split.empty())
+        HIPCHK(ctx, timed(ctx, pair_name(p, PAIR_SPLIT), s, [&] {
+            return launch_pairs(p, PAIR_SPLIT, 1, dd, reinterpret_cast<const PairItem *>(base + o_split),
+                                (int)P.split.size(), s);
+        }));
+    if (!P.tile1.empty())
+        HIPCHK(ctx, timed(ctx, pair_name(p, PAIR_TILE), s, [&] {
+            return launch_pairs(p, PAIR_TILE, 1, dd, reinterpret_cast<const PairItem *>(base + o_t1),
+                                (int)P.tile1.size(), s);
+        }));
+    if (!P.tile2.empty())
+        HIPCHK(ctx, timed(ctx, pair_name(p, PAIR_TILE), s, [&] {
+            return launch_pairs(p, PAIR_TILE, 2, dd, reinterpret_cast<const PairItem *>(base + o_t2),
+                                (int)P.tile2.size(), s);
+        }));
+    HIPCHK(ctx, timed(ctx, "reduce_write", s, [&] {
+        return launch_reduce(EPI_WRITE, 0, 0.0, dd, reinterpret_cast<const PointItem *>(base + o_pts),
+                             (int)P.pts.size(), s);
+    }));
+    return MRS_OK;
+}
+
+mrs_status mrs_eval_host(mrs_context *ctx, int64_t n, const double *X, const double *f, const double *t,
+                         double eps, double mu, mrs_precision prec, double *U, double *W) {
+    CHECK_CTX(ctx);
+    if (n < 0) return fail(ctx, MRS_EINVAL, "n < 0");
+    if (n == 0) return MRS_OK;
+    if (!X || !f || !t || !U || !W) return fail(ctx, MRS_EINVAL, "null array");
+    for (int64_t i = 0; i < 3 * n; i++)
+        if (!std::isfinite(X[i]) || !std::isfinite(f[i]) || !std::isfinite(t[i]))
+            return fail(ctx, MRS_EINVAL, "non-finite input at %lld", (long long)i);
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    hipStream_t s = ctx->stream;
+    const size_t b = (size_t)n * 3 * sizeof(double);
+    DevBuf io;
+    HIPCHK(ctx, io.reserve(5 * b));
+    double *dX = io.as<double>(), *df = dX + 3 * n, *dn = df + 3 * n, *dU = dn + 3 * n, *dW = dU + 3 * n;
+    HIPCHK(ctx, hipMemcpyAsync(dX, X, b, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(df, f, b, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(dn, t, b, hipMemcpyHostToDevice, s));
+    mrs_status st = mrs_eval_device(ctx, n, dX, df, dn, eps, mu, prec, dU, dW, s);
+    if (st != MRS_OK) {
+        (void)hipStreamSynchronize(s);
+        return st;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(U, dU, b, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(W, dW, b, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    for (int64_t i = 0; i < 3 * n; i++)
+        if (!std::isfinite(U[i]) || !std::isfinite(W[i])) return fail(ctx, MRS_ENUMERIC, "non-finite result");
+    return MRS_OK;
+}
+
+static bool valid_offsets(int32_t n_fil, const int32_t *off) {
+    if (n_fil < 1 || !off || off[0] != 0) return false;
+    for (int32_t i = 0; i < n_fil; i++)
+        if (off[i + 1] <= off[i]) return false;
+    return true;
+}
+
+static bool valid_rod(const mrs_rod_params *r) {
+    if (!r || !finite_pos(r->ds)) return false;
+    for (int i = 0; i < 3; i++)
+        if (!std::isfinite(r->a[i]) || !std::isfinite(r->b[i]) || !std::isfinite(r->omega0[i])) return false;
+    return true;
+}
+
+mrs_status mrs_rod_forces_device(mrs_context *ctx, int32_t n_fil, const int32_t *offsets, const double *dX,
+                                 const double *dD, const mrs_rod_params *rod, const double *dfext,
+                                 const double *dnext, double *dg, double *dm, void *stream) {
+    CHECK_CTX(ctx);
+    if (!valid_offsets(n_fil, offsets)) return fail(ctx, MRS_EINVAL, "bad offsets");
+    if (!valid_rod(rod)) return fail(ctx, MRS_EINVAL, "bad rod parameters");
+    if (!dX || !dD || !dg || !dm) return fail(ctx, MRS_EINVAL, "null array");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    hipStream_t s = pick_stream(ctx, stream);
+    const int64_t n = offsets[n_fil];
+    // The rod kernel reads SoA state; stage the caller's AoS arrays as SoA
+    // through a temporary ensemble-shaped descriptor.
+    DevBuf soa, offb;
+    HIPCHK(ctx, soa.reserve((size_t)n * (3 + 9 + 6) * sizeof(double) + (size_t)n * sizeof(RecF64)));
+    HIPCHK(ctx, offb.reserve((size_t)(n_fil + 1) * sizeof(int32_t)));
+    double *Xs = soa.as<double>(), *Ds = Xs + 3 * n, *E6 = Ds + 9 * n;
+    void *rec = E6 + 6 * n;
+    // transpose on the host side of a device copy would need a kernel; use
+    // 2D strided copies instead: component c of AoS -> row c of SoA
+    for (int c = 0; c < 3; c++)
+        HIPCHK(ctx, hipMemcpy2DAsync(Xs + c * n, sizeof(double), dX + c, 3 * sizeof(double), sizeof(double), n,
+                                     hipMemcpyDeviceToDevice, s));
+    for (int c = 0; c < 9; c++)
+        HIPCHK(ctx, hipMemcpy2DAsync(Ds + c * n, sizeof(double), dD + c, 9 * sizeof(double), sizeof(double), n,
+                                     hipMemcpyDeviceToDevice, s));
+    const bool ext = dfext || dnext;
+    if (ext) {
+        HIPCHK(ctx, hipMemsetAsync(E6, 0, 6 * n * sizeof(double), s));
+        for (int c = 0; c < 3; c++) {
+            if (dfext)
+                HIPCHK(ctx, hipMemcpy2DAsync(E6 + c * n, sizeof(double), dfext + c, 3 * sizeof(double),
+                                             sizeof(double), n, hipMemcpyDeviceToDevice, s));
+            if (dnext)
+                HIPCHK(ctx, hipMemcpy2DAsync(E6 + (3 + c) * n, sizeof(double), dnext + c, 3 * sizeof(double),
+                                             sizeof(double), n, hipMemcpyDeviceToDevice, s));
+        }
+    }
+    HIPCHK(ctx, hipMemcpyAsync(offb.p, offsets, (size_t)(n_fil + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    EnsDesc d{};
+    d.N = (int32_t)n;
+    d.n_fil = n_fil;
+    d.K = 1;
+    d.off = offb.as<int32_t>();
+    d.X = Xs;
+    d.D = Ds;
+    d.fext = ext ? E6 : nullptr;
+    d.next = ext ? E6 + 3 * n : nullptr;
+    d.rec = rec;
+    d.g_out = dg;
+    d.m_out = dm;
+    d.eps = 1.0;
+    d.inv_eps = 1.0;
+    d.mu = 1.0;
+    for (int i = 0; i < 3; i++) {
+        d.a[i] = rod->a[i];
+        d.b[i] = rod->b[i];
+        d.om0[i] = rod->omega0[i];
+    }
+    d.ds = rod->ds;
+    std::vector<RodItem> items;
+    for (int f = 0; f < n_fil; f++) items.push_back({0, f});
+    const size_t items_off = (sizeof(EnsDesc) + 255) & ~size_t(255);
+    std::vector<char> blob(items_off + items.size() * sizeof(RodItem));
+    std::memcpy(blob.data(), &d, sizeof d);
+    std::memcpy(blob.data() + items_off, items.data(), items.size() * sizeof(RodItem));
+    HIPCHK(ctx, ctx->eval_rod.reserve(blob.size()));
+    HIPCHK(ctx, upload(ctx, ctx->eval_rod.p, blob.data(), blob.size(), s));
+    HIPCHK(ctx, timed(ctx, "rod_forces", s, [&] {
+        return launch_rod_forces(MRS_FP64, 0, 1, ctx->eval_rod.as<EnsDesc>(),
+                                 reinterpret_cast<const RodItem *>(ctx->eval_rod.as<char>() + items_off), n_fil, s);
+    }));
+    // temporaries are freed by DevBuf destructors: wait for the kernel first
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return MRS_OK;
+}
+
+mrs_status mrs_rotsqrt_device(mrs_context *ctx, int64_t count, const double *dR, double *dS, void *stream) {
+    CHECK_CTX(ctx);
+    if (count < 0) return fail(ctx, MRS_EINVAL, "count < 0");
+    if (count == 0) return MRS_OK;
+    if (!dR || !dS) return fail(ctx, MRS_EINVAL, "null array");
+    hipStream_t s = pick_stream(ctx, stream);
+    HIPCHK(ctx, timed(ctx, "rotsqrt", s, [&] { return launch_rotsqrt(count, dR, dS, s); }));
+    return MRS_OK;
+}
+
+// ---- ensembles
+
+static void aos_to_soa(const double *src, double *dst, int64_t n, int w) {
+    for (int64_t k = 0; k < n; k++)
+        for (int c = 0; c < w; c++) dst[(size_t)c * n + k] = src[(size_t)w * k + c];
+}
+
+static void soa_to_aos(const double *src, double *dst, int64_t n, int w) {
+    for (int64_t k = 0; k < n; k++)
+        for (int c = 0; c < w; c++) dst[(size_t)w * k + c] = src[(size_t)c * n + k];
+}
+
+static mrs_status put_soa(mrs_context *ctx, DevBuf &d, const double *src, int64_t n, int w) {
+    std::vector<double> tmp((size_t)n * w);
+    aos_to_soa(src, tmp.data(), n, w);
+    HIPCHK(ctx, hipMemcpy(d.p, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice));
+    return MRS_OK;
+}
+
+static bool all_finite(const double *p, size_t n) {
+    for (size_t i = 0; i < n; i++)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+mrs_status mrs_ensemble_create(mrs_context *ctx, int32_t n_fil, const int32_t *offsets, const double *X,
+                               const double *D, const double *f_ext, const double *n_ext, double eps, double mu,
+                               const mrs_rod_params *rod, mrs_ensemble **out) {
+    CHECK_CTX(ctx);
+    if (!out) return fail(ctx, MRS_EINVAL, "null out");
+    *out = nullptr;
+    if (!valid_offsets(n_fil, offsets)) return fail(ctx, MRS_EINVAL, "bad offsets");
+    if (!finite_pos(eps) || !finite_pos(mu)) return fail(ctx, MRS_EINVAL, "eps and mu must be finite and > 0");
+    if (!valid_rod(rod)) return fail(ctx, MRS_EINVAL, "bad rod parameters");
+    if (!X || !D) return fail(ctx, MRS_EINVAL, "null state");
+    const int64_t n = offsets[n_fil];
+    if (n > INT32_MAX / 16) return fail(ctx, MRS_EINVAL, "too many points");
+    if (!all_finite(X, 3 * n) || !all_finite(D, 9 * n) || (f_ext && !all_finite(f_ext, 3 * n)) ||
+        (n_ext && !all_finite(n_ext, 3 * n)))
+        return fail(ctx, MRS_EINVAL, "non-finite input");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto E = std::make_unique<mrs_ensemble>();
+    E->ctx = ctx;
+    E->n_fil = n_fil;
+    E->N = n;
+    E->offsets.assign(offsets, offsets + n_fil + 1);
+    E->eps = eps;
+    E->mu = mu;
+    E->rod = *rod;
+    E->has_ext = f_ext || n_ext;
+    const size_t v3 = (size_t)n * 3 * sizeof(double), v9 = 3 * v3;
+    bool ok = E->off.reserve((n_fil + 1) * sizeof(int32_t)) == hipSuccess && E->X.reserve(v3) == hipSuccess &&
+              E->D.reserve(v9) == hipSuccess && E->U.reserve(v3) == hipSuccess && E->W.reserve(v3) == hipSuccess &&
+              E->Xs.reserve(v3) == hipSuccess && E->Ds.reserve(v9) == hipSuccess &&
+              E->Ua.reserve(v3) == hipSuccess && E->Wa.reserve(v3) == hipSuccess &&
+              E->rec.reserve((size_t)n * sizeof(RecF64)) == hipSuccess;
+    if (ok && E->has_ext) ok = E->fext.reserve(v3) == hipSuccess && E->next.reserve(v3) == hipSuccess;
+    if (!ok) return fail(ctx, MRS_ENOMEM, "ensemble allocation (%lld points)", (long long)n);
+    HIPCHK(ctx, hipMemcpy(E->off.p, offsets, (n_fil + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    mrs_status st;
+    if ((st = put_soa(ctx, E->X, X, n, 3)) != MRS_OK) return st;
+    if ((st = put_soa(ctx, E->D, D, n, 9)) != MRS_OK) return st;
+    if (E->has_ext) {
+        std::vector<double> z((size_t)3 * n, 0.0);
+        if ((st = put_soa(ctx, E->fext, f_ext ? f_ext : z.data(), n, 3)) != MRS_OK) return st;
+        if ((st = put_soa(ctx, E->next, n_ext ? n_ext : z.data(), n, 3)) != MRS_OK) return st;
+    }
+    HIPCHK(ctx, hipMemset(E->U.p, 0, v3));
+    HIPCHK(ctx, hipMemset(E->W.p, 0, v3));
+    ctx->ensembles.push_back(E.get());
+    *out = E.release();
+    return MRS_OK;
+}
+
+mrs_status mrs_ensemble_set_state(mrs_ensemble *E, const double *X, const double *D) {
+    if (!E) return MRS_EINVAL;
+    mrs_context *ctx = E->ctx;
+    if ((X && !all_finite(X, 3 * E->N)) || (D && !all_finite(D, 9 * E->N)))
+        return fail(ctx, MRS_EINVAL, "non-finite state");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    mrs_status st;
+    if (X && (st = put_soa(ctx, E->X, X, E->N, 3)) != MRS_OK) return st;
+    if (D && (st = put_soa(ctx, E->D, D, E->N, 9)) != MRS_OK) return st;
+    return MRS_OK;
+}
+
+mrs_status mrs_ensemble_size(const mrs_ensemble *E, int64_t *n) {
+    if (!E || !n) return MRS_EINVAL;
+    *n = E->N;
+    return MRS_OK;
+}
+
+mrs_status mrs_ensemble_eval(mrs_ensemble *E, mrs_precision prec, int include_elastic) {
+    if (!E) return MRS_EINVAL;
+    mrs_context *ctx = E->ctx;
+    if (prec != MRS_FP64 && prec != MRS_FP32C) return fail(ctx, MRS_EINVAL, "unknown precision");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    Plan *P;
+    mrs_status st = ensemble_plan(E, (int)prec, &P);
+    if (st != MRS_OK) return st;
+    HIPCHK(ctx, run_stage(ctx, *P, 0, include_elastic ? 1 : 0, EPI_WRITE, 0, 0.0, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MRS_OK;
+}
+
+static mrs_status check_step_args(mrs_context *ctx, mrs_integrator integ, double dt, int32_t nsteps,
+                                  mrs_precision prec) {
+    if (integ != MRS_EULER && integ != MRS_RK4) return fail(ctx, MRS_EINVAL, "unknown integrator %d", (int)integ);
+    if (!std::isfinite(dt)) return fail(ctx, MRS_EINVAL, "dt must be finite");
+    if (nsteps < 0) return fail(ctx, MRS_EINVAL, "nsteps < 0");
+    if (prec != MRS_FP64 && prec != MRS_FP32C) return fail(ctx, MRS_EINVAL, "unknown precision");
+    return MRS_OK;
+}
+
+mrs_status mrs_ensemble_step(mrs_ensemble *E, mrs_integrator integ, double dt, int32_t nsteps,
+                             mrs_precision prec, int include_elastic) {
+    if (!E) return MRS_EINVAL;
+    mrs_context *ctx = E->ctx;
+    mrs_status st = check_step_args(ctx, integ, dt, nsteps, prec);
+    if (st != MRS_OK) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    Plan *P;
+    if ((st = ensemble_plan(E, (int)prec, &P)) != MRS_OK) return st;
+    HIPCHK(ctx, queue_steps(ctx, *P, (int)integ, dt, nsteps, include_elastic ? 1 : 0, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MRS_OK;
+}
+
+mrs_status mrs_ensemble_get(mrs_ensemble *E, double *X, double *D, double *U, double *W) {
+    if (!E) return MRS_EINVAL;
+    mrs_context *ctx = E->ctx;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const int64_t n = E->N;
+    std::vector<double> tmp((size_t)n * 9);
+    struct { double *dst; DevBuf *src; int w; } outs[4] = {{X, &E->X, 3}, {D, &E->D, 9}, {U, &E->U, 3}, {W, &E->W, 3}};
+    for (auto &o : outs) {
+        if (!o.dst) continue;
+        HIPCHK(ctx, hipMemcpy(tmp.data(), o.src->p, (size_t)n * o.w * sizeof(double), hipMemcpyDeviceToHost));
+        soa_to_aos(tmp.data(), o.dst, n, o.w);
+    }
+    return MRS_OK;
+}
+
+void mrs_ensemble_destroy(mrs_ensemble *E) {
+    if (!E) return;
+    mrs_context *ctx = E->ctx;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto it = ctx->batch_plans.begin(); it != ctx->batch_plans.end();) {
+        const auto &v = it->first.first;
+        if (std::find(v.begin(), v.end(), E) != v.end()) it = ctx->batch_plans.erase(it);
+        else ++it;
+    }
+    auto &L = ctx->ensembles;
+    L.erase(std::remove(L.begin(), L.end(), E), L.end());
+    delete E;
+}
+
+// ---- batching
+
+static mrs_status batch_plan(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *ens, int prec, Plan **out) {
+    std::vector<mrs_ensemble *> key(ens, ens + n_ens);
+    auto k = std::make_pair(key, prec);
+    auto it = ctx->batch_plans.find(k);
+    if (it == ctx->batch_plans.end()) {
+        auto P = std::make_unique<Plan>();
+        P->prec = prec;
+        P->n_ens = n_ens;
+        for (int e = 0; e < n_ens; e++) {
+            mrs_ensemble *E = ens[e];
+            // the single-ensemble plan owns the partial buffer size; reuse its config
+            Plan *single;
+            mrs_status st = ensemble_plan(E, prec, &single);
+            if (st != MRS_OK) return st;
+            PairCfg c = choose_cfg(ctx, E->N, prec);
+            P->h_desc.push_back(single->h_desc[0]);
+            add_items(*P, e, E->N, E->n_fil, c);
+        }
+        hipError_t e = finalize_plan(*P);
+        if (e != hipSuccess) return fail(ctx, MRS_EDEVICE, "batch plan upload: %s", hipGetErrorString(e));
+        it = ctx->batch_plans.emplace(k, std::move(P)).first;
+    }
+    *out = it->second.get();
+    return MRS_OK;
+}
+
+static mrs_status check_batch(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *ens) {
+    if (n_ens < 1 || !ens) return fail(ctx, MRS_EINVAL, "empty batch");
+    for (int i = 0; i < n_ens; i++) {
+        if (!ens[i] || ens[i]->ctx != ctx) return fail(ctx, MRS_EINVAL, "ensemble %d not of this context", i);
+        for (int j = 0; j < i; j++)
+            if (ens[j] == ens[i]) return fail(ctx, MRS_EINVAL, "ensemble listed twice");
+    }
+    return MRS_OK;
+}
+
+mrs_status mrs_batch_step(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *ens, mrs_integrator integ,
+                          double dt, int32_t nsteps, mrs_precision prec, int include_elastic, int use_graph) {
+    CHECK_CTX(ctx);
+    mrs_status st = check_batch(ctx, n_ens, ens);
+    if (st != MRS_OK) return st;
+    if ((st = check_step_args(ctx, integ, dt, nsteps, prec)) != MRS_OK) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    Plan *P;
+    if ((st = batch_plan(ctx, n_ens, ens, (int)prec, &P)) != MRS_OK) return st;
+    const int el = include_elastic ? 1 : 0;
+    if (use_graph && !ctx->prof_on)
+        HIPCHK(ctx, graph_steps(ctx, *P, (int)integ, dt, nsteps, el, ctx->stream));
+    else
+        HIPCHK(ctx, queue_steps(ctx, *P, (int)integ, dt, nsteps, el, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MRS_OK;
+}
+
+mrs_status mrs_batch_eval(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *ens, mrs_precision prec,
+                          int include_elastic) {
+    CHECK_CTX(ctx);
+    mrs_status st = check_batch(ctx, n_ens, ens);
+    if (st != MRS_OK) return st;
+    if (prec != MRS_FP64 && prec != MRS_FP32C) return fail(ctx, MRS_EINVAL, "unknown precision");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    Plan *P;
+    if ((st = batch_plan(ctx, n_ens, ens, (int)prec, &P)) != MRS_OK) return st;
+    HIPCHK(ctx, run_stage(ctx, *P, 0, include_elastic ? 1 : 0, EPI_WRITE, 0, 0.0, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MRS_OK;
+}
+
+// ---- profiling
+
+mrs_status mrs_profile_enable(mrs_context *ctx, int on) {
+    CHECK_CTX(ctx);
+    ctx->prof_on = on != 0;
+    return MRS_OK;
+}
+
+mrs_status mrs_profile_reset(mrs_context *ctx) {
+    CHECK_CTX(ctx);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &r : ctx->prof) {
+        ctx->event_pool.push_back(r.start);
+        ctx->event_pool.push_back(r.stop);
+    }
+    ctx->prof.clear();
+    return MRS_OK;
+}
+
+mrs_status mrs_profile_query(mrs_context *ctx, const char *kernel, int64_t *launches, double *total_ms) {
+    CHECK_CTX(ctx);
+    if (!launches || !total_ms) return fail(ctx, MRS_EINVAL, "null output");
+    int64_t n = 0;
+    double ms = 0.0;
+    for (auto &r : ctx->prof) {
+        if (kernel && *kernel && r.name.find(kernel) == std::string::npos) continue;
+        HIPCHK(ctx, hipEventSynchronize(r.stop));
+        float t = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&t, r.start, r.stop));
+        ms += t;
+        n++;
+    }
+    *launches = n;
+    *total_ms = ms;
+    return MRS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Host runtime objects behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mrs.h"
+#include "mrs_internal.h"
+
+namespace mrs {
+
+// Device allocation owned by the runtime.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // Grow-only: keeps the allocation when it is already large enough.
+    hipError_t reserve(size_t n) {
+        if (n <= bytes) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) { p = nullptr; return e; }
+        bytes = n;
+        return hipSuccess;
+    }
+    template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// How the pair kernel covers one ensemble.
+struct PairCfg {
+    int mode = PAIR_TILE;  // PAIR_TILE or PAIR_SPLIT
+    int tpl = 1;           // targets per lane (tile mode)
+    int K = 1;             // source chunks
+    int chunk = 0;         // sources per chunk
+};
+
+// Work lists of one launch sequence over a set of ensembles.
+struct Plan {
+    int prec = 0;
+    int n_ens = 0;
+    std::vector<EnsDesc> h_desc;
+    std::vector<PairItem> split, tile1, tile2;
+    std::vector<RodItem> rods;
+    std::vector<PointItem> pts;
+    DevBuf d_desc, d_split, d_tile1, d_tile2, d_rods, d_pts;
+    // cached graphs: key = (integrator, dt bits, steps, elastic)
+    std::map<std::tuple<int, uint64_t, int, int>, hipGraphExec_t> graphs;
+    int64_t pairs_per_eval = 0;
+    ~Plan();
+};
+
+struct ProfRec {
+    std::string name;
+    hipEvent_t start, stop;
+};
+
+}  // namespace mrs
+
+struct mrs_context {
+    int device = 0;
+    int n_cu = 256;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // scratch of the one-shot evaluation
+    mrs::DevBuf eval_rec, eval_part, eval_desc, eval_items, eval_rod;
+    // pinned staging for small uploads, reused after its event completes
+    void *stage_host = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t stage_event = nullptr;
+    bool stage_pending = false;
+    // profiling
+    bool prof_on = false;
+    std::vector<mrs::ProfRec> prof;
+    std::vector<hipEvent_t> event_pool;
+    // tuning table: (prec, log2 bucket of N) -> config
+    std::map<std::pair<int, int>, mrs::PairCfg> tune;
+    // batch plans
+    std::map<std::pair<std::vector<mrs_ensemble *>, int>, std::unique_ptr<mrs::Plan>> batch_plans;
+    std::vector<mrs_ensemble *> ensembles;
+    std::recursive_mutex mu;
+};
+
+struct mrs_ensemble {
+    mrs_context *ctx = nullptr;
+    int32_t n_fil = 0;
+    int64_t N = 0;
+    std::vector<int32_t> offsets;
+    double eps = 0, mu = 0;
+    mrs_rod_params rod{};
+    bool has_ext = false;
+    mrs::DevBuf off, X, D, U, W, Xs, Ds, Ua, Wa, fext, next, rec, part;
+    std::unique_ptr<mrs::Plan> plan[2];  // per precision
+};
+
+namespace mrs {
+
+// Error helpers
+mrs_status fail(mrs_context *ctx, mrs_status st, const char *fmt, ...);
+PairCfg choose_cfg(mrs_context *ctx, int64_t N, int prec);
+size_t ensemble_bytes(int64_t N, int n_fil, bool has_ext, int K64, int K32);
+hipError_t run_stage(mrs_context *ctx, Plan &P, int stage_state, int elastic, int epi, int stage,
+                     double dt, hipStream_t s);
+hipError_t upload(mrs_context *ctx, void *dst, const void *src, size_t bytes, hipStream_t s);
+
+}  // namespace mrs

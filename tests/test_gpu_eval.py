@@ -1,0 +1,129 @@
+"""GPU parity of the one-shot MRS evaluation against the FP64 oracle.
+
+Error metric: the paper's relative error form (Eq. true_err),
+max_i |a_i - b_i|_2 / |b_i|_2, separately for U and Omega.  Tolerances:
+1e-12 for MRS_FP64 and 1e-5 for MRS_FP32C.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import eval_dev, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def mrs():
+    import paper_2604_12083_amd as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mrs):
+    c = mrs.mrs_context_create(0)
+    yield c
+    mrs.mrs_context_destroy(c)
+
+
+def _cloud(N, seed, box=1.0):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0, box, (N, 3)), rng.normal(size=(N, 3)), rng.normal(size=(N, 3))
+
+
+def _check(mrs, ctx, X, f, n, eps, mu, prec, tag, oracle_UW=None):
+    say(f"eval {tag} N={len(X)} prec={prec}")
+    U, W = eval_dev(mrs, ctx, X, f, n, eps, mu, prec)
+    Uo, Wo = oracle_UW if oracle_UW is not None else oracle.mrs_eval(X, f, n, eps, mu)
+    eu, ew = oracle.rel_err(U, Uo), oracle.rel_err(W, Wo)
+    say(f"  rel err U {eu:.3e} W {ew:.3e}")
+    assert eu <= TOL[prec] and ew <= TOL[prec], (tag, prec, eu, ew)
+    return eu, ew
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_config1_eval(mrs, ctx, prec):
+    e = synth.config1()
+    _check(mrs, ctx, e.X, e.f, e.n, e.eps, e.mu, prec, "config1")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("N", [1, 2, 3, 17, 64, 255, 1000, 1024, 1025, 2049, 3000])
+def test_sizes_and_ragged_tails(mrs, ctx, prec, N):
+    X, f, n = _cloud(N, N, box=0.5)
+    _check(mrs, ctx, X, f, n, 0.02, 1.3, prec, f"cloud{N}")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_config2_full(mrs, ctx, prec):
+    e = synth.config2()
+    _check(mrs, ctx, e.X, e.f, e.n, e.eps, e.mu, prec, "config2")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_translation_far_from_origin(mrs, ctx, prec):
+    """Large coordinates exercise the hi/lo position split of the FP32C path."""
+    e = synth.filaments(8, 64, 2.0, 123)
+    Xs = e.X + np.array([1000.25, -750.5, 333.0])
+    _check(mrs, ctx, Xs, e.f, e.n, e.eps, e.mu, prec, "shifted")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("eps", [1e-4, 10.0])
+def test_eps_extremes(mrs, ctx, prec, eps):
+    X, f, n = _cloud(500, 9, box=1.0)
+    _check(mrs, ctx, X, f, n, eps, 1.0, prec, f"eps{eps}")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_linearity_and_zero_loads(mrs, ctx, prec):
+    X, f, n = _cloud(700, 3)
+    U, W = eval_dev(mrs, ctx, X, np.zeros_like(f), np.zeros_like(n), 0.05, 1.0, prec)
+    assert np.all(U == 0) and np.all(W == 0)
+
+
+def test_host_entry_matches_device(mrs, ctx):
+    X, f, n = _cloud(333, 4)
+    U, W = mrs.mrs_eval_host(ctx, X, f, n, 0.03, 0.7, mrs.MRS_FP64)
+    Ud, Wd = eval_dev(mrs, ctx, X, f, n, 0.03, 0.7, mrs.MRS_FP64)
+    np.testing.assert_array_equal(U, Ud)
+    np.testing.assert_array_equal(W, Wd)
+    Uo, Wo = oracle.mrs_eval(X, f, n, 0.03, 0.7)
+    assert oracle.rel_err(U, Uo) <= 1e-12
+
+
+def test_invalid_arguments(mrs, ctx):
+    X, f, n = _cloud(10, 5)
+    with pytest.raises(mrs.MrsError) as ei:
+        mrs.mrs_eval_host(ctx, X, f, n, -1.0, 1.0, mrs.MRS_FP64)
+    assert ei.value.status == mrs.MRS_EINVAL
+    with pytest.raises(mrs.MrsError):
+        mrs.mrs_eval_host(ctx, X, f, n, 0.1, 0.0, mrs.MRS_FP64)
+    with pytest.raises(mrs.MrsError):
+        mrs.mrs_eval_host(ctx, X, f, n, 0.1, 1.0, 7)
+    Xb = X.copy()
+    Xb[3, 1] = np.nan
+    with pytest.raises(mrs.MrsError):
+        mrs.mrs_eval_host(ctx, Xb, f, n, 0.1, 1.0, mrs.MRS_FP64)
+    # empty input is a no-op
+    U, W = mrs.mrs_eval_host(ctx, np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 3)), 0.1, 1.0, mrs.MRS_FP64)
+    assert U.shape == (0, 3)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_config5_full_size_sampled(mrs, ctx, prec):
+    """256,000 points, all targets evaluated on the GPU, 2,048 seeded targets
+    checked one by one against the oracle."""
+    e = synth.config5()
+    sub = synth.config5_subset(e.N)
+    say(f"config5 N={e.N} prec={prec}")
+    U, W = eval_dev(mrs, ctx, e.X, e.f, e.n, e.eps, e.mu, prec)
+    Uo, Wo = oracle.mrs_field(e.X[sub], e.X, e.f, e.n, e.eps, e.mu)
+    eu, ew = oracle.rel_err(U[sub], Uo), oracle.rel_err(W[sub], Wo)
+    say(f"  rel err (2048 sampled targets) U {eu:.3e} W {ew:.3e}")
+    assert eu <= TOL[prec] and ew <= TOL[prec]
+    assert np.all(np.isfinite(U)) and np.all(np.isfinite(W))
