@@ -175,6 +175,72 @@ mrs_status mrs_batch_step(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *
 mrs_status mrs_batch_eval(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *ens,
                           mrs_precision prec, int include_elastic);
 
+/* ---- serving (continuous batching) ------------------------------------ */
+
+/* One request: an independent filament ensemble and what to do with it.
+ * kind MRS_REQ_EVAL: one U, Omega evaluation; MRS_REQ_STEPS: nsteps steps of
+ * size dt with integrator `integ`.  Host arrays as in mrs_ensemble_create;
+ * they are copied by mrs_server_submit. */
+typedef enum { MRS_REQ_EVAL = 0, MRS_REQ_STEPS = 1 } mrs_request_kind;
+
+typedef struct {
+    int32_t kind;
+    int32_t n_fil;
+    const int32_t *offsets;
+    const double *X, *D, *f_ext, *n_ext;
+    double eps, mu, dt;
+    int32_t nsteps;
+    int32_t integ;
+    int32_t include_elastic;
+    mrs_rod_params rod;
+} mrs_request;
+
+/* Completion record.  Times are seconds on the steady (monotonic) clock:
+ * submission, admission to the device, and completion of the last step. */
+typedef struct {
+    int32_t status;
+    int32_t kind;
+    int64_t n;
+    int32_t steps_done;
+    double t_submit, t_admit, t_done;
+} mrs_result_info;
+
+typedef struct {
+    int64_t submitted, admitted, completed, rejected;
+    int64_t ticks, failed_ticks;
+    int64_t pairs;        /* pair interactions evaluated */
+    double busy_s;        /* device time spent in ticks */
+    int32_t active, queued;
+    int64_t hbm_in_use, hbm_budget;
+} mrs_server_stats;
+
+/* Start a server thread that owns ctx until mrs_server_stop.  Every tick it
+ * admits queued requests (arrival order, first fit) while a slot is free and
+ * their device footprint fits in hbm_budget_bytes, launches ONE batched
+ * sequence that advances every admitted request by one evaluation or one
+ * step, and retires finished requests.  All requests of a server use `prec`.
+ * Each request's result equals the one it gets alone (its work is split
+ * the same way in every batch).  A request larger than the whole budget
+ * completes with status MRS_ENOMEM without running.  If the environment variable
+ * MRS_DEBUG_FAIL_TICK=k is set, tick k is treated as failed before launch
+ * and its requests are retried from their step-boundary state. */
+mrs_status mrs_server_start(mrs_context *ctx, mrs_precision prec, int64_t hbm_budget_bytes,
+                            int32_t max_slots, mrs_server **out);
+/* Any host thread.  *ticket identifies the request. */
+mrs_status mrs_server_submit(mrs_server *srv, const mrs_request *req, uint64_t *ticket);
+/* Non-blocking.  MRS_ENOTREADY until the request is done; then fills info,
+ * copies X, D (state after the last step), U, Omega (last first-stage
+ * velocities) to the caller's n x 3 / n x 9 arrays (any may be NULL) and
+ * forgets the request. */
+mrs_status mrs_server_poll(mrs_server *srv, uint64_t ticket, mrs_result_info *info, double *X,
+                           double *D, double *U, double *Omega);
+/* Like poll, but waits up to timeout_s seconds. */
+mrs_status mrs_server_wait(mrs_server *srv, uint64_t ticket, double timeout_s,
+                           mrs_result_info *info, double *X, double *D, double *U, double *Omega);
+mrs_status mrs_server_stats_get(mrs_server *srv, mrs_server_stats *out);
+/* Finish admitted work, drop queued requests, join the thread, free srv. */
+mrs_status mrs_server_stop(mrs_server *srv);
+
 /* ---- kernel timing ---------------------------------------------------- */
 
 /* When enabled, every kernel launch of the context is bracketed by HIP events

@@ -44,6 +44,30 @@ class mrs_rod_params(ctypes.Structure):
                 ("ds", ctypes.c_double)]
 
 
+class mrs_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_fil", ctypes.c_int32), ("offsets", ctypes.c_void_p),
+                ("X", ctypes.c_void_p), ("D", ctypes.c_void_p), ("f_ext", ctypes.c_void_p),
+                ("n_ext", ctypes.c_void_p), ("eps", ctypes.c_double), ("mu", ctypes.c_double),
+                ("dt", ctypes.c_double), ("nsteps", ctypes.c_int32), ("integ", ctypes.c_int32),
+                ("include_elastic", ctypes.c_int32), ("rod", mrs_rod_params)]
+
+
+class mrs_result_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("kind", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("steps_done", ctypes.c_int32), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class mrs_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("ticks", ctypes.c_int64), ("failed_ticks", ctypes.c_int64),
+                ("pairs", ctypes.c_int64), ("busy_s", ctypes.c_double), ("active", ctypes.c_int32),
+                ("queued", ctypes.c_int32), ("hbm_in_use", ctypes.c_int64), ("hbm_budget", ctypes.c_int64)]
+
+
+MRS_REQ_EVAL, MRS_REQ_STEPS = 0, 1
+
+
 class MrsError(RuntimeError):
     def __init__(self, status, msg=""):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -78,6 +102,12 @@ _SIGS = {
     "mrs_ensemble_destroy": (None, [_vp]),
     "mrs_batch_step": (_int, [_vp, ctypes.c_int32, _vp, _int, _dbl, ctypes.c_int32, _int, _int, _int]),
     "mrs_batch_eval": (_int, [_vp, ctypes.c_int32, _vp, _int, _int]),
+    "mrs_server_start": (_int, [_vp, _int, _i64, ctypes.c_int32, ctypes.POINTER(_vp)]),
+    "mrs_server_submit": (_int, [_vp, ctypes.POINTER(mrs_request), ctypes.POINTER(ctypes.c_uint64)]),
+    "mrs_server_poll": (_int, [_vp, ctypes.c_uint64, ctypes.POINTER(mrs_result_info), _vp, _vp, _vp, _vp]),
+    "mrs_server_wait": (_int, [_vp, ctypes.c_uint64, _dbl, ctypes.POINTER(mrs_result_info), _vp, _vp, _vp, _vp]),
+    "mrs_server_stats_get": (_int, [_vp, ctypes.POINTER(mrs_server_stats)]),
+    "mrs_server_stop": (_int, [_vp]),
     "mrs_profile_enable": (_int, [_vp, _int]),
     "mrs_profile_reset": (_int, [_vp]),
     "mrs_profile_query": (_int, [_vp, ctypes.c_char_p, ctypes.POINTER(_i64), ctypes.POINTER(_dbl)]),
@@ -266,3 +296,56 @@ def mrs_profile_query(ctx, kernel=""):
     ms = _dbl()
     _check(_lib.mrs_profile_query(ctx, kernel.encode() if kernel else None, ctypes.byref(n), ctypes.byref(ms)), ctx)
     return int(n.value), float(ms.value)
+
+
+# ---- serving ------------------------------------------------------------
+
+
+def mrs_server_start(ctx, prec=MRS_FP32C, hbm_budget_bytes=8 << 30, max_slots=64):
+    h = _vp()
+    _check(_lib.mrs_server_start(ctx, int(prec), int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)), ctx)
+    return h
+
+
+def mrs_server_submit(srv, kind, offsets, X, D, f_ext, n_ext, eps, mu, rod, dt=0.0, nsteps=0, integ=MRS_RK4,
+                      include_elastic=True):
+    """Submit one request (inputs are copied); returns its ticket."""
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    X, D = _f64(X, 3), _f64(D, 9)
+    fe = None if f_ext is None else _f64(f_ext, 3)
+    ne = None if n_ext is None else _f64(n_ext, 3)
+    q = mrs_request(int(kind), len(off) - 1, _ptr(off), _ptr(X), _ptr(D), _ptr(fe), _ptr(ne), float(eps),
+                    float(mu), float(dt), int(nsteps), int(integ), int(bool(include_elastic)), rod)
+    t = ctypes.c_uint64()
+    _check(_lib.mrs_server_submit(srv, ctypes.byref(q), ctypes.byref(t)))
+    return int(t.value)
+
+
+def _server_out(n):
+    return np.empty((n, 3)), np.empty((n, 9)), np.empty((n, 3)), np.empty((n, 3))
+
+
+def mrs_server_poll(srv, ticket, n):
+    """(status, info, (X, D, U, Omega)); outputs are None unless done with MRS_OK."""
+    info = mrs_result_info()
+    X, D, U, W = _server_out(n)
+    st = _lib.mrs_server_poll(srv, ctypes.c_uint64(ticket), ctypes.byref(info), _ptr(X), _ptr(D), _ptr(U), _ptr(W))
+    return st, info, ((X, D, U, W) if st == MRS_OK else None)
+
+
+def mrs_server_wait(srv, ticket, n, timeout_s=60.0):
+    info = mrs_result_info()
+    X, D, U, W = _server_out(n)
+    st = _lib.mrs_server_wait(srv, ctypes.c_uint64(ticket), float(timeout_s), ctypes.byref(info), _ptr(X), _ptr(D),
+                              _ptr(U), _ptr(W))
+    return st, info, ((X, D, U, W) if st == MRS_OK else None)
+
+
+def mrs_server_stats_get(srv):
+    s = mrs_server_stats()
+    _check(_lib.mrs_server_stats_get(srv, ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in mrs_server_stats._fields_}
+
+
+def mrs_server_stop(srv) -> None:
+    _check(_lib.mrs_server_stop(srv))

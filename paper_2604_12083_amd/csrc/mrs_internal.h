@@ -50,6 +50,9 @@ struct EnsDesc {
     double eps, inv_eps, mu;
     double cU, cW;     // 1/(8 pi mu) and the Omega scale of the record form
     double a[3], b[3], om0[3], ds;
+    double dt;         // step size used when a launch passes dt = NaN
+    int32_t elastic;   // rod forces on/off used when a launch passes elastic < 0
+    int32_t pad_;
 };
 
 // One block of a pair kernel: targets [tgt0, tgt0 + ntgt) against sources
@@ -78,10 +81,12 @@ enum Epilogue : int {
 // Launch wrappers (mrs_kernels.hip).  All return the launch's hipError_t.
 hipError_t launch_pack_aos(int prec, const EnsDesc *d_desc, const EnsDesc &h_desc,
                            hipStream_t s);
+// elastic < 0: every ensemble uses its own EnsDesc::elastic.
 hipError_t launch_rod_forces(int prec, int stage_state, int elastic, const EnsDesc *d_desc,
                              const RodItem *d_items, int n_items, hipStream_t s);
 hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, const PairItem *d_items,
                         int n_items, hipStream_t s);
+// dt = NaN: every ensemble uses its own EnsDesc::dt.
 hipError_t launch_reduce(int epi, int stage, double dt, const EnsDesc *d_desc,
                          const PointItem *d_items, int n_items, hipStream_t s);
 hipError_t launch_rotsqrt(int64_t count, const double *R, double *S, hipStream_t s);

@@ -55,17 +55,32 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
     s = t;
 }
 
-// Contribution of one source to p[0..5] = (8 pi mu U, 8 pi mu eps Omega) of one
-// target, in units of eps.  Target position = th + tl (hi/lo split).
-__device__ __forceinline__ void pair_f32(float thx, float thy, float thz, float tlx, float tly,
-                                         float tlz, const float4 A, const float4 B,
-                                         const float4 C, float *p) {
-    const float rx = (thx - A.x) + (tlx - B.x);
-    const float ry = (thy - A.y) + (tly - B.y);
-    const float rz = (thz - A.z) + (tlz - B.z);
+// Pairs closer than rho = r/eps < 4 (R^2 = rho^2 + 1 < 17) carry the largest
+// terms of every sum; the FP32C kernels evaluate them in FP64 (on the exact
+// hi/lo difference) and every other pair in FP32.
+constexpr float kNearR2 = 17.0f;
+
+// R^2 = rho^2 + 1 of a target (th + tl) and a source record, in FP32.  Both
+// the hot loop and the near-pair rescan use this one function, so they take
+// the same near/far decision bit for bit.
+__device__ __forceinline__ float sep_f32(float thx, float thy, float thz, float tlx, float tly,
+                                         float tlz, const float4 A, const float4 B, float &rx,
+                                         float &ry, float &rz) {
+    rx = (thx - A.x) + (tlx - B.x);
+    ry = (thy - A.y) + (tly - B.y);
+    rz = (thz - A.z) + (tlz - B.z);
+    return fmaf(rz, rz, fmaf(ry, ry, fmaf(rx, rx, 1.0f)));
+}
+
+// Contribution of one far source to p[0..5] = (8 pi mu U, 8 pi mu eps Omega)
+// of one target, in units of eps; a near pair adds exactly zero.  Returns R^2.
+__device__ __forceinline__ float pair_f32(float thx, float thy, float thz, float tlx, float tly,
+                                          float tlz, const float4 A, const float4 B,
+                                          const float4 C, float *p) {
+    float rx, ry, rz;
+    const float R2 = sep_f32(thx, thy, thz, tlx, tly, tlz, A, B, rx, ry, rz);
     const float fx = A.w, fy = B.w, fz = C.x, nx = C.y, ny = C.z, nz = C.w;
-    const float R2 = fmaf(rz, rz, fmaf(ry, ry, fmaf(rx, rx, 1.0f)));
-    const float q = rsq_f32(R2);
+    const float q = R2 < kNearR2 ? 0.0f : rsq_f32(R2);
     const float q2 = q * q, q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
     const float h1 = q + q3;
     const float t = 1.5f * q5;
@@ -84,14 +99,15 @@ __device__ __forceinline__ void pair_f32(float thx, float thy, float thz, float 
     p[3] = fmaf(b, rx, fmaf(h4, nx, fmaf(h3, dx, p[3])));
     p[4] = fmaf(b, ry, fmaf(h4, ny, fmaf(h3, dy, p[4])));
     p[5] = fmaf(b, rz, fmaf(h4, nz, fmaf(h3, dz, p[5])));
+    return R2;
 }
 
-// Same in FP64 and unscaled units: p = (8 pi mu U, 8 pi mu Omega).
-__device__ __forceinline__ void pair_f64(double tx, double ty, double tz, double x, double y,
-                                         double z, double fx, double fy, double fz, double nx,
-                                         double ny, double nz, double e2, double c375e2,
-                                         double *p) {
-    const double rx = tx - x, ry = ty - y, rz = tz - z;
+// Same in FP64 for the separation r = x_target - X_source:
+// p += (8 pi mu U, 8 pi mu Omega) in unscaled units (e2 = eps^2, c375e2 =
+// 3.75 eps^2), or the eps-unit form with e2 = 1, c375e2 = 3.75.
+__device__ __forceinline__ void pair_f64_r(double rx, double ry, double rz, double fx, double fy,
+                                           double fz, double nx, double ny, double nz, double e2,
+                                           double c375e2, double *p) {
     const double R2 = fma(rz, rz, fma(ry, ry, fma(rx, rx, e2)));
     const double q = rsq_f64(R2);
     const double q2 = q * q, q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
@@ -112,6 +128,24 @@ __device__ __forceinline__ void pair_f64(double tx, double ty, double tz, double
     p[3] = fma(b, rx, fma(h4, nx, fma(h3, dx, p[3])));
     p[4] = fma(b, ry, fma(h4, ny, fma(h3, dy, p[4])));
     p[5] = fma(b, rz, fma(h4, nz, fma(h3, dz, p[5])));
+}
+
+__device__ __forceinline__ void pair_f64(double tx, double ty, double tz, double x, double y,
+                                         double z, double fx, double fy, double fz, double nx,
+                                         double ny, double nz, double e2, double c375e2,
+                                         double *p) {
+    pair_f64_r(tx - x, ty - y, tz - z, fx, fy, fz, nx, ny, nz, e2, c375e2, p);
+}
+
+// FP64 evaluation of a near pair from the FP32 record: the hi and lo
+// differences are exact in FP64, the loads are the record's FP32 values.
+__device__ __forceinline__ void near_pair_f64(float thx, float thy, float thz, float tlx, float tly,
+                                              float tlz, const float4 A, const float4 B,
+                                              const float4 C, double *p) {
+    const double rx = ((double)thx - (double)A.x) + ((double)tlx - (double)B.x);
+    const double ry = ((double)thy - (double)A.y) + ((double)tly - (double)B.y);
+    const double rz = ((double)thz - (double)A.z) + ((double)tlz - (double)B.z);
+    pair_f64_r(rx, ry, rz, A.w, B.w, C.x, C.y, C.z, C.w, 1.0, 3.75, p);
 }
 
 __device__ __forceinline__ RecF32 make_rec_f32(double x, double y, double z, double fx, double fy,
@@ -310,6 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_rod_forces(int prec, int stage_state
     const int k0 = E.off[it.fil];
     const int M = E.off[it.fil + 1] - k0;
     const int tid = threadIdx.x;
+    if (elastic < 0) elastic = E.elastic;
     for (int c0 = 0; c0 < M; c0 += kBlock - 1) {
         if (elastic) {
             const int s = c0 - 1 + tid;
@@ -368,6 +403,7 @@ template <int T>
 __global__ __launch_bounds__(kBlock) void k_pairs_tile_f32(const EnsDesc *__restrict__ desc,
                                                            const PairItem *__restrict__ items) {
     __shared__ float4 sA[kSrcTile], sB[kSrcTile], sC[kSrcTile];
+    __shared__ double sNear[6][T][kBlock];  // FP64 near-pair sums, one slot per lane and target
     const PairItem it = items[blockIdx.x];
     const EnsDesc &E = desc[it.ens];
     const RecF32 *__restrict__ rec = reinterpret_cast<const RecF32 *>(E.rec);
@@ -381,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs_tile_f32(const EnsDesc *__rest
         thx[t] = r.a.x; thy[t] = r.a.y; thz[t] = r.a.z;
         tlx[t] = r.b.x; tly[t] = r.b.y; tlz[t] = r.b.z;
 #pragma unroll
-        for (int k = 0; k < 6; k++) { s[t][k] = 0.0f; c[t][k] = 0.0f; }
+        for (int k = 0; k < 6; k++) { s[t][k] = 0.0f; c[t][k] = 0.0f; sNear[k][t][tid] = 0.0; }
     }
     for (int base = 0; base < it.nsrc; base += kSrcTile) {
         __syncthreads();
@@ -396,6 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs_tile_f32(const EnsDesc *__rest
         const int cnt = min(kSrcTile, it.nsrc - base);
         for (int sb = 0; sb < cnt; sb += kKahanBlock) {
             float p[T][6];
+            float rmin = kNearR2;
 #pragma unroll
             for (int t = 0; t < T; t++)
 #pragma unroll
@@ -404,12 +441,31 @@ __global__ __launch_bounds__(kBlock) void k_pairs_tile_f32(const EnsDesc *__rest
             for (int jj = sb; jj < sb + kKahanBlock; jj++) {
                 const float4 A = sA[jj], B = sB[jj], C = sC[jj];
 #pragma unroll
-                for (int t = 0; t < T; t++) pair_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], A, B, C, p[t]);
+                for (int t = 0; t < T; t++)
+                    rmin = fminf(rmin, pair_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], A, B, C, p[t]));
             }
 #pragma unroll
             for (int t = 0; t < T; t++)
 #pragma unroll
                 for (int k = 0; k < 6; k++) kahan_add(s[t][k], c[t][k], p[t][k]);
+            if (rmin < kNearR2) {
+                // this lane met a near pair in the sub-block: evaluate those in FP64
+                for (int jj = sb; jj < sb + kKahanBlock; jj++) {
+                    const float4 A = sA[jj], B = sB[jj], C = sC[jj];
+#pragma unroll
+                    for (int t = 0; t < T; t++) {
+                        float rx, ry, rz;
+                        if (sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], A, B, rx, ry, rz) < kNearR2) {
+                            double pn[6];
+#pragma unroll
+                            for (int k = 0; k < 6; k++) pn[k] = sNear[k][t][tid];
+                            near_pair_f64(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], A, B, C, pn);
+#pragma unroll
+                            for (int k = 0; k < 6; k++) sNear[k][t][tid] = pn[k];
+                        }
+                    }
+                }
+            }
         }
     }
     const int N = E.N;
@@ -419,7 +475,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs_tile_f32(const EnsDesc *__rest
         if (li < it.ntgt) {
 #pragma unroll
             for (int k = 0; k < 6; k++)
-                E.part[((size_t)it.chunk * 6 + k) * N + it.tgt0 + li] = (double)s[t][k] - (double)c[t][k];
+                E.part[((size_t)it.chunk * 6 + k) * N + it.tgt0 + li] =
+                    ((double)s[t][k] - (double)c[t][k]) + sNear[k][t][tid];
         }
     }
 }
@@ -495,17 +552,19 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
     if (PREC == 1) {
         const RecF32 *__restrict__ rec = reinterpret_cast<const RecF32 *>(E.rec);
         float thx[TW], thy[TW], thz[TW], tlx[TW], tly[TW], tlz[TW], s[TW][6], c[TW][6];
+        double pn[TW][6];
 #pragma unroll
         for (int t = 0; t < TW; t++) {
             const RecF32 r = rec[it.tgt0 + min(tb + t, it.ntgt - 1)];
             thx[t] = r.a.x; thy[t] = r.a.y; thz[t] = r.a.z;
             tlx[t] = r.b.x; tly[t] = r.b.y; tlz[t] = r.b.z;
 #pragma unroll
-            for (int k = 0; k < 6; k++) { s[t][k] = 0.f; c[t][k] = 0.f; }
+            for (int k = 0; k < 6; k++) { s[t][k] = 0.f; c[t][k] = 0.f; pn[t][k] = 0.0; }
         }
         constexpr int kPerLane = 16;  // sources per lane between compensated updates
         for (int j0 = 0; j0 < it.nsrc; j0 += 64 * kPerLane) {
             float p[TW][6];
+            float rmin = kNearR2;
 #pragma unroll
             for (int t = 0; t < TW; t++)
 #pragma unroll
@@ -514,17 +573,29 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
             for (int j = j0 + lane; j < jend; j += 64) {
                 const RecF32 r = rec[it.src0 + j];
 #pragma unroll
-                for (int t = 0; t < TW; t++) pair_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a, r.b, r.c, p[t]);
+                for (int t = 0; t < TW; t++)
+                    rmin = fminf(rmin, pair_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a, r.b, r.c, p[t]));
             }
 #pragma unroll
             for (int t = 0; t < TW; t++)
 #pragma unroll
                 for (int k = 0; k < 6; k++) kahan_add(s[t][k], c[t][k], p[t][k]);
+            if (rmin < kNearR2) {  // near pairs of this lane's sources: FP64
+                for (int j = j0 + lane; j < jend; j += 64) {
+                    const RecF32 r = rec[it.src0 + j];
+#pragma unroll
+                    for (int t = 0; t < TW; t++) {
+                        float rx, ry, rz;
+                        if (sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a, r.b, rx, ry, rz) < kNearR2)
+                            near_pair_f64(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a, r.b, r.c, pn[t]);
+                    }
+                }
+            }
         }
 #pragma unroll
         for (int t = 0; t < TW; t++)
 #pragma unroll
-            for (int k = 0; k < 6; k++) out[t][k] = wave_sum((double)s[t][k] - (double)c[t][k]);
+            for (int k = 0; k < 6; k++) out[t][k] = wave_sum(((double)s[t][k] - (double)c[t][k]) + pn[t][k]);
     } else {
         const RecF64 *__restrict__ rec = reinterpret_cast<const RecF64 *>(E.rec);
         const double e2 = E.eps * E.eps, c375e2 = 3.75 * e2;
@@ -591,6 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int stage, double dt, const E
     const int N = E.N;
     const int i = it.p0 + threadIdx.x;
     if (i >= N) return;
+    if (dt != dt) dt = E.dt;  // NaN: per-ensemble step size
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double *__restrict__ part = E.part;
     for (int k = 0; k < E.K; k++)

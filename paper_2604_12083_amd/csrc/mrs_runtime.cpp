@@ -69,7 +69,7 @@ PairCfg choose_cfg(mrs_context *ctx, int64_t N, int prec) {
     return c;
 }
 
-static void add_items(Plan &P, int e, int64_t N, int n_fil, const PairCfg &c) {
+void add_items(Plan &P, int e, int64_t N, int n_fil, const PairCfg &c) {
     if (c.mode == PAIR_SPLIT) {
         for (int64_t t0 = 0; t0 < N; t0 += kSplitTargetsPerBlock)
             P.split.push_back({e, (int)t0, (int)std::min<int64_t>(kSplitTargetsPerBlock, N - t0), 0, (int)N, 0});
@@ -97,7 +97,7 @@ static hipError_t upload_vec(DevBuf &d, const std::vector<T> &v) {
     return hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
-static hipError_t finalize_plan(Plan &P) {
+hipError_t finalize_plan(Plan &P) {
     hipError_t e;
     if ((e = upload_vec(P.d_desc, P.h_desc)) != hipSuccess) return e;
     if ((e = upload_vec(P.d_split, P.split)) != hipSuccess) return e;
@@ -139,11 +139,13 @@ static EnsDesc ensemble_desc(mrs_ensemble *E, int prec, const PairCfg &c) {
         d.om0[i] = E->rod.omega0[i];
     }
     d.ds = E->rod.ds;
+    d.dt = 0.0;
+    d.elastic = 1;
     return d;
 }
 
 // Plan of one ensemble for one precision (built once, reused).
-static mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out) {
+mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out) {
     mrs_context *ctx = E->ctx;
     if (!E->plan[prec]) {
         auto P = std::make_unique<Plan>();
@@ -152,6 +154,7 @@ static mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out) {
         PairCfg c = choose_cfg(ctx, E->N, prec);
         size_t need = (size_t)c.K * 6 * (size_t)E->N * sizeof(double);
         if (E->part.reserve(need) != hipSuccess) return fail(ctx, MRS_ENOMEM, "partial buffer (%zu bytes)", need);
+        P->cfg = c;
         P->h_desc.push_back(ensemble_desc(E, prec, c));
         add_items(*P, 0, E->N, E->n_fil, c);
         hipError_t e = finalize_plan(*P);
@@ -162,7 +165,7 @@ static mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out) {
     return MRS_OK;
 }
 
-static hipEvent_t take_event(mrs_context *ctx) {
+hipEvent_t take_event(mrs_context *ctx) {
     hipEvent_t ev = nullptr;
     if (!ctx->event_pool.empty()) {
         ev = ctx->event_pool.back();
@@ -173,23 +176,12 @@ static hipEvent_t take_event(mrs_context *ctx) {
     return ev;
 }
 
-template <class F>
-static hipError_t timed(mrs_context *ctx, const char *name, hipStream_t s, F &&launch) {
-    if (!ctx->prof_on) return launch();
-    hipEvent_t a = take_event(ctx), b = take_event(ctx);
-    if (a) (void)hipEventRecord(a, s);
-    hipError_t e = launch();
-    if (b) (void)hipEventRecord(b, s);
-    if (a && b) ctx->prof.push_back({name, a, b});
-    return e;
-}
-
 static const char *pair_name(int prec, int mode) {
     if (mode == PAIR_SPLIT) return prec == MRS_FP32C ? "pairs_split_f32c" : "pairs_split_f64";
     return prec == MRS_FP32C ? "pairs_tile_f32c" : "pairs_tile_f64";
 }
 
-static hipError_t run_pairs(mrs_context *ctx, Plan &P, hipStream_t s) {
+hipError_t run_pairs(mrs_context *ctx, Plan &P, hipStream_t s) {
     hipError_t e = hipSuccess;
     if (!P.split.empty())
         e = timed(ctx, pair_name(P.prec, PAIR_SPLIT), s, [&] {
@@ -209,7 +201,7 @@ static hipError_t run_pairs(mrs_context *ctx, Plan &P, hipStream_t s) {
     return e;
 }
 
-static const char *epi_name(int epi) {
+const char *epi_name(int epi) {
     switch (epi) {
         case EPI_EULER: return "reduce_euler";
         case EPI_RK4_STAGE: return "reduce_rk4_stage";
@@ -778,9 +770,8 @@ static mrs_status batch_plan(mrs_context *ctx, int32_t n_ens, mrs_ensemble *cons
             Plan *single;
             mrs_status st = ensemble_plan(E, prec, &single);
             if (st != MRS_OK) return st;
-            PairCfg c = choose_cfg(ctx, E->N, prec);
             P->h_desc.push_back(single->h_desc[0]);
-            add_items(*P, e, E->N, E->n_fil, c);
+            add_items(*P, e, E->N, E->n_fil, single->cfg);
         }
         hipError_t e = finalize_plan(*P);
         if (e != hipSuccess) return fail(ctx, MRS_EDEVICE, "batch plan upload: %s", hipGetErrorString(e));

@@ -61,6 +61,7 @@ struct Plan {
     // cached graphs: key = (integrator, dt bits, steps, elastic)
     std::map<std::tuple<int, uint64_t, int, int>, hipGraphExec_t> graphs;
     int64_t pairs_per_eval = 0;
+    PairCfg cfg;  // configuration of a single-ensemble plan
     ~Plan();
 };
 
@@ -112,6 +113,26 @@ namespace mrs {
 
 // Error helpers
 mrs_status fail(mrs_context *ctx, mrs_status st, const char *fmt, ...);
+mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out);
+void add_items(Plan &P, int e, int64_t N, int n_fil, const PairCfg &c);
+hipError_t finalize_plan(Plan &P);
+hipError_t run_pairs(mrs_context *ctx, Plan &P, hipStream_t s);
+hipEvent_t take_event(mrs_context *ctx);
+const char *epi_name(int epi);
+
+// Launch `launch()` on stream s; with profiling on, bracket it with events.
+template <class F>
+inline hipError_t timed(mrs_context *ctx, const char *name, hipStream_t s, F &&launch) {
+    if (!ctx->prof_on) return launch();
+    hipEvent_t a = take_event(ctx), b = take_event(ctx);
+    if (a) (void)hipEventRecord(a, s);
+    hipError_t e = launch();
+    if (b) (void)hipEventRecord(b, s);
+    if (a && b) ctx->prof.push_back({name, a, b});
+    return e;
+}
+
+
 PairCfg choose_cfg(mrs_context *ctx, int64_t N, int prec);
 size_t ensemble_bytes(int64_t N, int n_fil, bool has_ext, int K64, int K32);
 hipError_t run_stage(mrs_context *ctx, Plan &P, int stage_state, int elastic, int epi, int stage,

@@ -1,0 +1,157 @@
+"""Serving: continuous batching of independent ensemble requests.
+
+Each request's result must be identical alone (ensemble API, one request on
+the device) and served in a mix with others; admission respects the HBM
+budget; a request larger than the budget is rejected; a forced tick failure
+is retried from the step-boundary state without changing results."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import rod_of, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mrs():
+    import paper_2604_12083_amd as m
+
+    return m
+
+
+def _requests():
+    specs = [(4, 64, 0), (12, 100, 1), (1, 200, 1), (30, 128, 0), (7, 77, 1), (64, 64, 1), (2, 256, 0)]
+    out = []
+    for i, (F, M, kind) in enumerate(specs):
+        e = synth.filaments(F, M, 10.0, 500 + i)
+        out.append((e, kind))
+    return out
+
+
+def _alone(mrs, ctx, e, kind, prec, nsteps, dt):
+    h = mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, e.rod()))
+    try:
+        if kind == 0:
+            mrs.mrs_ensemble_eval(ctx, h, prec, True)
+        else:
+            mrs.mrs_ensemble_step(ctx, h, mrs.MRS_RK4, dt, nsteps, prec, True)
+        return mrs.mrs_ensemble_get(ctx, h)
+    finally:
+        mrs.mrs_ensemble_destroy(h)
+
+
+def _serve(mrs, ctx, reqs, prec, nsteps, dt, budget=8 << 30, slots=64, stagger=0.0):
+    srv = mrs.mrs_server_start(ctx, prec, budget, slots)
+    try:
+        tickets = []
+        for e, kind in reqs:
+            t = mrs.mrs_server_submit(srv, kind, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, e.rod()),
+                                      dt=dt, nsteps=nsteps, integ=mrs.MRS_RK4)
+            tickets.append(t)
+            if stagger:
+                time.sleep(stagger)
+        results = []
+        for (e, kind), t in zip(reqs, tickets):
+            st, info, out = mrs.mrs_server_wait(srv, t, e.N, timeout_s=120)
+            results.append((st, info, out))
+        stats = mrs.mrs_server_stats_get(srv)
+    finally:
+        mrs.mrs_server_stop(srv)
+    return results, stats
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_served_equals_alone(mrs, prec):
+    ctx = mrs.mrs_context_create(0)
+    try:
+        reqs = _requests()
+        nsteps, dt = 5, 1e-5
+        results, stats = _serve(mrs, ctx, reqs, prec, nsteps, dt, stagger=0.002)
+        say(f"served {len(reqs)} requests prec={prec}: ticks={stats['ticks']} pairs={stats['pairs']:.3e}")
+        for (e, kind), (st, info, out) in zip(reqs, results):
+            assert st == mrs.MRS_OK, (st, info.status)
+            X, D, U, W = out
+            Xa, Da, Ua, Wa = _alone(mrs, ctx, e, kind, prec, nsteps, dt)
+            np.testing.assert_array_equal(X, Xa)
+            np.testing.assert_array_equal(D, Da)
+            np.testing.assert_array_equal(U, Ua)
+            np.testing.assert_array_equal(W, Wa)
+            assert info.t_submit <= info.t_admit <= info.t_done
+            if kind == 1:
+                assert info.steps_done == nsteps
+        # one served evaluation against the oracle
+        e, kind = reqs[0]
+        Uo, Wo = oracle.velocities(e.offsets, e.X, e.D, e.rod(), e.f, e.n, e.eps, e.mu, True)
+        U, W = results[0][2][2], results[0][2][3]
+        tol = 1e-5 if prec == 1 else 1e-12
+        assert oracle.rel_err(U, Uo) <= tol and oracle.rel_err(W, Wo) <= tol
+    finally:
+        mrs.mrs_context_destroy(ctx)
+
+
+def test_admission_by_hbm_budget(mrs):
+    ctx = mrs.mrs_context_create(0)
+    try:
+        reqs = _requests()[:4]
+        # budget just above the largest single request: at most a couple resident at once
+        results, stats = _serve(mrs, ctx, reqs, mrs.MRS_FP32C, 2, 1e-5, budget=40 << 20, slots=64)
+        assert all(st == mrs.MRS_OK for st, _, _ in results)
+        assert stats["completed"] == len(reqs) and stats["hbm_in_use"] == 0
+        big = synth.filaments(400, 256, 10.0, 9)
+        srv = mrs.mrs_server_start(ctx, mrs.MRS_FP32C, 1 << 20, 4)
+        try:
+            t = mrs.mrs_server_submit(srv, 0, big.offsets, big.X, big.D, big.f, big.n, big.eps, big.mu,
+                                      rod_of(mrs, big.rod()))
+            st, info, out = mrs.mrs_server_wait(srv, t, big.N, timeout_s=60)
+            assert st == mrs.MRS_ENOMEM and out is None
+        finally:
+            mrs.mrs_server_stop(srv)
+    finally:
+        mrs.mrs_context_destroy(ctx)
+
+
+def test_forced_tick_failure_is_retried(mrs):
+    ctx = mrs.mrs_context_create(0)
+    os.environ["MRS_DEBUG_FAIL_TICK"] = "2"
+    try:
+        reqs = _requests()[:3]
+        results, stats = _serve(mrs, ctx, reqs, mrs.MRS_FP32C, 3, 1e-5)
+    finally:
+        del os.environ["MRS_DEBUG_FAIL_TICK"]
+    try:
+        assert stats["failed_ticks"] == 1
+        for (e, kind), (st, info, out) in zip(reqs, results):
+            assert st == mrs.MRS_OK
+            Xa, Da, Ua, Wa = _alone(mrs, ctx, e, kind, mrs.MRS_FP32C, 3, 1e-5)
+            np.testing.assert_array_equal(out[0], Xa)
+            np.testing.assert_array_equal(out[1], Da)
+    finally:
+        mrs.mrs_context_destroy(ctx)
+
+
+def test_invalid_requests(mrs):
+    ctx = mrs.mrs_context_create(0)
+    try:
+        srv = mrs.mrs_server_start(ctx, mrs.MRS_FP32C, 1 << 30, 4)
+        try:
+            e = synth.filaments(2, 10, 1.0, 3)
+            with pytest.raises(mrs.MrsError):
+                mrs.mrs_server_submit(srv, 1, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, e.rod()),
+                                      dt=1e-5, nsteps=0)
+            with pytest.raises(mrs.MrsError):
+                mrs.mrs_server_submit(srv, 0, e.offsets, e.X, e.D, e.f, e.n, -1.0, e.mu, rod_of(mrs, e.rod()))
+            Xb = e.X.copy()
+            Xb[0, 0] = np.inf
+            with pytest.raises(mrs.MrsError):
+                mrs.mrs_server_submit(srv, 0, e.offsets, Xb, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, e.rod()))
+            st, _, _ = mrs.mrs_server_poll(srv, 12345, 1)
+            assert st == mrs.MRS_EINVAL
+        finally:
+            mrs.mrs_server_stop(srv)
+    finally:
+        mrs.mrs_context_destroy(ctx)
