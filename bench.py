@@ -141,12 +141,100 @@ def roofline(pairs_per_launch, avg_s, peak_tflops, traffic=None):
             "frac": round(ach / peak_tflops, 4), "traffic": traffic}
 
 
+def bench_config3(mrs, ctx, steps, args):
+    """16 Parareal fine slices (32 x 100 points each), RK4 at dt = 1e-5, FP32C:
+    one batched launch sequence replayed from HIP graphs vs one launch per
+    kernel per slice per stage."""
+    import synth
+
+    base, slices = synth.config3()
+    rod = mrs.rod_params(*(getattr(base.rod(), k) for k in ("a", "b", "omega0", "ds")))
+
+    def make():
+        return [mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod) for e in slices]
+
+    hb, hp = make(), make()
+    try:
+        warm = max(1, min(10, steps // 10))
+        mrs.mrs_batch_step(ctx, hb, mrs.MRS_RK4, 1e-5, warm, mrs.MRS_FP32C, True, use_graph=True)
+        for h in hp:
+            mrs.mrs_ensemble_step(ctx, h, mrs.MRS_RK4, 1e-5, warm, mrs.MRS_FP32C, True)
+        t0 = time.perf_counter()
+        mrs.mrs_batch_step(ctx, hb, mrs.MRS_RK4, 1e-5, steps, mrs.MRS_FP32C, True, use_graph=True)
+        tb = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for h in hp:
+            mrs.mrs_ensemble_step(ctx, h, mrs.MRS_RK4, 1e-5, steps, mrs.MRS_FP32C, True)
+        tp = time.perf_counter() - t0
+        same = all(np.array_equal(mrs.mrs_ensemble_get(ctx, a)[0], mrs.mrs_ensemble_get(ctx, b)[0])
+                   for a, b in zip(hb, hp))
+    finally:
+        for h in hb + hp:
+            mrs.mrs_ensemble_destroy(h)
+    pairs = len(slices) * slices[0].N ** 2 * 4 * steps
+    return {"slices": len(slices), "points_per_slice": slices[0].N, "rk4_steps": steps,
+            "batched_graph_s": tb, "plain_s": tp, "batched_pairs_per_s": pairs / tb,
+            "plain_pairs_per_s": pairs / tp, "speedup": tp / tb, "identical_results": bool(same)}
+
+
+def bench_config4(mrs, ctx, n_req, rates, slots, budget):
+    """Serving: the fixed request sequence at Poisson arrival rates; continuous
+    batching (many slots) vs one request at a time (one slot)."""
+    import synth
+
+    reqs = synth.config4_requests()[:n_req]
+    ens = [synth.filaments(r.n_fil, r.M, 10.0, r.seed) for r in reqs]
+    out = {"requests": n_req, "points": [e.N for e in ens], "kinds": [r.kind for r in reqs]}
+    rods = [mrs.rod_params(*(getattr(e.rod(), k) for k in ("a", "b", "omega0", "ds"))) for e in ens]
+
+    def run(rate, nslots):
+        arr = synth.poisson_arrivals(n_req, rate)
+        srv = mrs.mrs_server_start(ctx, mrs.MRS_FP32C, budget, nslots)
+        tickets = []
+        try:
+            t0 = time.monotonic()
+            for i, (r, e) in enumerate(zip(reqs, ens)):
+                delay = t0 + arr[i] - time.monotonic()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets.append(mrs.mrs_server_submit(srv, r.kind, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu,
+                                                     rods[i], dt=1e-5, nsteps=50, integ=mrs.MRS_RK4))
+            lat, kinds = [], []
+            for i, t in enumerate(tickets):
+                st, info, _ = mrs.mrs_server_wait(srv, t, ens[i].N, timeout_s=600)
+                assert st == mrs.MRS_OK, st
+                lat.append(info.t_done - info.t_submit)
+                kinds.append(reqs[i].kind)
+            wall = time.monotonic() - t0
+            stats = mrs.mrs_server_stats_get(srv)
+        finally:
+            mrs.mrs_server_stop(srv)
+        lat = np.array(lat) * 1e3
+        kinds = np.array(kinds)
+        res = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "pairs_per_s": stats["pairs"] / wall, "wall_s": wall, "ticks": stats["ticks"],
+               "offered_req_per_s": rate}
+        for k, name in ((0, "eval"), (1, "rk4x50")):
+            if np.any(kinds == k):
+                res[f"p50_ms_{name}"] = float(np.percentile(lat[kinds == k], 50))
+                res[f"p99_ms_{name}"] = float(np.percentile(lat[kinds == k], 99))
+        return res
+
+    out["batched"] = {str(r): run(r, slots) for r in rates}
+    out["one_at_a_time"] = {str(rates[-1]): run(rates[-1], 1)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="config2", choices=["config2", "config5"])
+    ap.add_argument("--workload", default="config2", choices=["config2", "config5", "config3", "config4"])
+    ap.add_argument("--requests", type=int, default=32, help="config4: prefix of the request sequence")
+    ap.add_argument("--rates", default="10,100,1000", help="config4: Poisson arrival rates (req/s)")
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--dt", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
@@ -160,6 +248,33 @@ def main():
     import paper_2604_12083_amd as mrs
 
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.workload in ("config3", "config4"):
+        ctx = mrs.mrs_context_create(0)
+        try:
+            if args.workload == "config3":
+                r = bench_config3(mrs, ctx, args.steps, args)
+                line = {"metric": METRIC, "value": r["batched_pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+                        "steps": args.steps, "warmup": args.warmup,
+                        "ms_per_step": 1e3 * r["batched_graph_s"] / args.steps, "higher_is_better": True,
+                        "scaling": "weak", "vs_baseline": None, "dtype": "f32c", "data": "synthetic",
+                        "config": {"workload": "config3: 16 Parareal fine slices x (32 filaments x 100 points), "
+                                               "RK4 dt=1e-5, batched + HIP graph vs plain per-slice launches"},
+                        "config3": r}
+            else:
+                rates = [float(x) for x in args.rates.split(",")]
+                r = bench_config4(mrs, ctx, args.requests, rates, args.slots, int(args.budget_gb * (1 << 30)))
+                best = r["batched"][str(rates[-1])]
+                line = {"metric": METRIC, "value": best["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+                        "steps": args.requests, "warmup": 0, "ms_per_step": best["p50_ms"],
+                        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32c",
+                        "data": "synthetic",
+                        "config": {"workload": f"config4: first {args.requests} requests of the serving sequence, "
+                                               "Poisson arrivals, continuous batching"},
+                        "config4": r}
+        finally:
+            mrs.mrs_context_destroy(ctx)
+        print(json.dumps(line), flush=True)
+        return
     e, desc = workload(args.workload)
     ctx = mrs.mrs_context_create(0)
     try:

@@ -241,6 +241,28 @@ mrs_status mrs_server_stats_get(mrs_server *srv, mrs_server_stats *out);
 /* Finish admitted work, drop queued requests, join the thread, free srv. */
 mrs_status mrs_server_stop(mrs_server *srv);
 
+/* ---- pair-kernel tuning ------------------------------------------------ */
+
+/* How the pair kernel covers an ensemble of a given size: mode 0 = LDS-tiled
+ * (targets_per_lane 1 or 2, `chunks` source chunks, 0 = automatic), mode 1 =
+ * wave-split for small ensembles. */
+typedef struct {
+    int32_t mode;
+    int32_t targets_per_lane;
+    int32_t chunks;
+} mrs_pair_config;
+
+/* Time candidate configurations on a seeded synthetic ensemble of n points
+ * in precision `prec` (each candidate `reps` times, median kept) and store
+ * the fastest for every n of the same power-of-two size class.  *best (may
+ * be NULL) receives it and *best_ms its median pair-kernel time.  Ensembles
+ * already created keep the configuration they were planned with. */
+mrs_status mrs_autotune(mrs_context *ctx, int64_t n, mrs_precision prec, int32_t reps,
+                        mrs_pair_config *best, double *best_ms);
+/* Read / set the configuration used for ensembles of n points. */
+mrs_status mrs_tune_get(mrs_context *ctx, int64_t n, mrs_precision prec, mrs_pair_config *out);
+mrs_status mrs_tune_set(mrs_context *ctx, int64_t n, mrs_precision prec, const mrs_pair_config *cfg);
+
 /* ---- kernel timing ---------------------------------------------------- */
 
 /* When enabled, every kernel launch of the context is bracketed by HIP events

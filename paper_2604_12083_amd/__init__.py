@@ -68,6 +68,10 @@ class mrs_server_stats(ctypes.Structure):
 MRS_REQ_EVAL, MRS_REQ_STEPS = 0, 1
 
 
+class mrs_pair_config(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("targets_per_lane", ctypes.c_int32), ("chunks", ctypes.c_int32)]
+
+
 class MrsError(RuntimeError):
     def __init__(self, status, msg=""):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -108,6 +112,10 @@ _SIGS = {
     "mrs_server_wait": (_int, [_vp, ctypes.c_uint64, _dbl, ctypes.POINTER(mrs_result_info), _vp, _vp, _vp, _vp]),
     "mrs_server_stats_get": (_int, [_vp, ctypes.POINTER(mrs_server_stats)]),
     "mrs_server_stop": (_int, [_vp]),
+    "mrs_autotune": (_int, [_vp, _i64, _int, ctypes.c_int32, ctypes.POINTER(mrs_pair_config),
+                            ctypes.POINTER(_dbl)]),
+    "mrs_tune_get": (_int, [_vp, _i64, _int, ctypes.POINTER(mrs_pair_config)]),
+    "mrs_tune_set": (_int, [_vp, _i64, _int, ctypes.POINTER(mrs_pair_config)]),
     "mrs_profile_enable": (_int, [_vp, _int]),
     "mrs_profile_reset": (_int, [_vp]),
     "mrs_profile_query": (_int, [_vp, ctypes.c_char_p, ctypes.POINTER(_i64), ctypes.POINTER(_dbl)]),
@@ -349,3 +357,25 @@ def mrs_server_stats_get(srv):
 
 def mrs_server_stop(srv) -> None:
     _check(_lib.mrs_server_stop(srv))
+
+
+# ---- tuning -------------------------------------------------------------
+
+
+def mrs_autotune(ctx, n, prec=MRS_FP32C, reps=3):
+    """Returns ({mode, targets_per_lane, chunks}, best pair-kernel ms)."""
+    c = mrs_pair_config()
+    ms = _dbl()
+    _check(_lib.mrs_autotune(ctx, int(n), int(prec), int(reps), ctypes.byref(c), ctypes.byref(ms)), ctx)
+    return {"mode": c.mode, "targets_per_lane": c.targets_per_lane, "chunks": c.chunks}, float(ms.value)
+
+
+def mrs_tune_get(ctx, n, prec=MRS_FP32C):
+    c = mrs_pair_config()
+    _check(_lib.mrs_tune_get(ctx, int(n), int(prec), ctypes.byref(c)), ctx)
+    return {"mode": c.mode, "targets_per_lane": c.targets_per_lane, "chunks": c.chunks}
+
+
+def mrs_tune_set(ctx, n, prec, mode, targets_per_lane=1, chunks=0) -> None:
+    c = mrs_pair_config(int(mode), int(targets_per_lane), int(chunks))
+    _check(_lib.mrs_tune_set(ctx, int(n), int(prec), ctypes.byref(c)), ctx)

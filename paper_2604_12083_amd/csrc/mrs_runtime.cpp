@@ -29,7 +29,7 @@ Plan::~Plan() {
     for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
 }
 
-static int ilog2_bucket(int64_t N) {
+int size_bucket(int64_t N) {
     int b = 0;
     while ((int64_t(1) << (b + 1)) <= N) b++;
     return b;
@@ -40,7 +40,7 @@ static int ilog2_bucket(int64_t N) {
 // enough source chunks that the grid holds several blocks per compute unit.
 PairCfg choose_cfg(mrs_context *ctx, int64_t N, int prec) {
     PairCfg c;
-    auto it = ctx->tune.find({prec, ilog2_bucket(std::max<int64_t>(N, 1))});
+    auto it = ctx->tune.find({prec, size_bucket(std::max<int64_t>(N, 1))});
     if (it != ctx->tune.end()) c = it->second;
     else {
         c.mode = N <= 1024 ? PAIR_SPLIT : PAIR_TILE;

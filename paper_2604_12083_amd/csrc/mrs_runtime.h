@@ -134,6 +134,8 @@ inline hipError_t timed(mrs_context *ctx, const char *name, hipStream_t s, F &&l
 
 
 PairCfg choose_cfg(mrs_context *ctx, int64_t N, int prec);
+// Power-of-two size class of the tuning table.
+int size_bucket(int64_t N);
 size_t ensemble_bytes(int64_t N, int n_fil, bool has_ext, int K64, int K32);
 hipError_t run_stage(mrs_context *ctx, Plan &P, int stage_state, int elastic, int epi, int stage,
                      double dt, hipStream_t s);

@@ -127,3 +127,25 @@ def test_config5_full_size_sampled(mrs, ctx, prec):
     say(f"  rel err (2048 sampled targets) U {eu:.3e} W {ew:.3e}")
     assert eu <= TOL[prec] and ew <= TOL[prec]
     assert np.all(np.isfinite(U)) and np.all(np.isfinite(W))
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_autotune_and_every_config_parity(mrs, prec):
+    """Every pair-kernel decomposition the tuner can pick gives the same
+    result within tolerance; the tuned one is kept for the size class."""
+    c = mrs.mrs_context_create(0)
+    try:
+        e = synth.filaments(20, 128, 4.0, 77)
+        Uo, Wo = oracle.mrs_eval(e.X, e.f, e.n, e.eps, e.mu)
+        for cfg in [(1, 1, 0), (0, 1, 1), (0, 1, 7), (0, 2, 3), (0, 2, 0), (0, 1, 40)]:
+            mrs.mrs_tune_set(c, e.N, prec, *cfg)
+            U, W = eval_dev(mrs, c, e.X, e.f, e.n, e.eps, e.mu, prec)
+            eu, ew = oracle.rel_err(U, Uo), oracle.rel_err(W, Wo)
+            say(f"cfg {cfg} prec={prec}: U {eu:.3e} W {ew:.3e}")
+            assert eu <= TOL[prec] and ew <= TOL[prec], cfg
+        best, ms = mrs.mrs_autotune(c, e.N, prec, 3)
+        say(f"autotune N={e.N} prec={prec}: {best} {ms:.4f} ms")
+        assert mrs.mrs_tune_get(c, e.N, prec)["mode"] == best["mode"]
+        _check(mrs, c, e.X, e.f, e.n, e.eps, e.mu, prec, "tuned")
+    finally:
+        mrs.mrs_context_destroy(c)
