@@ -230,7 +230,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="config2", choices=["config2", "config5", "config3", "config4"])
+    ap.add_argument("--workload", default="config2",
+                    choices=["config2", "config5", "config3", "config4", "copy"])
     ap.add_argument("--requests", type=int, default=32, help="config4: prefix of the request sequence")
     ap.add_argument("--rates", default="10,100,1000", help="config4: Poisson arrival rates (req/s)")
     ap.add_argument("--slots", type=int, default=64)
@@ -248,6 +249,26 @@ def main():
     import paper_2604_12083_amd as mrs
 
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.workload == "copy":
+        # counter calibration: a plain device copy of 256 MiB (read 256 MiB, write 256 MiB) per launch
+        nbytes = 256 << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.warmup):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"metric": "device copy GB/s (counter calibration)", "value": 2 * nbytes / dt / 1e9,
+                          "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "copy of 256 MiB float64", "bytes_read": nbytes,
+                                     "bytes_written": nbytes}}), flush=True)
+        return
     if args.workload in ("config3", "config4"):
         ctx = mrs.mrs_context_create(0)
         try:

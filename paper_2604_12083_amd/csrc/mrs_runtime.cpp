@@ -2,6 +2,7 @@
 #include "mrs_runtime.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -635,8 +636,10 @@ mrs_status mrs_ensemble_create(mrs_context *ctx, int32_t n_fil, const int32_t *o
         (n_ext && !all_finite(n_ext, 3 * n)))
         return fail(ctx, MRS_EINVAL, "non-finite input");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    static std::atomic<uint64_t> next_uid{1};
     auto E = std::make_unique<mrs_ensemble>();
     E->ctx = ctx;
+    E->uid = next_uid.fetch_add(1);
     E->n_fil = n_fil;
     E->N = n;
     E->offsets.assign(offsets, offsets + n_fil + 1);
@@ -746,7 +749,7 @@ void mrs_ensemble_destroy(mrs_ensemble *E) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto it = ctx->batch_plans.begin(); it != ctx->batch_plans.end();) {
         const auto &v = it->first.first;
-        if (std::find(v.begin(), v.end(), E) != v.end()) it = ctx->batch_plans.erase(it);
+        if (std::find(v.begin(), v.end(), E->uid) != v.end()) it = ctx->batch_plans.erase(it);
         else ++it;
     }
     auto &L = ctx->ensembles;
@@ -757,7 +760,8 @@ void mrs_ensemble_destroy(mrs_ensemble *E) {
 // ---- batching
 
 static mrs_status batch_plan(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *ens, int prec, Plan **out) {
-    std::vector<mrs_ensemble *> key(ens, ens + n_ens);
+    std::vector<uint64_t> key;
+    for (int32_t i = 0; i < n_ens; i++) key.push_back(ens[i]->uid);
     auto k = std::make_pair(key, prec);
     auto it = ctx->batch_plans.find(k);
     if (it == ctx->batch_plans.end()) {

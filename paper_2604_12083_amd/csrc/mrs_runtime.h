@@ -92,13 +92,14 @@ struct mrs_context {
     // tuning table: (prec, log2 bucket of N) -> config
     std::map<std::pair<int, int>, mrs::PairCfg> tune;
     // batch plans
-    std::map<std::pair<std::vector<mrs_ensemble *>, int>, std::unique_ptr<mrs::Plan>> batch_plans;
+    std::map<std::pair<std::vector<uint64_t>, int>, std::unique_ptr<mrs::Plan>> batch_plans;
     std::vector<mrs_ensemble *> ensembles;
     std::recursive_mutex mu;
 };
 
 struct mrs_ensemble {
     mrs_context *ctx = nullptr;
+    uint64_t uid = 0;  // unique per process; plan caches key on it, never on addresses
     int32_t n_fil = 0;
     int64_t N = 0;
     std::vector<int32_t> offsets;

@@ -50,7 +50,7 @@ struct Request {
 
 // Work lists of one tick over the admitted set.
 struct TickPlan {
-    std::vector<mrs_ensemble *> key;
+    std::vector<uint64_t> key;  // ensemble uids of the admitted set, in order
     Plan all;    // stage 0 over every admitted request
     Plan rk;     // stages 1..3 over the RK4 step requests
     std::vector<PointItem> pts_write, pts_euler, pts_rk0;
@@ -97,8 +97,8 @@ hipError_t upload_list(DevBuf &d, const std::vector<T> &v) {
 
 // Build the tick plan of the admitted set (reused while the set is unchanged).
 mrs_status build_tick_plan(mrs_server *S) {
-    std::vector<mrs_ensemble *> key;
-    for (auto *r : S->active) key.push_back(r->ens);
+    std::vector<uint64_t> key;
+    for (auto *r : S->active) key.push_back(r->ens->uid);
     if (S->plan && S->plan->key == key) return MRS_OK;
     auto T = std::make_unique<TickPlan>();
     T->key = key;

@@ -29,3 +29,16 @@ def eval_dev(mrs, ctx, X, f, n, eps, mu, prec):
 
 def rod_of(mrs, e_rod):
     return mrs.rod_params(e_rod.a, e_rod.b, e_rod.omega0, e_rod.ds)
+
+
+def step_err(X1, X1o, X0):
+    """Relative error of a step's displacement, max over points:
+    |X1 - X1o| / |X1o - X0|, after removing the rounding of the stored
+    positions themselves (each side rounds every component once, at most
+    2 ulp of |X| together), which no arithmetic can avoid."""
+    X1, X1o, X0 = (np.asarray(a, dtype=np.float64).reshape(len(a), -1) for a in (X1, X1o, X0))
+    diff = np.linalg.norm(X1 - X1o, axis=1)
+    slack = 2.0 * np.finfo(np.float64).eps * np.linalg.norm(X1o, axis=1)
+    disp = np.linalg.norm(X1o - X0, axis=1)
+    err = np.maximum(diff - slack, 0.0) / np.where(disp == 0, 1.0, disp)
+    return float(err.max()) if len(err) else 0.0
