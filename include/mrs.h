@@ -67,9 +67,12 @@ typedef enum {
 
 typedef enum { MRS_FP64 = 0, MRS_FP32C = 1 } mrs_precision;
 
-/* Forward Euler (Eqs. newx, newD) and the classical four-stage Runge-Kutta
- * method with Rodrigues frame updates. */
-typedef enum { MRS_EULER = 1, MRS_RK4 = 4 } mrs_integrator;
+/* Forward Euler (Eqs. newx, newD), the second-order Runge-Kutta method of
+ * the paper's fine propagator (Sec. III.A, n = 2; midpoint rule) and the
+ * classical four-stage Runge-Kutta method.  Runge-Kutta stage states are
+ * X_s = X + c_s dt U_{s-1}, D_s = Rod(c_s dt Omega_{s-1}) D; a step ends with
+ * X += dt sum w_s U_s, D = Rod(dt sum w_s Omega_s) D (Rod = Eq. newD). */
+typedef enum { MRS_EULER = 1, MRS_RK2 = 2, MRS_RK4 = 4 } mrs_integrator;
 
 /* Rod moduli (Sec. II.A, Eq. constitutive_N_F): a = bending, bending, twist;
  * b = shear, shear, stretch; omega0 = intrinsic strain-twist vector;

@@ -19,8 +19,8 @@ listed in the tests under ``tests/test_oracle_*.py``):
   rod_forces / rod_energy   pinned (closed forms for stretch, twist and bend,
                             force and torque balance, frame indifference,
                             energy dissipation under relaxation)
-  step (Euler, RK4)         pinned (convergence orders 1 and 4, reduction of
-                            one RK4 stage to Euler, energy decay)
+  step (Euler, RK2, RK4)    pinned (convergence orders 1, 2 and 4, reduction
+                            of one RK stage to Euler, energy decay)
 Absolute U/Omega values of the configured workloads are "parity unpinned"
 by the paper itself, which prints none.
 """
@@ -215,6 +215,7 @@ def velocities(offsets, X, D, rod, fext, next_, eps, mu=1.0, include_elastic=Tru
 
 
 EULER = 1
+RK2 = 2
 RK4 = 4
 
 

@@ -429,6 +429,9 @@ void oracle_velocities(int32_t nfil, const int32_t *off, const double *X, const 
  *               X_s = X + c_s dt U_{s-1}, D_s = Rodrigues(c_s dt Omega_{s-1}) D,
  *               and the step ends with X <- X + dt sum_s w_s U_s,
  *               D <- Rodrigues(dt sum_s w_s Omega_s) D.
+ * integrator 2: the second-order Runge-Kutta method the paper's fine
+ *               propagator uses (Sec. III.A, n = 2), taken as the midpoint
+ *               rule: nodes c = (0, 1/2), weights (0, 1), same stage form.
  * Every step ends with oracle_reorthonormalize.  U, W (may be NULL) receive
  * the velocities of the first stage of the last step.
  */
@@ -450,11 +453,16 @@ void oracle_step(int32_t nfil, const int32_t *off, double *X, double *D,
             rotate_frames(n, W, dt, D, Ds);
             memcpy(D, Ds, v9);
         } else {
-            static const double cnode[4] = {0.0, 0.5, 0.5, 1.0};
-            static const double wgt[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
+            static const double cnode4[4] = {0.0, 0.5, 0.5, 1.0};
+            static const double wgt4[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
+            static const double cnode2[2] = {0.0, 0.5};
+            static const double wgt2[2] = {0.0, 1.0};
+            const int nstage = integrator == 2 ? 2 : 4;
+            const double *cnode = integrator == 2 ? cnode2 : cnode4;
+            const double *wgt = integrator == 2 ? wgt2 : wgt4;
             memset(Ua, 0, v3);
             memset(Wa, 0, v3);
-            for (int s = 0; s < 4; s++) {
+            for (int s = 0; s < nstage; s++) {
                 if (s == 0) {
                     memcpy(Xs, X, v3);
                     memcpy(Ds, D, v9);

@@ -34,7 +34,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 MRS_OK, MRS_EINVAL, MRS_ENOMEM, MRS_EDEVICE, MRS_ENOTREADY, MRS_EBUSY, MRS_ENUMERIC = 0, -1, -2, -3, -4, -5, -6
 MRS_FP64, MRS_FP32C = 0, 1
-MRS_EULER, MRS_RK4 = 1, 4
+MRS_EULER, MRS_RK2, MRS_RK4 = 1, 2, 4
 STATUS_NAMES = {0: "MRS_OK", -1: "MRS_EINVAL", -2: "MRS_ENOMEM", -3: "MRS_EDEVICE", -4: "MRS_ENOTREADY",
                 -5: "MRS_EBUSY", -6: "MRS_ENUMERIC"}
 

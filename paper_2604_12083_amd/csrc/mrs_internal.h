@@ -66,7 +66,10 @@ struct RodItem {
     int32_t ens, fil;
 };
 
-// One block of the reduction/epilogue kernel: points [p0, p0 + kBlock).
+// Points per block of the reduction/epilogue kernel.
+constexpr int kReducePoints = 64;
+
+// One block of the reduction/epilogue kernel: points [p0, p0 + kReducePoints).
 struct PointItem {
     int32_t ens, p0;
 };
@@ -74,9 +77,12 @@ struct PointItem {
 enum Epilogue : int {
     EPI_WRITE = 0,     // U, W only
     EPI_EULER = 1,     // U, W and a forward Euler step
-    EPI_RK4_STAGE = 2, // accumulate stage s, build stage state s + 1
-    EPI_RK4_FINAL = 3, // accumulate last stage, finish the step
+    EPI_RK_STAGE = 2,  // accumulate stage s, build stage state s + 1
+    EPI_RK_FINAL = 3,  // accumulate last stage, finish the step
 };
+
+// Runge-Kutta schemes of the stage epilogue.
+enum RkScheme : int { RK_SCHEME_RK4 = 0, RK_SCHEME_RK2 = 1 };
 
 // Launch wrappers (mrs_kernels.hip).  All return the launch's hipError_t.
 hipError_t launch_pack_aos(int prec, const EnsDesc *d_desc, const EnsDesc &h_desc,
@@ -87,7 +93,7 @@ hipError_t launch_rod_forces(int prec, int stage_state, int elastic, const EnsDe
 hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, const PairItem *d_items,
                         int n_items, hipStream_t s);
 // dt = NaN: every ensemble uses its own EnsDesc::dt.
-hipError_t launch_reduce(int epi, int stage, double dt, const EnsDesc *d_desc,
+hipError_t launch_reduce(int epi, int stage, int scheme, double dt, const EnsDesc *d_desc,
                          const PointItem *d_items, int n_items, hipStream_t s);
 hipError_t launch_rotsqrt(int64_t count, const double *R, double *S, hipStream_t s);
 

@@ -635,8 +635,11 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
 
 // ------------------------------------------------------- reduce + epilogue
 
-__constant__ double kRkWeight[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
-__constant__ double kRkNextNode[3] = {0.5, 0.5, 1.0};
+// Explicit Runge-Kutta schemes whose stage s + 1 depends on stage s only:
+// weights w_s and the node c_{s+1} of the next stage.  Scheme 0 is the
+// classical RK4, scheme 1 the midpoint RK2.
+__constant__ double kRkWeight[2][4] = {{1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0}, {0.0, 1.0, 0.0, 0.0}};
+__constant__ double kRkNextNode[2][3] = {{0.5, 0.5, 1.0}, {0.5, 0.0, 0.0}};
 
 __device__ __forceinline__ void rotate_frame(const double *__restrict__ Din, double *__restrict__ Dout,
                                              int N, int i, double vx, double vy, double vz,
@@ -654,20 +657,40 @@ __device__ __forceinline__ void rotate_frame(const double *__restrict__ Din, dou
     for (int k = 0; k < 9; k++) Dout[(size_t)k * N + i] = d[k];
 }
 
+// One block per kReducePoints points: the 4 waves each sum a fixed quarter of
+// the split-K chunks for the block's points (lane = point), the quarters are
+// combined through LDS in wave order, and wave 0 runs the epilogue.
 template <int EPI>
-__global__ __launch_bounds__(kBlock) void k_reduce(int stage, double dt, const EnsDesc *__restrict__ desc,
+__global__ __launch_bounds__(kBlock) void k_reduce(int stage, int scheme, double dt,
+                                                   const EnsDesc *__restrict__ desc,
                                                    const PointItem *__restrict__ items) {
+    __shared__ double sPart[kBlock / 64][6][64];
     const PointItem it = items[blockIdx.x];
     const EnsDesc &E = desc[it.ens];
     const int N = E.N;
-    const int i = it.p0 + threadIdx.x;
-    if (i >= N) return;
-    if (dt != dt) dt = E.dt;  // NaN: per-ensemble step size
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = it.p0 + lane;
+    const int K = E.K;
+    const int k0 = (K * w) / (kBlock / 64), k1 = (K * (w + 1)) / (kBlock / 64);
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const double *__restrict__ part = E.part;
-    for (int k = 0; k < E.K; k++)
+    if (i < N) {
+        const double *__restrict__ part = E.part;
+        for (int k = k0; k < k1; k++)
 #pragma unroll
-        for (int c = 0; c < 6; c++) acc[c] += part[((size_t)k * 6 + c) * N + i];
+            for (int c = 0; c < 6; c++) acc[c] += part[((size_t)k * 6 + c) * N + i];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; c++) sPart[w][c][lane] = acc[c];
+    __syncthreads();
+    if (w != 0 || i >= N) return;
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+        double v = sPart[0][c][lane];
+#pragma unroll
+        for (int q = 1; q < kBlock / 64; q++) v += sPart[q][c][lane];
+        acc[c] = v;
+    }
+    if (dt != dt) dt = E.dt;  // NaN: per-ensemble step size
     const double U[3] = {acc[0] * E.cU, acc[1] * E.cU, acc[2] * E.cU};
     const double W[3] = {acc[3] * E.cW, acc[4] * E.cW, acc[5] * E.cW};
     if (EPI == EPI_WRITE) {
@@ -690,23 +713,23 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int stage, double dt, const E
         rotate_frame(E.D, E.D, N, i, dt * W[0], dt * W[1], dt * W[2], true);
         return;
     }
-    // RK4: stage s in 0..3 evaluated at the stage state.
-    const double w = kRkWeight[stage];
+    // Runge-Kutta stage `stage` of `scheme`, evaluated at the stage state.
+    const double wgt = kRkWeight[scheme][stage];
     double ua[3], wa[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         if (stage == 0) {
             E.U[(size_t)c * N + i] = U[c];
             E.W[(size_t)c * N + i] = W[c];
-            ua[c] = w * U[c];
-            wa[c] = w * W[c];
+            ua[c] = wgt * U[c];
+            wa[c] = wgt * W[c];
         } else {
-            ua[c] = E.Ua[(size_t)c * N + i] + w * U[c];
-            wa[c] = E.Wa[(size_t)c * N + i] + w * W[c];
+            ua[c] = E.Ua[(size_t)c * N + i] + wgt * U[c];
+            wa[c] = E.Wa[(size_t)c * N + i] + wgt * W[c];
         }
     }
-    if (EPI == EPI_RK4_STAGE) {
-        const double h = kRkNextNode[stage] * dt;
+    if (EPI == EPI_RK_STAGE) {
+        const double h = kRkNextNode[scheme][stage] * dt;
 #pragma unroll
         for (int c = 0; c < 3; c++) {
             E.Ua[(size_t)c * N + i] = ua[c];
@@ -756,15 +779,15 @@ hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, cons
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(int epi, int stage, double dt, const EnsDesc *d_desc,
+hipError_t launch_reduce(int epi, int stage, int scheme, double dt, const EnsDesc *d_desc,
                          const PointItem *d_items, int n_items, hipStream_t s) {
     if (n_items == 0) return hipSuccess;
     const dim3 g(n_items), b(kBlock);
     switch (epi) {
-        case EPI_EULER: hipLaunchKernelGGL(k_reduce<EPI_EULER>, g, b, 0, s, stage, dt, d_desc, d_items); break;
-        case EPI_RK4_STAGE: hipLaunchKernelGGL(k_reduce<EPI_RK4_STAGE>, g, b, 0, s, stage, dt, d_desc, d_items); break;
-        case EPI_RK4_FINAL: hipLaunchKernelGGL(k_reduce<EPI_RK4_FINAL>, g, b, 0, s, stage, dt, d_desc, d_items); break;
-        default: hipLaunchKernelGGL(k_reduce<EPI_WRITE>, g, b, 0, s, stage, dt, d_desc, d_items); break;
+        case EPI_EULER: hipLaunchKernelGGL(k_reduce<EPI_EULER>, g, b, 0, s, stage, scheme, dt, d_desc, d_items); break;
+        case EPI_RK_STAGE: hipLaunchKernelGGL(k_reduce<EPI_RK_STAGE>, g, b, 0, s, stage, scheme, dt, d_desc, d_items); break;
+        case EPI_RK_FINAL: hipLaunchKernelGGL(k_reduce<EPI_RK_FINAL>, g, b, 0, s, stage, scheme, dt, d_desc, d_items); break;
+        default: hipLaunchKernelGGL(k_reduce<EPI_WRITE>, g, b, 0, s, stage, scheme, dt, d_desc, d_items); break;
     }
     return hipGetLastError();
 }

@@ -86,7 +86,7 @@ void add_items(Plan &P, int e, int64_t N, int n_fil, const PairCfg &c) {
             }
     }
     for (int f = 0; f < n_fil; f++) P.rods.push_back({e, f});
-    for (int64_t p0 = 0; p0 < N; p0 += kBlock) P.pts.push_back({e, (int)p0});
+    for (int64_t p0 = 0; p0 < N; p0 += kReducePoints) P.pts.push_back({e, (int)p0});
     P.pairs_per_eval += N * N;
 }
 
@@ -205,13 +205,13 @@ hipError_t run_pairs(mrs_context *ctx, Plan &P, hipStream_t s) {
 const char *epi_name(int epi) {
     switch (epi) {
         case EPI_EULER: return "reduce_euler";
-        case EPI_RK4_STAGE: return "reduce_rk4_stage";
-        case EPI_RK4_FINAL: return "reduce_rk4_final";
+        case EPI_RK_STAGE: return "reduce_rk_stage";
+        case EPI_RK_FINAL: return "reduce_rk_final";
         default: return "reduce_write";
     }
 }
 
-hipError_t run_stage(mrs_context *ctx, Plan &P, int stage_state, int elastic, int epi, int stage,
+hipError_t run_stage(mrs_context *ctx, Plan &P, int stage_state, int elastic, int epi, int stage, int scheme,
                      double dt, hipStream_t s) {
     hipError_t e = timed(ctx, "rod_forces", s, [&] {
         return launch_rod_forces(P.prec, stage_state, elastic, P.d_desc.as<EnsDesc>(), P.d_rods.as<RodItem>(),
@@ -220,7 +220,8 @@ hipError_t run_stage(mrs_context *ctx, Plan &P, int stage_state, int elastic, in
     if (e != hipSuccess) return e;
     if ((e = run_pairs(ctx, P, s)) != hipSuccess) return e;
     return timed(ctx, epi_name(epi), s, [&] {
-        return launch_reduce(epi, stage, dt, P.d_desc.as<EnsDesc>(), P.d_pts.as<PointItem>(), (int)P.pts.size(), s);
+        return launch_reduce(epi, stage, scheme, dt, P.d_desc.as<EnsDesc>(), P.d_pts.as<PointItem>(),
+                             (int)P.pts.size(), s);
     });
 }
 
@@ -230,10 +231,11 @@ static hipError_t queue_steps(mrs_context *ctx, Plan &P, int integ, double dt, i
     for (int step = 0; step < nsteps; step++) {
         hipError_t e;
         if (integ == MRS_EULER) {
-            if ((e = run_stage(ctx, P, 0, elastic, EPI_EULER, 0, dt, s)) != hipSuccess) return e;
+            if ((e = run_stage(ctx, P, 0, elastic, EPI_EULER, 0, 0, dt, s)) != hipSuccess) return e;
         } else {
-            for (int st = 0; st < 4; st++) {
-                e = run_stage(ctx, P, st > 0, elastic, st < 3 ? EPI_RK4_STAGE : EPI_RK4_FINAL, st, dt, s);
+            const int nst = rk_stages(integ), scheme = rk_scheme(integ);
+            for (int st = 0; st < nst; st++) {
+                e = run_stage(ctx, P, st > 0, elastic, st < nst - 1 ? EPI_RK_STAGE : EPI_RK_FINAL, st, scheme, dt, s);
                 if (e != hipSuccess) return e;
             }
         }
@@ -458,7 +460,7 @@ mrs_status mrs_eval_device(mrs_context *ctx, int64_t n, const double *dX, const 
                                 (int)P.tile2.size(), s);
         }));
     HIPCHK(ctx, timed(ctx, "reduce_write", s, [&] {
-        return launch_reduce(EPI_WRITE, 0, 0.0, dd, reinterpret_cast<const PointItem *>(base + o_pts),
+        return launch_reduce(EPI_WRITE, 0, 0, 0.0, dd, reinterpret_cast<const PointItem *>(base + o_pts),
                              (int)P.pts.size(), s);
     }));
     return MRS_OK;
@@ -698,14 +700,15 @@ mrs_status mrs_ensemble_eval(mrs_ensemble *E, mrs_precision prec, int include_el
     Plan *P;
     mrs_status st = ensemble_plan(E, (int)prec, &P);
     if (st != MRS_OK) return st;
-    HIPCHK(ctx, run_stage(ctx, *P, 0, include_elastic ? 1 : 0, EPI_WRITE, 0, 0.0, ctx->stream));
+    HIPCHK(ctx, run_stage(ctx, *P, 0, include_elastic ? 1 : 0, EPI_WRITE, 0, 0, 0.0, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return MRS_OK;
 }
 
 static mrs_status check_step_args(mrs_context *ctx, mrs_integrator integ, double dt, int32_t nsteps,
                                   mrs_precision prec) {
-    if (integ != MRS_EULER && integ != MRS_RK4) return fail(ctx, MRS_EINVAL, "unknown integrator %d", (int)integ);
+    if (integ != MRS_EULER && integ != MRS_RK2 && integ != MRS_RK4)
+        return fail(ctx, MRS_EINVAL, "unknown integrator %d", (int)integ);
     if (!std::isfinite(dt)) return fail(ctx, MRS_EINVAL, "dt must be finite");
     if (nsteps < 0) return fail(ctx, MRS_EINVAL, "nsteps < 0");
     if (prec != MRS_FP64 && prec != MRS_FP32C) return fail(ctx, MRS_EINVAL, "unknown precision");
@@ -822,7 +825,7 @@ mrs_status mrs_batch_eval(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     Plan *P;
     if ((st = batch_plan(ctx, n_ens, ens, (int)prec, &P)) != MRS_OK) return st;
-    HIPCHK(ctx, run_stage(ctx, *P, 0, include_elastic ? 1 : 0, EPI_WRITE, 0, 0.0, ctx->stream));
+    HIPCHK(ctx, run_stage(ctx, *P, 0, include_elastic ? 1 : 0, EPI_WRITE, 0, 0, 0.0, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return MRS_OK;
 }

@@ -138,8 +138,11 @@ PairCfg choose_cfg(mrs_context *ctx, int64_t N, int prec);
 // Power-of-two size class of the tuning table.
 int size_bucket(int64_t N);
 size_t ensemble_bytes(int64_t N, int n_fil, bool has_ext, int K64, int K32);
-hipError_t run_stage(mrs_context *ctx, Plan &P, int stage_state, int elastic, int epi, int stage,
+hipError_t run_stage(mrs_context *ctx, Plan &P, int stage_state, int elastic, int epi, int stage, int scheme,
                      double dt, hipStream_t s);
+// Stages and epilogue scheme of a Runge-Kutta integrator.
+inline int rk_stages(int integ) { return integ == MRS_RK2 ? 2 : 4; }
+inline int rk_scheme(int integ) { return integ == MRS_RK2 ? RK_SCHEME_RK2 : RK_SCHEME_RK4; }
 hipError_t upload(mrs_context *ctx, void *dst, const void *src, size_t bytes, hipStream_t s);
 
 }  // namespace mrs

@@ -51,11 +51,11 @@ struct Request {
 // Work lists of one tick over the admitted set.
 struct TickPlan {
     std::vector<uint64_t> key;  // ensemble uids of the admitted set, in order
-    Plan all;    // stage 0 over every admitted request
-    Plan rk;     // stages 1..3 over the RK4 step requests
-    std::vector<PointItem> pts_write, pts_euler, pts_rk0;
-    DevBuf d_pts_write, d_pts_euler, d_pts_rk0;
-    bool has_rk = false;
+    Plan all;       // stage 0 over every admitted request
+    Plan rk[2];     // later stages of the RK4 (scheme 0) and RK2 (scheme 1) step requests
+    std::vector<PointItem> pts_write, pts_euler, pts_rk0[2];
+    DevBuf d_pts_write, d_pts_euler, d_pts_rk0[2];
+    bool has_rk[2] = {false, false};
 };
 
 }  // namespace
@@ -102,7 +102,7 @@ mrs_status build_tick_plan(mrs_server *S) {
     if (S->plan && S->plan->key == key) return MRS_OK;
     auto T = std::make_unique<TickPlan>();
     T->key = key;
-    T->all.prec = T->rk.prec = S->prec;
+    T->all.prec = T->rk[0].prec = T->rk[1].prec = S->prec;
     for (size_t e = 0; e < S->active.size(); e++) {
         Request *r = S->active[e];
         Plan *single;
@@ -112,23 +112,27 @@ mrs_status build_tick_plan(mrs_server *S) {
         d.dt = r->spec.dt;
         d.elastic = r->spec.include_elastic ? 1 : 0;
         T->all.h_desc.push_back(d);
-        T->rk.h_desc.push_back(d);
+        T->rk[0].h_desc.push_back(d);
+        T->rk[1].h_desc.push_back(d);
         add_items(T->all, (int)e, r->N, r->spec.n_fil, single->cfg);
-        const bool rk = r->spec.kind == MRS_REQ_STEPS && r->spec.integ == MRS_RK4;
+        const bool rk = r->spec.kind == MRS_REQ_STEPS && r->spec.integ != MRS_EULER;
+        const int sch = rk ? rk_scheme(r->spec.integ) : 0;
         if (rk) {
-            add_items(T->rk, (int)e, r->N, r->spec.n_fil, single->cfg);
-            T->has_rk = true;
+            add_items(T->rk[sch], (int)e, r->N, r->spec.n_fil, single->cfg);
+            T->has_rk[sch] = true;
         }
         std::vector<PointItem> *dst = r->spec.kind == MRS_REQ_EVAL ? &T->pts_write
-                                      : rk                           ? &T->pts_rk0
+                                      : rk                           ? &T->pts_rk0[sch]
                                                                      : &T->pts_euler;
-        for (int64_t p0 = 0; p0 < r->N; p0 += kBlock) dst->push_back({(int)e, (int)p0});
+        for (int64_t p0 = 0; p0 < r->N; p0 += kReducePoints) dst->push_back({(int)e, (int)p0});
     }
     hipError_t he = finalize_plan(T->all);
-    if (he == hipSuccess && T->has_rk) he = finalize_plan(T->rk);
+    for (int k = 0; k < 2; k++)
+        if (he == hipSuccess && T->has_rk[k]) he = finalize_plan(T->rk[k]);
     if (he == hipSuccess) he = upload_list(T->d_pts_write, T->pts_write);
     if (he == hipSuccess) he = upload_list(T->d_pts_euler, T->pts_euler);
-    if (he == hipSuccess) he = upload_list(T->d_pts_rk0, T->pts_rk0);
+    for (int k = 0; k < 2; k++)
+        if (he == hipSuccess) he = upload_list(T->d_pts_rk0[k], T->pts_rk0[k]);
     if (he != hipSuccess) return fail(S->ctx, MRS_EDEVICE, "tick plan upload: %s", hipGetErrorString(he));
     S->plan = std::move(T);
     return MRS_OK;
@@ -147,18 +151,23 @@ hipError_t launch_tick(mrs_server *S) {
     const EnsDesc *dd = T.all.d_desc.as<EnsDesc>();
     if (e == hipSuccess && !T.pts_write.empty())
         e = timed(ctx, epi_name(EPI_WRITE), s, [&] {
-            return launch_reduce(EPI_WRITE, 0, nan, dd, T.d_pts_write.as<PointItem>(), (int)T.pts_write.size(), s);
+            return launch_reduce(EPI_WRITE, 0, 0, nan, dd, T.d_pts_write.as<PointItem>(), (int)T.pts_write.size(), s);
         });
     if (e == hipSuccess && !T.pts_euler.empty())
         e = timed(ctx, epi_name(EPI_EULER), s, [&] {
-            return launch_reduce(EPI_EULER, 0, nan, dd, T.d_pts_euler.as<PointItem>(), (int)T.pts_euler.size(), s);
+            return launch_reduce(EPI_EULER, 0, 0, nan, dd, T.d_pts_euler.as<PointItem>(), (int)T.pts_euler.size(), s);
         });
-    if (e == hipSuccess && !T.pts_rk0.empty())
-        e = timed(ctx, epi_name(EPI_RK4_STAGE), s, [&] {
-            return launch_reduce(EPI_RK4_STAGE, 0, nan, dd, T.d_pts_rk0.as<PointItem>(), (int)T.pts_rk0.size(), s);
-        });
-    for (int st = 1; e == hipSuccess && T.has_rk && st < 4; st++)
-        e = run_stage(ctx, T.rk, 1, -1, st < 3 ? EPI_RK4_STAGE : EPI_RK4_FINAL, st, nan, s);
+    for (int k = 0; k < 2; k++)
+        if (e == hipSuccess && !T.pts_rk0[k].empty())
+            e = timed(ctx, epi_name(EPI_RK_STAGE), s, [&] {
+                return launch_reduce(EPI_RK_STAGE, 0, k, nan, dd, T.d_pts_rk0[k].as<PointItem>(),
+                                     (int)T.pts_rk0[k].size(), s);
+            });
+    for (int k = 0; k < 2; k++) {
+        const int nst = k == RK_SCHEME_RK2 ? 2 : 4;
+        for (int st = 1; e == hipSuccess && T.has_rk[k] && st < nst; st++)
+            e = run_stage(ctx, T.rk[k], 1, -1, st < nst - 1 ? EPI_RK_STAGE : EPI_RK_FINAL, st, k, nan, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e;
 }
@@ -283,8 +292,8 @@ void loop(mrs_server *S) {
                 finished.push_back(r);
                 continue;
             }
-            const bool rk = r->spec.kind == MRS_REQ_STEPS && r->spec.integ == MRS_RK4;
-            pairs += (rk ? 4 : 1) * r->N * r->N;
+            const int evals = (r->spec.kind == MRS_REQ_STEPS && r->spec.integ != MRS_EULER) ? rk_stages(r->spec.integ) : 1;
+            pairs += evals * r->N * r->N;
             const bool fin = r->spec.kind == MRS_REQ_EVAL || ++r->steps_done >= r->spec.nsteps;
             (fin ? finished : keep).push_back(r);
         }
@@ -353,7 +362,8 @@ mrs_status mrs_server_submit(mrs_server *S, const mrs_request *q, uint64_t *tick
         if (q->offsets[i + 1] <= q->offsets[i]) return MRS_EINVAL;
     if (!(q->eps > 0) || !(q->mu > 0) || !std::isfinite(q->eps) || !std::isfinite(q->mu)) return MRS_EINVAL;
     if (q->kind == MRS_REQ_STEPS &&
-        (q->nsteps < 1 || !std::isfinite(q->dt) || (q->integ != MRS_EULER && q->integ != MRS_RK4)))
+        (q->nsteps < 1 || !std::isfinite(q->dt) ||
+         (q->integ != MRS_EULER && q->integ != MRS_RK2 && q->integ != MRS_RK4)))
         return MRS_EINVAL;
     auto *r = new (std::nothrow) Request();
     if (!r) return MRS_ENOMEM;

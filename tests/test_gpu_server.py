@@ -24,22 +24,26 @@ def mrs():
     return m
 
 
+# (filaments, points per filament, kind, integrator) of a mixed request set
+SPECS = [(4, 64, 0, "RK4"), (12, 100, 1, "RK4"), (1, 200, 1, "RK2"), (30, 128, 0, "RK4"), (7, 77, 1, "EULER"),
+         (64, 64, 1, "RK4"), (2, 256, 0, "RK4"), (9, 90, 1, "RK2")]
+
+
 def _requests():
-    specs = [(4, 64, 0), (12, 100, 1), (1, 200, 1), (30, 128, 0), (7, 77, 1), (64, 64, 1), (2, 256, 0)]
     out = []
-    for i, (F, M, kind) in enumerate(specs):
+    for i, (F, M, kind, integ) in enumerate(SPECS):
         e = synth.filaments(F, M, 10.0, 500 + i)
-        out.append((e, kind))
+        out.append((e, kind, integ))
     return out
 
 
-def _alone(mrs, ctx, e, kind, prec, nsteps, dt):
+def _alone(mrs, ctx, e, kind, integ, prec, nsteps, dt):
     h = mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, e.rod()))
     try:
         if kind == 0:
             mrs.mrs_ensemble_eval(ctx, h, prec, True)
         else:
-            mrs.mrs_ensemble_step(ctx, h, mrs.MRS_RK4, dt, nsteps, prec, True)
+            mrs.mrs_ensemble_step(ctx, h, getattr(mrs, "MRS_" + integ), dt, nsteps, prec, True)
         return mrs.mrs_ensemble_get(ctx, h)
     finally:
         mrs.mrs_ensemble_destroy(h)
@@ -49,14 +53,14 @@ def _serve(mrs, ctx, reqs, prec, nsteps, dt, budget=8 << 30, slots=64, stagger=0
     srv = mrs.mrs_server_start(ctx, prec, budget, slots)
     try:
         tickets = []
-        for e, kind in reqs:
+        for e, kind, integ in reqs:
             t = mrs.mrs_server_submit(srv, kind, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, e.rod()),
-                                      dt=dt, nsteps=nsteps, integ=mrs.MRS_RK4)
+                                      dt=dt, nsteps=nsteps, integ=getattr(mrs, "MRS_" + integ))
             tickets.append(t)
             if stagger:
                 time.sleep(stagger)
         results = []
-        for (e, kind), t in zip(reqs, tickets):
+        for (e, kind, integ), t in zip(reqs, tickets):
             st, info, out = mrs.mrs_server_wait(srv, t, e.N, timeout_s=120)
             results.append((st, info, out))
         stats = mrs.mrs_server_stats_get(srv)
@@ -73,10 +77,10 @@ def test_served_equals_alone(mrs, prec):
         nsteps, dt = 5, 1e-5
         results, stats = _serve(mrs, ctx, reqs, prec, nsteps, dt, stagger=0.002)
         say(f"served {len(reqs)} requests prec={prec}: ticks={stats['ticks']} pairs={stats['pairs']:.3e}")
-        for (e, kind), (st, info, out) in zip(reqs, results):
+        for (e, kind, integ), (st, info, out) in zip(reqs, results):
             assert st == mrs.MRS_OK, (st, info.status)
             X, D, U, W = out
-            Xa, Da, Ua, Wa = _alone(mrs, ctx, e, kind, prec, nsteps, dt)
+            Xa, Da, Ua, Wa = _alone(mrs, ctx, e, kind, integ, prec, nsteps, dt)
             np.testing.assert_array_equal(X, Xa)
             np.testing.assert_array_equal(D, Da)
             np.testing.assert_array_equal(U, Ua)
@@ -85,7 +89,7 @@ def test_served_equals_alone(mrs, prec):
             if kind == 1:
                 assert info.steps_done == nsteps
         # one served evaluation against the oracle
-        e, kind = reqs[0]
+        e, kind, _ = reqs[0]
         Uo, Wo = oracle.velocities(e.offsets, e.X, e.D, e.rod(), e.f, e.n, e.eps, e.mu, True)
         U, W = results[0][2][2], results[0][2][3]
         tol = 1e-5 if prec == 1 else 1e-12
@@ -125,9 +129,9 @@ def test_forced_tick_failure_is_retried(mrs):
         del os.environ["MRS_DEBUG_FAIL_TICK"]
     try:
         assert stats["failed_ticks"] == 1
-        for (e, kind), (st, info, out) in zip(reqs, results):
+        for (e, kind, integ), (st, info, out) in zip(reqs, results):
             assert st == mrs.MRS_OK
-            Xa, Da, Ua, Wa = _alone(mrs, ctx, e, kind, mrs.MRS_FP32C, 3, 1e-5)
+            Xa, Da, Ua, Wa = _alone(mrs, ctx, e, kind, integ, mrs.MRS_FP32C, 3, 1e-5)
             np.testing.assert_array_equal(out[0], Xa)
             np.testing.assert_array_equal(out[1], Da)
     finally:

@@ -88,9 +88,10 @@ def test_config1_euler_teacher_forced(mrs, ctx, prec):
         mrs.mrs_ensemble_destroy(ens)
 
 
+@pytest.mark.parametrize("integ", ["RK4", "RK2"])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_rk4_teacher_forced(mrs, ctx, prec):
-    """Config-3 geometry (32 filaments x 100 points), RK4 at dt = 1e-5."""
+def test_rk_teacher_forced(mrs, ctx, prec, integ):
+    """Config-3 geometry (32 filaments x 100 points), RK4 / RK2 at dt = 1e-5."""
     base, slices = synth.config3(n_slices=1)
     e = slices[0]
     rod = e.rod()
@@ -99,11 +100,11 @@ def test_rk4_teacher_forced(mrs, ctx, prec):
     try:
         X, D, _, _ = mrs.mrs_ensemble_get(ctx, ens)
         for step in range(3):
-            Xo, Do, _, _ = oracle.step(e.offsets, X, D, rod, e.f, e.n, e.eps, e.mu, oracle.RK4, dt, 1)
-            mrs.mrs_ensemble_step(ctx, ens, mrs.MRS_RK4, dt, 1, prec, True)
+            Xo, Do, _, _ = oracle.step(e.offsets, X, D, rod, e.f, e.n, e.eps, e.mu, getattr(oracle, integ), dt, 1)
+            mrs.mrs_ensemble_step(ctx, ens, getattr(mrs, "MRS_" + integ), dt, 1, prec, True)
             X1, D1, _, _ = mrs.mrs_ensemble_get(ctx, ens)
             ex, ed = step_err(X1, Xo, X), _frame_err(D1, Do)
-            say(f"rk4 prec={prec} step {step}: dX {ex:.3e} D {ed:.3e}")
+            say(f"{integ} prec={prec} step {step}: dX {ex:.3e} D {ed:.3e}")
             assert ex <= TOL[prec] and ed <= TOL[prec]
             X, D = X1, D1
     finally:

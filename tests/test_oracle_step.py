@@ -3,8 +3,9 @@ the fine propagator of Sec. III.A is an explicit Runge-Kutta method).
 
   * Convergence orders: with zero moduli the positions follow the autonomous
     ODE dX/dt = U(X) driven by fixed loads, so forward Euler must converge
-    at order 1 and the classical RK4 at order 4 (error ratios ~2 and ~16
-    when dt halves), measured against a much finer RK4 solution.
+    at order 1, the midpoint RK2 at order 2 and the classical RK4 at order
+    4 (error ratios ~2, ~4 and ~16 when dt halves), measured against a much
+    finer RK4 solution.
   * One Euler step equals its definition composed from the pinned pieces
     (rod forces, MRS sum, Rodrigues update, re-orthonormalisation).
   * Frames stay orthonormal and right-handed over many steps.
@@ -37,9 +38,12 @@ def test_convergence_orders(oracle_mod):
     errs = {}
     for integ, steps in ((oracle_mod.EULER, (32, 64, 128)), (oracle_mod.RK4, (8, 16, 32))):
         errs[integ] = [np.abs(_run(oracle_mod, e, rod, integ, T, s)[0] - Xref).max() for s in steps]
+    errs[2] = [np.abs(_run(oracle_mod, e, rod, oracle_mod.RK2, T, s)[0] - Xref).max() for s in (16, 32, 64)]
     r_e = [errs[1][i] / errs[1][i + 1] for i in range(2)]
+    r_2 = [errs[2][i] / errs[2][i + 1] for i in range(2)]
     r_4 = [errs[4][i] / errs[4][i + 1] for i in range(2)]
     assert all(1.8 < r < 2.3 for r in r_e), (errs[1], r_e)
+    assert all(3.5 < r < 4.6 for r in r_2), (errs[2], r_2)
     assert all(13.0 < r < 19.0 for r in r_4), (errs[4], r_4)
 
 
