@@ -177,7 +177,7 @@ def bench_config3(mrs, ctx, steps, args):
             "plain_pairs_per_s": pairs / tp, "speedup": tp / tb, "identical_results": bool(same)}
 
 
-def bench_config4(mrs, ctx, n_req, rates, slots, budget):
+def bench_config4(mrs, ctx, n_req, rates, slots, budget, tick_pairs=0):
     """Serving: the fixed request sequence at Poisson arrival rates; continuous
     batching (many slots) vs one request at a time (one slot)."""
     import synth
@@ -190,6 +190,7 @@ def bench_config4(mrs, ctx, n_req, rates, slots, budget):
     def run(rate, nslots):
         arr = synth.poisson_arrivals(n_req, rate)
         srv = mrs.mrs_server_start(ctx, mrs.MRS_FP32C, budget, nslots)
+        mrs.mrs_server_set_tick_pairs(srv, int(tick_pairs) if nslots > 1 else 0)
         tickets = []
         try:
             t0 = time.monotonic()
@@ -236,6 +237,7 @@ def main():
     ap.add_argument("--rates", default="10,100,1000", help="config4: Poisson arrival rates (req/s)")
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--tick-pairs", type=float, default=2e10, help="config4: pair budget of one serving tick")
     ap.add_argument("--dt", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
@@ -283,7 +285,8 @@ def main():
                         "config3": r}
             else:
                 rates = [float(x) for x in args.rates.split(",")]
-                r = bench_config4(mrs, ctx, args.requests, rates, args.slots, int(args.budget_gb * (1 << 30)))
+                r = bench_config4(mrs, ctx, args.requests, rates, args.slots, int(args.budget_gb * (1 << 30)),
+                                  args.tick_pairs)
                 best = r["batched"][str(rates[-1])]
                 line = {"metric": METRIC, "value": best["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
                         "steps": args.requests, "warmup": 0, "ms_per_step": best["p50_ms"],

@@ -229,6 +229,13 @@ typedef struct {
  * and its requests are retried from their step-boundary state. */
 mrs_status mrs_server_start(mrs_context *ctx, mrs_precision prec, int64_t hbm_budget_bytes,
                             int32_t max_slots, mrs_server **out);
+/* Bound the work of one tick to about max_pairs pair interactions (0 = no
+ * bound: every admitted request advances every tick).  With a bound, each
+ * admitted request earns an equal share of the budget per tick and runs in
+ * the ticks where its earned share covers one unit of its work (deficit
+ * round robin): small requests advance every tick, larger ones every few
+ * ticks, so a large request does not hold every small one to its pace. */
+mrs_status mrs_server_set_tick_pairs(mrs_server *srv, int64_t max_pairs);
 /* Any host thread.  *ticket identifies the request. */
 mrs_status mrs_server_submit(mrs_server *srv, const mrs_request *req, uint64_t *ticket);
 /* Non-blocking.  MRS_ENOTREADY until the request is done; then fills info,

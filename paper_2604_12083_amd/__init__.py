@@ -112,6 +112,7 @@ _SIGS = {
     "mrs_server_wait": (_int, [_vp, ctypes.c_uint64, _dbl, ctypes.POINTER(mrs_result_info), _vp, _vp, _vp, _vp]),
     "mrs_server_stats_get": (_int, [_vp, ctypes.POINTER(mrs_server_stats)]),
     "mrs_server_stop": (_int, [_vp]),
+    "mrs_server_set_tick_pairs": (_int, [_vp, _i64]),
     "mrs_autotune": (_int, [_vp, _i64, _int, ctypes.c_int32, ctypes.POINTER(mrs_pair_config),
                             ctypes.POINTER(_dbl)]),
     "mrs_tune_get": (_int, [_vp, _i64, _int, ctypes.POINTER(mrs_pair_config)]),
@@ -353,6 +354,10 @@ def mrs_server_stats_get(srv):
     s = mrs_server_stats()
     _check(_lib.mrs_server_stats_get(srv, ctypes.byref(s)))
     return {k: getattr(s, k) for k, _ in mrs_server_stats._fields_}
+
+
+def mrs_server_set_tick_pairs(srv, max_pairs) -> None:
+    _check(_lib.mrs_server_set_tick_pairs(srv, int(max_pairs)))
 
 
 def mrs_server_stop(srv) -> None:

@@ -13,6 +13,7 @@
 // Requests arriving while a tick runs join at the next tick, so work of
 // requests of different sizes and kinds overlaps inside the same kernels.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -45,6 +46,8 @@ struct Request {
     int64_t footprint = -1;
     mrs_result_info info{};
     bool done = false;
+    double credit = 0.0;  // pair budget earned and not yet spent (deficit round robin)
+    int64_t cost = 0;     // pair interactions of one unit of work (eval or step)
     std::vector<double> Xo, Do, Uo, Wo;
 };
 
@@ -76,7 +79,10 @@ struct mrs_server {
     bool stopping = false;
     mrs_server_stats st{};
     int64_t fail_tick = -1;
-    std::unique_ptr<TickPlan> plan;
+    std::atomic<int64_t> tick_pairs{0};  // 0 = no per-tick bound
+    // tick plans of recently used request sets (small LRU)
+    std::vector<std::unique_ptr<TickPlan>> plans;
+    TickPlan *plan = nullptr;
 };
 
 namespace {
@@ -95,16 +101,23 @@ hipError_t upload_list(DevBuf &d, const std::vector<T> &v) {
     return hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
-// Build the tick plan of the admitted set (reused while the set is unchanged).
-mrs_status build_tick_plan(mrs_server *S) {
+constexpr size_t kPlanCache = 16;
+
+// Tick plan of the requests `run` (cached per set; the cache is small LRU).
+mrs_status build_tick_plan(mrs_server *S, const std::vector<Request *> &run) {
     std::vector<uint64_t> key;
-    for (auto *r : S->active) key.push_back(r->ens->uid);
-    if (S->plan && S->plan->key == key) return MRS_OK;
+    for (auto *r : run) key.push_back(r->ens->uid);
+    for (size_t i = 0; i < S->plans.size(); i++)
+        if (S->plans[i]->key == key) {
+            std::rotate(S->plans.begin(), S->plans.begin() + i, S->plans.begin() + i + 1);
+            S->plan = S->plans.front().get();
+            return MRS_OK;
+        }
     auto T = std::make_unique<TickPlan>();
     T->key = key;
     T->all.prec = T->rk[0].prec = T->rk[1].prec = S->prec;
-    for (size_t e = 0; e < S->active.size(); e++) {
-        Request *r = S->active[e];
+    for (size_t e = 0; e < run.size(); e++) {
+        Request *r = run[e];
         Plan *single;
         mrs_status st = ensemble_plan(r->ens, S->prec, &single);
         if (st != MRS_OK) return st;
@@ -134,13 +147,47 @@ mrs_status build_tick_plan(mrs_server *S) {
     for (int k = 0; k < 2; k++)
         if (he == hipSuccess) he = upload_list(T->d_pts_rk0[k], T->pts_rk0[k]);
     if (he != hipSuccess) return fail(S->ctx, MRS_EDEVICE, "tick plan upload: %s", hipGetErrorString(he));
-    S->plan = std::move(T);
+    S->plans.insert(S->plans.begin(), std::move(T));
+    if (S->plans.size() > kPlanCache) S->plans.pop_back();
+    S->plan = S->plans.front().get();
     return MRS_OK;
+}
+
+// Forget cached plans that mention a retired request's ensemble.
+void drop_plans(mrs_server *S, uint64_t uid) {
+    for (auto it = S->plans.begin(); it != S->plans.end();) {
+        const auto &k = (*it)->key;
+        if (std::find(k.begin(), k.end(), uid) != k.end()) it = S->plans.erase(it);
+        else ++it;
+    }
+    S->plan = nullptr;
+}
+
+int evals_per_unit(const Request *r) {
+    return (r->spec.kind == MRS_REQ_STEPS && r->spec.integ != MRS_EULER) ? rk_stages(r->spec.integ) : 1;
+}
+
+// Requests that advance in this tick: all of them without a tick bound; with
+// one, deficit round robin over the admitted requests.
+std::vector<Request *> pick_tick(mrs_server *S) {
+    const int64_t budget = S->tick_pairs.load();
+    if (budget <= 0) return S->active;
+    std::vector<Request *> run;
+    const double quantum = (double)budget / (double)S->active.size();
+    Request *best = nullptr;
+    for (auto *r : S->active) {
+        r->credit += quantum;
+        if (r->credit >= (double)r->cost) run.push_back(r);
+        if (!best || r->credit / (double)r->cost > best->credit / (double)best->cost) best = r;
+    }
+    if (run.empty()) run.push_back(best);  // always make progress
+    for (auto *r : run) r->credit = std::max(0.0, r->credit - (double)r->cost);
+    return run;
 }
 
 hipError_t launch_tick(mrs_server *S) {
     mrs_context *ctx = S->ctx;
-    TickPlan &T = *S->plan;
+    TickPlan &T = *S->plan;  // set by build_tick_plan
     hipStream_t s = ctx->stream;
     const double nan = std::nan("");
     hipError_t e = timed(ctx, "rod_forces", s, [&] {
@@ -269,7 +316,10 @@ void loop(mrs_server *S) {
         }
         if (S->active.empty()) continue;
         tick++;
-        mrs_status st = build_tick_plan(S);
+        for (auto *r : S->active)
+            if (r->cost == 0) r->cost = (int64_t)evals_per_unit(r) * r->N * r->N;
+        std::vector<Request *> run = pick_tick(S);
+        mrs_status st = build_tick_plan(S, run);
         const double t0 = now_s();
         hipError_t he = hipSuccess;
         bool failed = false;
@@ -292,13 +342,22 @@ void loop(mrs_server *S) {
                 finished.push_back(r);
                 continue;
             }
-            const int evals = (r->spec.kind == MRS_REQ_STEPS && r->spec.integ != MRS_EULER) ? rk_stages(r->spec.integ) : 1;
-            pairs += evals * r->N * r->N;
+            if (std::find(run.begin(), run.end(), r) == run.end()) {  // did not run this tick
+                keep.push_back(r);
+                continue;
+            }
+            pairs += r->cost;
             const bool fin = r->spec.kind == MRS_REQ_EVAL || ++r->steps_done >= r->spec.nsteps;
             (fin ? finished : keep).push_back(r);
         }
-        for (auto *r : finished) collect(r, ok ? MRS_OK : (st != MRS_OK ? st : MRS_EDEVICE));
-        if (!ok) S->plan.reset();
+        for (auto *r : finished) {
+            if (r->ens) drop_plans(S, r->ens->uid);
+            collect(r, ok ? MRS_OK : (st != MRS_OK ? st : MRS_EDEVICE));
+        }
+        if (!ok) {
+            S->plans.clear();
+            S->plan = nullptr;
+        }
         std::lock_guard<std::mutex> lk(S->mu);
         S->st.ticks++;
         S->st.busy_s += t1 - t0;
@@ -445,6 +504,12 @@ mrs_status mrs_server_wait(mrs_server *S, uint64_t ticket, double timeout_s, mrs
     }
 }
 
+mrs_status mrs_server_set_tick_pairs(mrs_server *S, int64_t max_pairs) {
+    if (!S || max_pairs < 0) return MRS_EINVAL;
+    S->tick_pairs.store(max_pairs);
+    return MRS_OK;
+}
+
 mrs_status mrs_server_stats_get(mrs_server *S, mrs_server_stats *out) {
     if (!S || !out) return MRS_EINVAL;
     std::lock_guard<std::mutex> lk(S->mu);
@@ -469,7 +534,7 @@ mrs_status mrs_server_stop(mrs_server *S) {
     }
     if (S->th.joinable()) S->th.join();
     for (auto &kv : S->table) delete kv.second;
-    S->plan.reset();
+    S->plans.clear();
     delete S;
     return MRS_OK;
 }

@@ -49,8 +49,9 @@ def _alone(mrs, ctx, e, kind, integ, prec, nsteps, dt):
         mrs.mrs_ensemble_destroy(h)
 
 
-def _serve(mrs, ctx, reqs, prec, nsteps, dt, budget=8 << 30, slots=64, stagger=0.0):
+def _serve(mrs, ctx, reqs, prec, nsteps, dt, budget=8 << 30, slots=64, stagger=0.0, tick_pairs=0):
     srv = mrs.mrs_server_start(ctx, prec, budget, slots)
+    mrs.mrs_server_set_tick_pairs(srv, tick_pairs)
     try:
         tickets = []
         for e, kind, integ in reqs:
@@ -69,14 +70,16 @@ def _serve(mrs, ctx, reqs, prec, nsteps, dt, budget=8 << 30, slots=64, stagger=0
     return results, stats
 
 
+@pytest.mark.parametrize("tick_pairs", [0, 2_000_000])
 @pytest.mark.parametrize("prec", [1, 0])
-def test_served_equals_alone(mrs, prec):
+def test_served_equals_alone(mrs, prec, tick_pairs):
     ctx = mrs.mrs_context_create(0)
     try:
         reqs = _requests()
         nsteps, dt = 5, 1e-5
-        results, stats = _serve(mrs, ctx, reqs, prec, nsteps, dt, stagger=0.002)
-        say(f"served {len(reqs)} requests prec={prec}: ticks={stats['ticks']} pairs={stats['pairs']:.3e}")
+        results, stats = _serve(mrs, ctx, reqs, prec, nsteps, dt, stagger=0.002, tick_pairs=tick_pairs)
+        say(f"served {len(reqs)} requests prec={prec} tick_pairs={tick_pairs}: ticks={stats['ticks']} "
+            f"pairs={stats['pairs']:.3e}")
         for (e, kind, integ), (st, info, out) in zip(reqs, results):
             assert st == mrs.MRS_OK, (st, info.status)
             X, D, U, W = out
