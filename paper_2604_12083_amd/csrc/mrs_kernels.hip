@@ -91,14 +91,14 @@ __device__ __forceinline__ float pair_f32(float thx, float thy, float thz, float
     const float fr = fmaf(fz, rz, fmaf(fy, ry, fx * rx));
     const float nr = fmaf(nz, rz, fmaf(ny, ry, nx * rx));
     const float a = q3 * fr, b = h5 * nr;
-    const float cx = fmaf(ny, rz, -nz * ry), cy = fmaf(nz, rx, -nx * rz), cz = fmaf(nx, ry, -ny * rx);
-    const float dx = fmaf(fy, rz, -fz * ry), dy = fmaf(fz, rx, -fx * rz), dz = fmaf(fx, ry, -fy * rx);
-    p[0] = fmaf(h3, cx, fmaf(a, rx, fmaf(h1, fx, p[0])));
-    p[1] = fmaf(h3, cy, fmaf(a, ry, fmaf(h1, fy, p[1])));
-    p[2] = fmaf(h3, cz, fmaf(a, rz, fmaf(h1, fz, p[2])));
-    p[3] = fmaf(b, rx, fmaf(h4, nx, fmaf(h3, dx, p[3])));
-    p[4] = fmaf(b, ry, fmaf(h4, ny, fmaf(h3, dy, p[4])));
-    p[5] = fmaf(b, rz, fmaf(h4, nz, fmaf(h3, dz, p[5])));
+    // H3 (n x r) = n x g and H3 (f x r) = f x g with g = H3 r
+    const float gx = h3 * rx, gy = h3 * ry, gz = h3 * rz;
+    p[0] = fmaf(-nz, gy, fmaf(ny, gz, fmaf(a, rx, fmaf(h1, fx, p[0]))));
+    p[1] = fmaf(-nx, gz, fmaf(nz, gx, fmaf(a, ry, fmaf(h1, fy, p[1]))));
+    p[2] = fmaf(-ny, gx, fmaf(nx, gy, fmaf(a, rz, fmaf(h1, fz, p[2]))));
+    p[3] = fmaf(-fz, gy, fmaf(fy, gz, fmaf(b, rx, fmaf(h4, nx, p[3]))));
+    p[4] = fmaf(-fx, gz, fmaf(fz, gx, fmaf(b, ry, fmaf(h4, ny, p[4]))));
+    p[5] = fmaf(-fy, gx, fmaf(fx, gy, fmaf(b, rz, fmaf(h4, nz, p[5]))));
     return R2;
 }
 
@@ -120,14 +120,13 @@ __device__ __forceinline__ void pair_f64_r(double rx, double ry, double rz, doub
     const double fr = fma(fz, rz, fma(fy, ry, fx * rx));
     const double nr = fma(nz, rz, fma(ny, ry, nx * rx));
     const double a = q3 * fr, b = h5 * nr;
-    const double cx = fma(ny, rz, -nz * ry), cy = fma(nz, rx, -nx * rz), cz = fma(nx, ry, -ny * rx);
-    const double dx = fma(fy, rz, -fz * ry), dy = fma(fz, rx, -fx * rz), dz = fma(fx, ry, -fy * rx);
-    p[0] = fma(h3, cx, fma(a, rx, fma(h1, fx, p[0])));
-    p[1] = fma(h3, cy, fma(a, ry, fma(h1, fy, p[1])));
-    p[2] = fma(h3, cz, fma(a, rz, fma(h1, fz, p[2])));
-    p[3] = fma(b, rx, fma(h4, nx, fma(h3, dx, p[3])));
-    p[4] = fma(b, ry, fma(h4, ny, fma(h3, dy, p[4])));
-    p[5] = fma(b, rz, fma(h4, nz, fma(h3, dz, p[5])));
+    const double gx = h3 * rx, gy = h3 * ry, gz = h3 * rz;  // see pair_f32
+    p[0] = fma(-nz, gy, fma(ny, gz, fma(a, rx, fma(h1, fx, p[0]))));
+    p[1] = fma(-nx, gz, fma(nz, gx, fma(a, ry, fma(h1, fy, p[1]))));
+    p[2] = fma(-ny, gx, fma(nx, gy, fma(a, rz, fma(h1, fz, p[2]))));
+    p[3] = fma(-fz, gy, fma(fy, gz, fma(b, rx, fma(h4, nx, p[3]))));
+    p[4] = fma(-fx, gz, fma(fz, gx, fma(b, ry, fma(h4, ny, p[4]))));
+    p[5] = fma(-fy, gx, fma(fx, gy, fma(b, rz, fma(h4, nz, p[5]))));
 }
 
 __device__ __forceinline__ void pair_f64(double tx, double ty, double tz, double x, double y,

@@ -38,14 +38,19 @@ int size_bucket(int64_t N) {
 
 // Default pair-kernel configuration for an ensemble of N points.  Small
 // ensembles use the wave-split kernel; larger ones the LDS-tiled kernel with
-// enough source chunks that the grid holds several blocks per compute unit.
+// 1 (FP32C) or 2 (FP64) targets per lane and enough source chunks that the
+// grid holds ~64 blocks per compute unit (short blocks keep the tail of the
+// grid short; measured on MI355X at 12,800 and 256,000 points).  A chunk
+// has at least 128 sources and at least N/64, so the split-K partials stay
+// a small fraction of the pair work.
+
 PairCfg choose_cfg(mrs_context *ctx, int64_t N, int prec) {
     PairCfg c;
     auto it = ctx->tune.find({prec, size_bucket(std::max<int64_t>(N, 1))});
     if (it != ctx->tune.end()) c = it->second;
     else {
         c.mode = N <= 1024 ? PAIR_SPLIT : PAIR_TILE;
-        c.tpl = (prec == MRS_FP32C) ? 2 : 1;
+        c.tpl = (prec == MRS_FP32C) ? 1 : 2;
         c.K = 0;
     }
     if (c.mode == PAIR_SPLIT) {
@@ -55,18 +60,17 @@ PairCfg choose_cfg(mrs_context *ctx, int64_t N, int prec) {
     }
     const int64_t tile = (int64_t)kBlock * c.tpl;
     const int64_t tiles = (N + tile - 1) / tile;
-    int64_t K = c.K;
-    if (K <= 0) {
-        const int64_t want_blocks = (int64_t)ctx->n_cu * 8;
-        K = (want_blocks + tiles - 1) / tiles;
+    int64_t chunk;
+    if (c.K <= 0) {
+        const int64_t want_blocks = (int64_t)ctx->n_cu * 64;
+        const int64_t K = (want_blocks + tiles - 1) / tiles;
+        chunk = std::max<int64_t>({(N + K - 1) / K, (int64_t)2 * kKahanBlock, N / 64});
+    } else {
+        chunk = (N + c.K - 1) / c.K;
     }
-    const int64_t maxK = std::max<int64_t>(1, (N + kKahanBlock - 1) / kKahanBlock);
-    K = std::min(std::max<int64_t>(K, 1), maxK);
-    int64_t chunk = (N + K - 1) / K;
     chunk = ((chunk + kKahanBlock - 1) / kKahanBlock) * kKahanBlock;
     c.chunk = (int)std::max<int64_t>(chunk, kKahanBlock);
-    c.K = (int)((N + c.chunk - 1) / c.chunk);
-    if (c.K < 1) c.K = 1;
+    c.K = (int)std::max<int64_t>(1, (N + c.chunk - 1) / c.chunk);
     return c;
 }
 
