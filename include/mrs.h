@@ -273,6 +273,29 @@ mrs_status mrs_autotune(mrs_context *ctx, int64_t n, mrs_precision prec, int32_t
 mrs_status mrs_tune_get(mrs_context *ctx, int64_t n, mrs_precision prec, mrs_pair_config *out);
 mrs_status mrs_tune_set(mrs_context *ctx, int64_t n, mrs_precision prec, const mrs_pair_config *cfg);
 
+/* ---- Parareal on one device (Sec. II.D, Eqs. initial, intermediate,
+ *      serial_correct; Sec. III.A) -------------------------------------- */
+
+/* Parareal from the current state of `ens` over n_slices time slices of
+ * length fine_steps * fine_dt.  The fine propagator F takes fine_steps steps
+ * of fine_integ; the coarse propagator G takes coarse_steps forward-Euler
+ * steps of the same slice.  Iteration 0 is the serial coarse sweep; iteration
+ * k runs F on slices k..n_slices as ONE batched launch sequence (replayed
+ * from a HIP graph), then corrects slices k+1.. serially with
+ * X^k_n = F(X^{k-1}_{n-1}) + G(X^k_{n-1}) - G(X^{k-1}_{n-1}) applied to the
+ * positions and the frames (frames re-orthonormalised after the
+ * correction).  Stops when the relative increment of the slice-boundary
+ * positions (max over points of |x^k - x^{k-1}| / |x^k|) is <= tol, or after
+ * max_iter iterations (max_iter <= n_slices; after n_slices iterations the
+ * result equals the serial fine solution).  On return `ens` holds the state
+ * at the end of the last slice; history (max_iter doubles, may be NULL)
+ * receives the increments, *iters (may be NULL) the iterations done.  All
+ * state stays on the device; one host copy of the positions per iteration
+ * evaluates the increment. */
+mrs_status mrs_parareal(mrs_ensemble *ens, int32_t n_slices, mrs_integrator fine_integ, double fine_dt,
+                        int32_t fine_steps, int32_t coarse_steps, int32_t max_iter, double tol,
+                        mrs_precision prec, int include_elastic, double *history, int32_t *iters);
+
 /* ---- kernel timing ---------------------------------------------------- */
 
 /* When enabled, every kernel launch of the context is bracketed by HIP events

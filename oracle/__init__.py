@@ -242,3 +242,58 @@ def rel_err(a, b) -> float:
     num = np.linalg.norm(a - b, axis=1)
     den = np.linalg.norm(b, axis=1)
     return float(np.max(num / np.where(den == 0, 1.0, den))) if len(num) else 0.0
+
+
+def parareal(offsets, X0, D0, rod, fext, next_, eps, mu, n_slices, fine_integ, fine_dt, fine_steps,
+             coarse_steps, max_iter, tol=0.0, include_elastic=True):
+    """Standard Parareal (Sec. II.D, Eqs. initial, intermediate, serial_correct).
+
+    The slice propagators advance one time slice of length
+    Delta T = fine_dt * fine_steps: F takes `fine_steps` steps of `fine_integ`,
+    G takes `coarse_steps` forward-Euler steps (Sec. III.A: the coarse solver
+    is explicit Euler).  The state of a slice boundary is (X, D); the
+    correction of Eq. serial_correct is applied to both and the frames are
+    re-orthonormalised afterwards.  Iteration k keeps slices n < k, sets
+    slice k to its fine value and corrects slices k+1.. serially.  The
+    iteration stops when the relative increment (Eq. true_err, second form)
+    over all slice-boundary positions drops to `tol` or after `max_iter`.
+
+    Returns (states, history): states[n] = (X, D) at T_n for n = 0..n_slices,
+    history = list of relative increments per iteration.
+    """
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    dT_coarse = fine_dt * fine_steps / coarse_steps
+
+    def F(X, D):
+        Xn, Dn, _, _ = step(off, X, D, rod, fext, next_, eps, mu, fine_integ, fine_dt, fine_steps, include_elastic)
+        return Xn, Dn
+
+    def G(X, D):
+        Xn, Dn, _, _ = step(off, X, D, rod, fext, next_, eps, mu, EULER, dT_coarse, coarse_steps, include_elastic)
+        return Xn, Dn
+
+    # k = 0: serial coarse sweep (Eq. initial)
+    U = [(np.array(X0, dtype=np.float64).reshape(-1, 3), np.array(D0, dtype=np.float64).reshape(-1, 9))]
+    Gold = [None]
+    for n in range(1, n_slices + 1):
+        g = G(*U[n - 1])
+        Gold.append(g)
+        U.append(g)
+    history = []
+    for k in range(1, max_iter + 1):
+        Fv = [None] + [F(*U[n - 1]) for n in range(1, n_slices + 1)]  # Eq. intermediate (in parallel)
+        new = list(U[:k])
+        new.append(Fv[k])
+        Gnew = list(Gold)
+        for n in range(k + 1, n_slices + 1):  # Eq. serial_correct
+            g = G(*new[n - 1])
+            Gnew[n] = g
+            X = Fv[n][0] + g[0] - Gold[n][0]
+            D = reorthonormalize(Fv[n][1] + g[1] - Gold[n][1])
+            new.append((X, D))
+        inc = max(rel_err(new[n][0], U[n][0]) if n >= k else 0.0 for n in range(1, n_slices + 1))
+        history.append(inc)
+        U, Gold = new, Gnew
+        if inc <= tol:
+            break
+    return U, history

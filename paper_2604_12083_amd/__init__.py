@@ -117,6 +117,8 @@ _SIGS = {
                             ctypes.POINTER(_dbl)]),
     "mrs_tune_get": (_int, [_vp, _i64, _int, ctypes.POINTER(mrs_pair_config)]),
     "mrs_tune_set": (_int, [_vp, _i64, _int, ctypes.POINTER(mrs_pair_config)]),
+    "mrs_parareal": (_int, [_vp, ctypes.c_int32, _int, _dbl, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dbl,
+                            _int, _int, _vp, ctypes.POINTER(ctypes.c_int32)]),
     "mrs_profile_enable": (_int, [_vp, _int]),
     "mrs_profile_reset": (_int, [_vp]),
     "mrs_profile_query": (_int, [_vp, ctypes.c_char_p, ctypes.POINTER(_i64), ctypes.POINTER(_dbl)]),
@@ -384,3 +386,17 @@ def mrs_tune_get(ctx, n, prec=MRS_FP32C):
 def mrs_tune_set(ctx, n, prec, mode, targets_per_lane=1, chunks=0) -> None:
     c = mrs_pair_config(int(mode), int(targets_per_lane), int(chunks))
     _check(_lib.mrs_tune_set(ctx, int(n), int(prec), ctypes.byref(c)), ctx)
+
+
+# ---- Parareal -----------------------------------------------------------
+
+
+def mrs_parareal(ctx, ens, n_slices, fine_integ, fine_dt, fine_steps, coarse_steps, max_iter, tol=0.0,
+                 prec=MRS_FP64, include_elastic=True):
+    """Returns (iterations done, relative increment per iteration)."""
+    hist = np.zeros(max(int(max_iter), 1))
+    it = ctypes.c_int32()
+    _check(_lib.mrs_parareal(ens, int(n_slices), int(fine_integ), float(fine_dt), int(fine_steps), int(coarse_steps),
+                             int(max_iter), float(tol), int(prec), int(bool(include_elastic)), _ptr(hist),
+                             ctypes.byref(it)), ctx)
+    return int(it.value), hist[: it.value].copy()

@@ -96,6 +96,9 @@ hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, cons
 hipError_t launch_reduce(int epi, int stage, int scheme, double dt, const EnsDesc *d_desc,
                          const PointItem *d_items, int n_items, hipStream_t s);
 hipError_t launch_rotsqrt(int64_t count, const double *R, double *S, hipStream_t s);
+// Parareal correction (SoA states of N points): X = Xf + Xg - Xo, D = reorth(Df + Dg - Do).
+hipError_t launch_parareal_correct(int N, const double *Xf, const double *Df, const double *Xg, const double *Dg,
+                                  const double *Xo, const double *Do, double *X, double *D, hipStream_t s);
 
 // Pair-kernel modes.
 enum PairMode : int { PAIR_TILE = 0, PAIR_SPLIT = 1 };

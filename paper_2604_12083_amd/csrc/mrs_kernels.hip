@@ -743,6 +743,34 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int stage, int scheme, double
     }
 }
 
+// ------------------------------------------------------ Parareal correction
+
+// X = Xf + Xg - Xo and D = reorth(Df + Dg - Do) for every point (SoA state).
+__global__ __launch_bounds__(kBlock) void k_parareal_correct(int N, const double *__restrict__ Xf,
+                                                             const double *__restrict__ Df,
+                                                             const double *__restrict__ Xg,
+                                                             const double *__restrict__ Dg,
+                                                             const double *__restrict__ Xo,
+                                                             const double *__restrict__ Do,
+                                                             double *__restrict__ X, double *__restrict__ D) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N) return;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const size_t k = (size_t)c * N + i;
+        X[k] = Xf[k] + Xg[k] - Xo[k];
+    }
+    double d[9];
+#pragma unroll
+    for (int c = 0; c < 9; c++) {
+        const size_t k = (size_t)c * N + i;
+        d[c] = Df[k] + Dg[k] - Do[k];
+    }
+    reorthonormalize(d);
+#pragma unroll
+    for (int c = 0; c < 9; c++) D[(size_t)c * N + i] = d[c];
+}
+
 // --------------------------------------------------------- launch wrappers
 
 static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -788,6 +816,13 @@ hipError_t launch_reduce(int epi, int stage, int scheme, double dt, const EnsDes
         case EPI_RK_FINAL: hipLaunchKernelGGL(k_reduce<EPI_RK_FINAL>, g, b, 0, s, stage, scheme, dt, d_desc, d_items); break;
         default: hipLaunchKernelGGL(k_reduce<EPI_WRITE>, g, b, 0, s, stage, scheme, dt, d_desc, d_items); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_parareal_correct(int N, const double *Xf, const double *Df, const double *Xg, const double *Dg,
+                                  const double *Xo, const double *Do, double *X, double *D, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_parareal_correct, dim3(blocks_for(N)), dim3(kBlock), 0, s, N, Xf, Df, Xg, Dg, Xo, Do, X, D);
     return hipGetLastError();
 }
 

@@ -313,6 +313,58 @@ size_t ensemble_bytes(int64_t N, int n_fil, bool has_ext, int K64, int K32) {
 
 }  // namespace mrs
 
+namespace mrs {
+
+// Device arrays of a new ensemble (state, stage state, velocities, records).
+mrs_status ensemble_alloc(mrs_context *ctx, int32_t n_fil, const int32_t *offsets, double eps, double mu,
+                          const mrs_rod_params *rod, bool has_ext, std::unique_ptr<mrs_ensemble> &E) {
+    static std::atomic<uint64_t> next_uid{1};
+    const int64_t n = offsets[n_fil];
+    E = std::make_unique<mrs_ensemble>();
+    E->ctx = ctx;
+    E->uid = next_uid.fetch_add(1);
+    E->n_fil = n_fil;
+    E->N = n;
+    E->offsets.assign(offsets, offsets + n_fil + 1);
+    E->eps = eps;
+    E->mu = mu;
+    E->rod = *rod;
+    E->has_ext = has_ext;
+    const size_t v3 = (size_t)n * 3 * sizeof(double), v9 = 3 * v3;
+    bool ok = E->off.reserve((n_fil + 1) * sizeof(int32_t)) == hipSuccess && E->X.reserve(v3) == hipSuccess &&
+              E->D.reserve(v9) == hipSuccess && E->U.reserve(v3) == hipSuccess && E->W.reserve(v3) == hipSuccess &&
+              E->Xs.reserve(v3) == hipSuccess && E->Ds.reserve(v9) == hipSuccess &&
+              E->Ua.reserve(v3) == hipSuccess && E->Wa.reserve(v3) == hipSuccess &&
+              E->rec.reserve((size_t)n * sizeof(RecF64)) == hipSuccess;
+    if (ok && has_ext) ok = E->fext.reserve(v3) == hipSuccess && E->next.reserve(v3) == hipSuccess;
+    if (!ok) return fail(ctx, MRS_ENOMEM, "ensemble allocation (%lld points)", (long long)n);
+    if (hipMemcpy(E->off.p, offsets, (n_fil + 1) * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(E->U.p, 0, v3) != hipSuccess || hipMemset(E->W.p, 0, v3) != hipSuccess)
+        return fail(ctx, MRS_EDEVICE, "ensemble initialisation");
+    return MRS_OK;
+}
+
+// New ensemble with the same layout, parameters, loads and state (device copies).
+mrs_status ensemble_clone(mrs_ensemble *S, mrs_ensemble **out) {
+    mrs_context *ctx = S->ctx;
+    std::unique_ptr<mrs_ensemble> E;
+    mrs_status st = ensemble_alloc(ctx, S->n_fil, S->offsets.data(), S->eps, S->mu, &S->rod, S->has_ext, E);
+    if (st != MRS_OK) return st;
+    const size_t v3 = (size_t)S->N * 3 * sizeof(double), v9 = 3 * v3;
+    hipStream_t s = ctx->stream;
+    if (hipMemcpyAsync(E->X.p, S->X.p, v3, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(E->D.p, S->D.p, v9, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        (S->has_ext && (hipMemcpyAsync(E->fext.p, S->fext.p, v3, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                        hipMemcpyAsync(E->next.p, S->next.p, v3, hipMemcpyDeviceToDevice, s) != hipSuccess)) ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(ctx, MRS_EDEVICE, "ensemble clone");
+    ctx->ensembles.push_back(E.get());
+    *out = E.release();
+    return MRS_OK;
+}
+
+}  // namespace mrs
+
 // ------------------------------------------------------------------ C ABI
 
 #define CHECK_CTX(ctx)                                   \
@@ -642,27 +694,9 @@ mrs_status mrs_ensemble_create(mrs_context *ctx, int32_t n_fil, const int32_t *o
         (n_ext && !all_finite(n_ext, 3 * n)))
         return fail(ctx, MRS_EINVAL, "non-finite input");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    static std::atomic<uint64_t> next_uid{1};
-    auto E = std::make_unique<mrs_ensemble>();
-    E->ctx = ctx;
-    E->uid = next_uid.fetch_add(1);
-    E->n_fil = n_fil;
-    E->N = n;
-    E->offsets.assign(offsets, offsets + n_fil + 1);
-    E->eps = eps;
-    E->mu = mu;
-    E->rod = *rod;
-    E->has_ext = f_ext || n_ext;
-    const size_t v3 = (size_t)n * 3 * sizeof(double), v9 = 3 * v3;
-    bool ok = E->off.reserve((n_fil + 1) * sizeof(int32_t)) == hipSuccess && E->X.reserve(v3) == hipSuccess &&
-              E->D.reserve(v9) == hipSuccess && E->U.reserve(v3) == hipSuccess && E->W.reserve(v3) == hipSuccess &&
-              E->Xs.reserve(v3) == hipSuccess && E->Ds.reserve(v9) == hipSuccess &&
-              E->Ua.reserve(v3) == hipSuccess && E->Wa.reserve(v3) == hipSuccess &&
-              E->rec.reserve((size_t)n * sizeof(RecF64)) == hipSuccess;
-    if (ok && E->has_ext) ok = E->fext.reserve(v3) == hipSuccess && E->next.reserve(v3) == hipSuccess;
-    if (!ok) return fail(ctx, MRS_ENOMEM, "ensemble allocation (%lld points)", (long long)n);
-    HIPCHK(ctx, hipMemcpy(E->off.p, offsets, (n_fil + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
-    mrs_status st;
+    std::unique_ptr<mrs_ensemble> E;
+    mrs_status st = ensemble_alloc(ctx, n_fil, offsets, eps, mu, rod, f_ext || n_ext, E);
+    if (st != MRS_OK) return st;
     if ((st = put_soa(ctx, E->X, X, n, 3)) != MRS_OK) return st;
     if ((st = put_soa(ctx, E->D, D, n, 9)) != MRS_OK) return st;
     if (E->has_ext) {
@@ -670,8 +704,6 @@ mrs_status mrs_ensemble_create(mrs_context *ctx, int32_t n_fil, const int32_t *o
         if ((st = put_soa(ctx, E->fext, f_ext ? f_ext : z.data(), n, 3)) != MRS_OK) return st;
         if ((st = put_soa(ctx, E->next, n_ext ? n_ext : z.data(), n, 3)) != MRS_OK) return st;
     }
-    HIPCHK(ctx, hipMemset(E->U.p, 0, v3));
-    HIPCHK(ctx, hipMemset(E->W.p, 0, v3));
     ctx->ensembles.push_back(E.get());
     *out = E.release();
     return MRS_OK;

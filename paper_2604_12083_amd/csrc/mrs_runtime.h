@@ -119,6 +119,9 @@ void add_items(Plan &P, int e, int64_t N, int n_fil, const PairCfg &c);
 hipError_t finalize_plan(Plan &P);
 hipError_t run_pairs(mrs_context *ctx, Plan &P, hipStream_t s);
 hipEvent_t take_event(mrs_context *ctx);
+mrs_status ensemble_alloc(mrs_context *ctx, int32_t n_fil, const int32_t *offsets, double eps, double mu,
+                          const mrs_rod_params *rod, bool has_ext, std::unique_ptr<mrs_ensemble> &E);
+mrs_status ensemble_clone(mrs_ensemble *S, mrs_ensemble **out);
 const char *epi_name(int epi);
 
 // Launch `launch()` on stream s; with profiling on, bracket it with events.

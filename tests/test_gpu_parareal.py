@@ -1,0 +1,86 @@
+"""Parareal on one device against the oracle's Parareal and the serial fine
+solution (Sec. II.D)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import rod_of, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mrs():
+    import paper_2604_12083_amd as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mrs):
+    c = mrs.mrs_context_create(0)
+    yield c
+    mrs.mrs_context_destroy(c)
+
+
+def _ens(mrs, ctx, e):
+    return mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, e.rod()))
+
+
+def test_parareal_full_iterations_equal_serial_fine(mrs, ctx):
+    e = synth.filaments(4, 50, 2.0, 21)
+    ns, steps, dt = 5, 8, 1e-5
+    a, b = _ens(mrs, ctx, e), _ens(mrs, ctx, e)
+    try:
+        it, hist = mrs.mrs_parareal(ctx, a, ns, mrs.MRS_RK4, dt, steps, 1, ns, 0.0, mrs.MRS_FP64, True)
+        mrs.mrs_ensemble_step(ctx, b, mrs.MRS_RK4, dt, ns * steps, mrs.MRS_FP64, True)
+        Xa, Da, _, _ = mrs.mrs_ensemble_get(ctx, a)
+        Xb, Db, _, _ = mrs.mrs_ensemble_get(ctx, b)
+        say(f"parareal {it} iterations, increments {hist}")
+        assert it == ns
+        np.testing.assert_array_equal(Xa, Xb)
+        np.testing.assert_array_equal(Da, Db)
+    finally:
+        mrs.mrs_ensemble_destroy(a)
+        mrs.mrs_ensemble_destroy(b)
+
+
+@pytest.mark.parametrize("integ", ["RK2", "RK4"])
+def test_parareal_matches_oracle(mrs, ctx, integ):
+    e = synth.filaments(2, 16, 1.0, 9)
+    ns, steps, dt, iters = 4, 10, 2e-4, 3
+    h = _ens(mrs, ctx, e)
+    try:
+        it, hist = mrs.mrs_parareal(ctx, h, ns, getattr(mrs, "MRS_" + integ), dt, steps, 1, iters, 0.0,
+                                    mrs.MRS_FP64, True)
+        X, D, _, _ = mrs.mrs_ensemble_get(ctx, h)
+    finally:
+        mrs.mrs_ensemble_destroy(h)
+    U, ohist = oracle.parareal(e.offsets, e.X, e.D, e.rod(), e.f, e.n, e.eps, e.mu, ns, getattr(oracle, integ), dt,
+                               steps, 1, iters)
+    say(f"{integ}: gpu increments {hist} oracle {ohist}")
+    assert it == iters
+    np.testing.assert_allclose(hist, ohist, rtol=1e-6)
+    disp = np.linalg.norm(U[ns][0] - e.X, axis=1)
+    assert np.max(np.linalg.norm(X - U[ns][0], axis=1) / disp) <= 1e-9
+    assert np.abs(D - U[ns][1]).max() <= 1e-9
+
+
+def test_parareal_stops_at_tolerance_and_fp32c(mrs, ctx):
+    base, slices = synth.config3(n_slices=1)
+    e = slices[0]
+    h = _ens(mrs, ctx, e)
+    try:
+        it, hist = mrs.mrs_parareal(ctx, h, 8, mrs.MRS_RK4, 1e-5, 20, 2, 8, 1e-9, mrs.MRS_FP32C, True)
+        say(f"config3 slice, 8 slices: {it} iterations, increments {hist}")
+        assert it <= 8 and (hist[-1] <= 1e-9 or it == 8)
+        assert np.all(np.diff(hist) < 0)
+    finally:
+        mrs.mrs_ensemble_destroy(h)
+    with pytest.raises(mrs.MrsError):
+        h = _ens(mrs, ctx, e)
+        try:
+            mrs.mrs_parareal(ctx, h, 2, mrs.MRS_RK4, 1e-5, 4, 1, 3)  # max_iter > n_slices
+        finally:
+            mrs.mrs_ensemble_destroy(h)
