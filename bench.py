@@ -36,6 +36,8 @@ def log(*a):
 def workload(name):
     import synth
 
+    if name == "config1":
+        return synth.config1(), "1 filament x 64 points, eps = 1.5/64; dt = 1e-4 forward-Euler steps"
     if name == "config2":
         return synth.config2(), "100 filaments x 128 points (12,800 points) in [0,10]^3, eps = 1.5/128"
     if name == "config5":
@@ -68,7 +70,8 @@ def measure(mrs, ctx, e, prec, steps, warmup, dt):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         mrs.mrs_profile_enable(ctx, False)
-        kname = "pairs_tile_f32c" if prec == mrs.MRS_FP32C else "pairs_tile_f64"
+        kname = ("pairs_tile_f32c" if prec == mrs.MRS_FP32C else "pairs_tile_f64") if e.N > 1024 else \
+            ("pairs_split_f32c" if prec == mrs.MRS_FP32C else "pairs_split_f64")
         n_k, ms_k = mrs.mrs_profile_query(ctx, kname)
         kernels = {}
         for k in ("rod_forces", "pairs_tile", "pairs_split", "reduce_euler"):
@@ -177,6 +180,42 @@ def bench_config3(mrs, ctx, steps, args):
             "plain_pairs_per_s": pairs / tp, "speedup": tp / tb, "identical_results": bool(same)}
 
 
+def bench_parareal(mrs, ctx, prec, tol, coarse_steps):
+    """Parareal on one GPU for the config-3 base ensemble: 16 slices of 200 RK4
+    steps at dt = 1e-5 (fine), forward Euler with `coarse_steps` steps per slice
+    (coarse), against the serial fine solve of the same 3,200 steps."""
+    import synth
+
+    base, _ = synth.config3(n_slices=1)
+    rod = mrs.rod_params(*(getattr(base.rod(), k) for k in ("a", "b", "omega0", "ds")))
+    mk = lambda: mrs.mrs_ensemble_create(ctx, base.offsets, base.X, base.D, base.f, base.n, base.eps, base.mu, rod)
+    a, b = mk(), mk()
+    try:
+        # warm both paths (plans, graphs) on throwaway copies
+        w = mk()
+        mrs.mrs_parareal(ctx, w, 16, mrs.MRS_RK4, 1e-5, 200, coarse_steps, 1, 0.0, prec, True)
+        mrs.mrs_ensemble_step(ctx, w, mrs.MRS_RK4, 1e-5, 10, prec, True)
+        mrs.mrs_ensemble_destroy(w)
+        t0 = time.perf_counter()
+        it, hist = mrs.mrs_parareal(ctx, a, 16, mrs.MRS_RK4, 1e-5, 200, coarse_steps, 16, tol, prec, True)
+        tpar = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        mrs.mrs_ensemble_step(ctx, b, mrs.MRS_RK4, 1e-5, 16 * 200, prec, True)
+        tser = time.perf_counter() - t0
+        Xa = mrs.mrs_ensemble_get(ctx, a)[0]
+        Xb = mrs.mrs_ensemble_get(ctx, b)[0]
+        disp = np.linalg.norm(Xb - base.X, axis=1)
+        eta = float(np.max(np.linalg.norm(Xa - Xb, axis=1) / np.linalg.norm(Xb, axis=1)))
+        eta_disp = float(np.max(np.linalg.norm(Xa - Xb, axis=1) / disp))
+    finally:
+        mrs.mrs_ensemble_destroy(a)
+        mrs.mrs_ensemble_destroy(b)
+    return {"slices": 16, "fine": "RK4 x 200 at dt=1e-5 per slice", "coarse": f"Euler x {coarse_steps} per slice",
+            "iterations": it, "increments": [float(x) for x in hist], "tol": tol, "parareal_s": tpar,
+            "serial_fine_s": tser, "speedup_vs_serial": tser / tpar,
+            "eta_vs_serial_fine": eta, "error_relative_to_displacement": eta_disp}
+
+
 def bench_config4(mrs, ctx, n_req, rates, slots, budget, tick_pairs=0):
     """Serving: the fixed request sequence at Poisson arrival rates; continuous
     batching (many slots) vs one request at a time (one slot)."""
@@ -232,7 +271,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="config2",
-                    choices=["config2", "config5", "config3", "config4", "copy"])
+                    choices=["config1", "config2", "config5", "config3", "config4", "parareal", "copy"])
     ap.add_argument("--requests", type=int, default=32, help="config4: prefix of the request sequence")
     ap.add_argument("--rates", default="10,100,1000", help="config4: Poisson arrival rates (req/s)")
     ap.add_argument("--slots", type=int, default=64)
@@ -271,10 +310,19 @@ def main():
                           "config": {"workload": "copy of 256 MiB float64", "bytes_read": nbytes,
                                      "bytes_written": nbytes}}), flush=True)
         return
-    if args.workload in ("config3", "config4"):
+    if args.workload in ("config3", "config4", "parareal"):
         ctx = mrs.mrs_context_create(0)
         try:
-            if args.workload == "config3":
+            if args.workload == "parareal":
+                r = {tag: bench_parareal(mrs, ctx, p, tol, 10) for tag, p, tol in
+                     (("fp64", mrs.MRS_FP64, 1e-10), ("fp32c", mrs.MRS_FP32C, 1e-6))}
+                line = {"metric": "Parareal wall time on one GPU vs serial fine (config-3 base ensemble)",
+                        "value": r["fp32c"]["speedup_vs_serial"], "unit": "x", "n_gpus": 1, "steps": 3200,
+                        "warmup": 1, "ms_per_step": 1e3 * r["fp32c"]["parareal_s"] / 3200,
+                        "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f32c",
+                        "data": "synthetic",
+                        "config": {"workload": "parareal: 32 filaments x 100 points, 16 slices"}, "parareal": r}
+            elif args.workload == "config3":
                 r = bench_config3(mrs, ctx, args.steps, args)
                 line = {"metric": METRIC, "value": r["batched_pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
                         "steps": args.steps, "warmup": args.warmup,

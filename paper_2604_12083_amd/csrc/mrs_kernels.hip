@@ -73,14 +73,16 @@ __device__ __forceinline__ float sep_f32(float thx, float thy, float thz, float 
 }
 
 // Contribution of one far source to p[0..5] = (8 pi mu U, 8 pi mu eps Omega)
-// of one target, in units of eps; a near pair adds exactly zero.  Returns R^2.
+// of one target, in units of eps.  With MASK a near pair adds exactly zero;
+// without it the caller guarantees that no pair is near.  Returns R^2.
+template <bool MASK>
 __device__ __forceinline__ float pair_f32(float thx, float thy, float thz, float tlx, float tly,
                                           float tlz, const float4 A, const float4 B,
                                           const float4 C, float *p) {
     float rx, ry, rz;
     const float R2 = sep_f32(thx, thy, thz, tlx, tly, tlz, A, B, rx, ry, rz);
     const float fx = A.w, fy = B.w, fz = C.x, nx = C.y, ny = C.z, nz = C.w;
-    const float q = R2 < kNearR2 ? 0.0f : rsq_f32(R2);
+    const float q = (MASK && R2 < kNearR2) ? 0.0f : rsq_f32(R2);
     const float q2 = q * q, q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
     const float h1 = q + q3;
     const float t = 1.5f * q5;
@@ -398,26 +400,63 @@ __global__ __launch_bounds__(kBlock) void k_rod_forces(int prec, int stage_state
 
 // ----------------------------------------------------------------- pairs
 
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Squared distance between the boxes [lo0, hi0] and [lo1, hi1] (0 if they overlap).
+__device__ __forceinline__ float box_gap2(const float *lo0, const float *hi0, const float *lo1, const float *hi1) {
+    float d2 = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const float g = fmaxf(0.0f, fmaxf(lo0[c] - hi1[c], lo1[c] - hi0[c]));
+        d2 = fmaf(g, g, d2);
+    }
+    return d2;
+}
+
+// A wave whose target box is farther than this (squared, in units of eps)
+// from a source block's box has no near pair in it: 17 > (4 + margin)^2 for
+// the hi-part rounding of the boxes (at most 2^-24 of 2^14 per coordinate).
+constexpr float kFarBoxGap2 = 17.0f;
+
+// Blocks per CU the register budget must allow: 5 with one target per lane
+// (<= 102 VGPRs), 3 with two (<= 170).
 template <int T>
-__global__ __launch_bounds__(kBlock) void k_pairs_tile_f32(const EnsDesc *__restrict__ desc,
+__global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const EnsDesc *__restrict__ desc,
                                                            const PairItem *__restrict__ items) {
     __shared__ float4 sA[kSrcTile], sB[kSrcTile], sC[kSrcTile];
     __shared__ double sNear[6][T][kBlock];  // FP64 near-pair sums, one slot per lane and target
+    __shared__ float sBox[kSrcTile / kKahanBlock][6];  // hi-part box of every 64-source block
+    static_assert(kSrcTile / kKahanBlock == kBlock / 64, "one source block per wave");
     const PairItem it = items[blockIdx.x];
     const EnsDesc &E = desc[it.ens];
     const RecF32 *__restrict__ rec = reinterpret_cast<const RecF32 *>(E.rec);
     const int tid = threadIdx.x;
     float thx[T], thy[T], thz[T], tlx[T], tly[T], tlz[T];
     float s[T][6], c[T][6];
+    float tlo[3] = {INFINITY, INFINITY, INFINITY}, thi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
     for (int t = 0; t < T; t++) {
         const int li = min(tid + t * kBlock, it.ntgt - 1);
         const RecF32 r = rec[it.tgt0 + li];
         thx[t] = r.a.x; thy[t] = r.a.y; thz[t] = r.a.z;
         tlx[t] = r.b.x; tly[t] = r.b.y; tlz[t] = r.b.z;
+        tlo[0] = fminf(tlo[0], thx[t]); tlo[1] = fminf(tlo[1], thy[t]); tlo[2] = fminf(tlo[2], thz[t]);
+        thi[0] = fmaxf(thi[0], thx[t]); thi[1] = fmaxf(thi[1], thy[t]); thi[2] = fmaxf(thi[2], thz[t]);
 #pragma unroll
         for (int k = 0; k < 6; k++) { s[t][k] = 0.0f; c[t][k] = 0.0f; sNear[k][t][tid] = 0.0; }
     }
+#pragma unroll
+    for (int k = 0; k < 3; k++) { tlo[k] = wave_min(tlo[k]); thi[k] = wave_max(thi[k]); }
     for (int base = 0; base < it.nsrc; base += kSrcTile) {
         __syncthreads();
         const int j = base + tid;
@@ -427,6 +466,18 @@ __global__ __launch_bounds__(kBlock) void k_pairs_tile_f32(const EnsDesc *__rest
             a = r.a; b = r.b; cc = r.c;
         }
         sA[tid] = a; sB[tid] = b; sC[tid] = cc;
+        {
+            // this wave staged source block tid / 64: reduce its box (padding excluded)
+            const bool real = j < it.nsrc;
+            const float bx0 = wave_min(real ? a.x : INFINITY), by0 = wave_min(real ? a.y : INFINITY),
+                        bz0 = wave_min(real ? a.z : INFINITY);
+            const float bx1 = wave_max(real ? a.x : -INFINITY), by1 = wave_max(real ? a.y : -INFINITY),
+                        bz1 = wave_max(real ? a.z : -INFINITY);
+            if ((tid & 63) == 0) {
+                float *bx = sBox[tid >> 6];
+                bx[0] = bx0; bx[1] = by0; bx[2] = bz0; bx[3] = bx1; bx[4] = by1; bx[5] = bz1;
+            }
+        }
         __syncthreads();
         const int cnt = min(kSrcTile, it.nsrc - base);
         for (int sb = 0; sb < cnt; sb += kKahanBlock) {
@@ -436,12 +487,24 @@ __global__ __launch_bounds__(kBlock) void k_pairs_tile_f32(const EnsDesc *__rest
             for (int t = 0; t < T; t++)
 #pragma unroll
                 for (int k = 0; k < 6; k++) p[t][k] = 0.0f;
+            const float *bx = sBox[sb / kKahanBlock];
+            if (box_gap2(tlo, thi, bx, bx + 3) > kFarBoxGap2) {
+                // wave-uniform: no source of this block is near any target of the wave
 #pragma unroll 2
-            for (int jj = sb; jj < sb + kKahanBlock; jj++) {
-                const float4 A = sA[jj], B = sB[jj], C = sC[jj];
+                for (int jj = sb; jj < sb + kKahanBlock; jj++) {
+                    const float4 A = sA[jj], B = sB[jj], C = sC[jj];
 #pragma unroll
-                for (int t = 0; t < T; t++)
-                    rmin = fminf(rmin, pair_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], A, B, C, p[t]));
+                    for (int t = 0; t < T; t++)
+                        (void)pair_f32<false>(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], A, B, C, p[t]);
+                }
+            } else {
+#pragma unroll 2
+                for (int jj = sb; jj < sb + kKahanBlock; jj++) {
+                    const float4 A = sA[jj], B = sB[jj], C = sC[jj];
+#pragma unroll
+                    for (int t = 0; t < T; t++)
+                        rmin = fminf(rmin, pair_f32<true>(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], A, B, C, p[t]));
+                }
             }
 #pragma unroll
             for (int t = 0; t < T; t++)
@@ -573,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
                 const RecF32 r = rec[it.src0 + j];
 #pragma unroll
                 for (int t = 0; t < TW; t++)
-                    rmin = fminf(rmin, pair_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a, r.b, r.c, p[t]));
+                    rmin = fminf(rmin, pair_f32<true>(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a, r.b, r.c, p[t]));
             }
 #pragma unroll
             for (int t = 0; t < TW; t++)

@@ -149,3 +149,27 @@ def test_autotune_and_every_config_parity(mrs, prec):
         _check(mrs, c, e.X, e.f, e.n, e.eps, e.mu, prec, "tuned")
     finally:
         mrs.mrs_context_destroy(c)
+
+
+@pytest.mark.parametrize("tpl", [1, 2])
+def test_fp32c_near_pairs_across_filaments(mrs, tpl):
+    """Filaments crossing through one small region: near pairs (r < 4 eps)
+    between points far apart in index order must still be taken in FP64."""
+    c = mrs.mrs_context_create(0)
+    try:
+        rng = np.random.default_rng(31)
+        F, M = 24, 128
+        ds = 1.0 / M
+        eps = 1.5 * ds
+        X = []
+        for _ in range(F):
+            d = rng.normal(size=3)
+            d /= np.linalg.norm(d)
+            s = (np.arange(M) - M / 2) * ds
+            X.append(np.array([5.0, 5.0, 5.0]) + rng.normal(scale=0.5 * eps, size=3) + s[:, None] * d[None, :])
+        X = np.concatenate(X)
+        f, n = rng.normal(size=X.shape), rng.normal(size=X.shape)
+        mrs.mrs_tune_set(c, len(X), 1, 0, tpl, 0)
+        _check(mrs, c, X, f, n, eps, 1.0, 1, f"crossing-tpl{tpl}")
+    finally:
+        mrs.mrs_context_destroy(c)
