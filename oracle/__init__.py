@@ -291,7 +291,8 @@ def parareal(offsets, X0, D0, rod, fext, next_, eps, mu, n_slices, fine_integ, f
             X = Fv[n][0] + g[0] - Gold[n][0]
             D = reorthonormalize(Fv[n][1] + g[1] - Gold[n][1])
             new.append((X, D))
-        inc = max(rel_err(new[n][0], U[n][0]) if n >= k else 0.0 for n in range(1, n_slices + 1))
+        # Eq. true_err, second form: |x^k - x^{k-1}| / |x^k|
+        inc = max(rel_err(U[n][0], new[n][0]) if n >= k else 0.0 for n in range(1, n_slices + 1))
         history.append(inc)
         U, Gold = new, Gnew
         if inc <= tol:
