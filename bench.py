@@ -136,7 +136,7 @@ def cpu_baseline(mrs, ctx, e, prec_list):
         g, m = oracle.rod_forces(e.offsets, e.X, e.D, e.rod(), e.f, e.n)
         Uo, Wo = oracle.mrs_field(e.X[idx], e.X, g, m, e.eps, e.mu)
         reps += 1
-        if time.perf_counter() - t0 > 10.0 or reps >= 50:
+        if time.perf_counter() - t0 > 10.0 or reps >= 5000:
             break
     dt = time.perf_counter() - t0
     pairs = reps * n_t * e.N
@@ -158,7 +158,34 @@ def cpu_baseline(mrs, ctx, e, prec_list):
         "kind": "oracle",
         "sample": f"rod forces of all {e.N} points + MRS sum for {n_t} seeded targets x {e.N} sources, "
                   f"repeated {reps}x ({dt:.1f} s)",
+        "cpu": cpu_model(),
     }, errs
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+# Algorithmic bytes per point of the frame update in FP64: the rod stage reads
+# X, D (96 B) and writes the point loads (48 B); the Euler update reads X, D,
+# U, Omega (144 B) and writes X, D (96 B).
+ROD_BYTES_PER_POINT = 144
+EULER_BYTES_PER_POINT = 240
+
+
+def frame_update_gbps(n_points, kernels):
+    out = {}
+    for name, nbytes in (("rod_forces", ROD_BYTES_PER_POINT), ("reduce_euler", EULER_BYTES_PER_POINT)):
+        if name in kernels and kernels[name]["avg_us"] > 0:
+            out[name] = round(nbytes * n_points / (kernels[name]["avg_us"] * 1e-6) / 1e9, 1)
+    return out
 
 
 def roofline(pairs_per_launch, avg_s, peak_tflops, traffic=None):
@@ -401,6 +428,7 @@ def main():
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
             "roofline": roofline(pairs_step, r["kernel_avg_s"], peak, measured_traffic(args.workload, tag)),
             "kernels_avg_us": {k: round(v["avg_us"], 2) for k, v in r["kernels"].items()},
+            "frame_update_GBps": frame_update_gbps(e.N, r["kernels"]),
         }
 
     s32 = summary(res["fp32c"], PEAK_FP32_TFLOPS, "fp32c")
@@ -424,6 +452,7 @@ def main():
         "latency_ms": s32["latency_ms"],
         "ms_per_step_graph": s32["ms_per_step_graph"],
         "kernels_avg_us": s32["kernels_avg_us"],
+        "frame_update_GBps": s32["frame_update_GBps"],
         "roofline": s32["roofline"],
         "fp64": s64,
         "cpu_baseline": cpu,

@@ -60,28 +60,26 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
 // hi/lo difference) and every other pair in FP32.
 constexpr float kNearR2 = 17.0f;
 
-// R^2 = rho^2 + 1 of a target (th + tl) and a source record, in FP32.  Both
-// the hot loop and the near-pair rescan use this one function, so they take
-// the same near/far decision bit for bit.
+// R^2 = rho^2 + 1 of a target (th + tl) and a source (sh + sl), in FP32.
+// Both the hot loop and the near-pair rescan use this one function, so they
+// take the same near/far decision bit for bit.
 __device__ __forceinline__ float sep_f32(float thx, float thy, float thz, float tlx, float tly,
-                                         float tlz, const float4 A, const float4 B, float &rx,
-                                         float &ry, float &rz) {
-    rx = (thx - A.x) + (tlx - B.x);
-    ry = (thy - A.y) + (tly - B.y);
-    rz = (thz - A.z) + (tlz - B.z);
+                                         float tlz, float shx, float shy, float shz, float slx,
+                                         float sly, float slz, float &rx, float &ry, float &rz) {
+    rx = (thx - shx) + (tlx - slx);
+    ry = (thy - shy) + (tly - sly);
+    rz = (thz - shz) + (tlz - slz);
     return fmaf(rz, rz, fmaf(ry, ry, fmaf(rx, rx, 1.0f)));
 }
 
-// Contribution of one far source to p[0..5] = (8 pi mu U, 8 pi mu eps Omega)
-// of one target, in units of eps.  With MASK a near pair adds exactly zero;
-// without it the caller guarantees that no pair is near.  Returns R^2.
+// Contribution of one source at separation r (R2 = |r|^2 + 1) to p[0..5] =
+// (8 pi mu U, 8 pi mu eps Omega) of one target, in units of eps.  With MASK a
+// near pair adds exactly zero; without it the caller guarantees that no pair
+// is near.
 template <bool MASK>
-__device__ __forceinline__ float pair_f32(float thx, float thy, float thz, float tlx, float tly,
-                                          float tlz, const float4 A, const float4 B,
-                                          const float4 C, float *p) {
-    float rx, ry, rz;
-    const float R2 = sep_f32(thx, thy, thz, tlx, tly, tlz, A, B, rx, ry, rz);
-    const float fx = A.w, fy = B.w, fz = C.x, nx = C.y, ny = C.z, nz = C.w;
+__device__ __forceinline__ void pair_core_f32(float rx, float ry, float rz, float R2, float fx,
+                                              float fy, float fz, float nx, float ny, float nz,
+                                              float *p) {
     const float q = (MASK && R2 < kNearR2) ? 0.0f : rsq_f32(R2);
     const float q2 = q * q, q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
     const float h1 = q + q3;
@@ -101,6 +99,16 @@ __device__ __forceinline__ float pair_f32(float thx, float thy, float thz, float
     p[3] = fmaf(-fz, gy, fmaf(fy, gz, fmaf(b, rx, fmaf(h4, nx, p[3]))));
     p[4] = fmaf(-fx, gz, fmaf(fz, gx, fmaf(b, ry, fmaf(h4, ny, p[4]))));
     p[5] = fmaf(-fy, gx, fmaf(fx, gy, fmaf(b, rz, fmaf(h4, nz, p[5]))));
+}
+
+// The same for a source record (a = hi + fx, b = lo + fy, c = fz, n); returns R^2.
+template <bool MASK>
+__device__ __forceinline__ float pair_f32(float thx, float thy, float thz, float tlx, float tly,
+                                          float tlz, const float4 A, const float4 B,
+                                          const float4 C, float *p) {
+    float rx, ry, rz;
+    const float R2 = sep_f32(thx, thy, thz, tlx, tly, tlz, A.x, A.y, A.z, B.x, B.y, B.z, rx, ry, rz);
+    pair_core_f32<MASK>(rx, ry, rz, R2, A.w, B.w, C.x, C.y, C.z, C.w, p);
     return R2;
 }
 
@@ -138,15 +146,16 @@ __device__ __forceinline__ void pair_f64(double tx, double ty, double tz, double
     pair_f64_r(tx - x, ty - y, tz - z, fx, fy, fz, nx, ny, nz, e2, c375e2, p);
 }
 
-// FP64 evaluation of a near pair from the FP32 record: the hi and lo
+// FP64 evaluation of a near pair from FP32 hi/lo positions: the hi and lo
 // differences are exact in FP64, the loads are the record's FP32 values.
 __device__ __forceinline__ void near_pair_f64(float thx, float thy, float thz, float tlx, float tly,
-                                              float tlz, const float4 A, const float4 B,
-                                              const float4 C, double *p) {
-    const double rx = ((double)thx - (double)A.x) + ((double)tlx - (double)B.x);
-    const double ry = ((double)thy - (double)A.y) + ((double)tly - (double)B.y);
-    const double rz = ((double)thz - (double)A.z) + ((double)tlz - (double)B.z);
-    pair_f64_r(rx, ry, rz, A.w, B.w, C.x, C.y, C.z, C.w, 1.0, 3.75, p);
+                                              float tlz, float shx, float shy, float shz, float slx,
+                                              float sly, float slz, float fx, float fy, float fz,
+                                              float nx, float ny, float nz, double *p) {
+    const double rx = ((double)thx - (double)shx) + ((double)tlx - (double)slx);
+    const double ry = ((double)thy - (double)shy) + ((double)tly - (double)sly);
+    const double rz = ((double)thz - (double)shz) + ((double)tlz - (double)slz);
+    pair_f64_r(rx, ry, rz, fx, fy, fz, nx, ny, nz, 1.0, 3.75, p);
 }
 
 __device__ __forceinline__ RecF32 make_rec_f32(double x, double y, double z, double fx, double fy,
@@ -428,14 +437,26 @@ __device__ __forceinline__ float box_gap2(const float *lo0, const float *hi0, co
 // the hi-part rounding of the boxes (at most 2^-24 of 2^14 per coordinate).
 constexpr float kFarBoxGap2 = 17.0f;
 
+// Anchored far blocks.  Relative to the centre c of a 64-source block's box,
+// a source sits at w = (sh - c) + sl and a target at u = (th - c) + tl, both
+// rounded once to FP32, and r = u - w costs 3 instead of 9 operations.  Each
+// rounding is at most 2^-24 of |u| <= |r| + |w| or of |w|; with the gap
+// between the boxes at least 4 times the block's half-diagonal, |w| <= |r|/4
+// and r keeps a relative error below 2^-21, against 2^-23 for the exact
+// hi/lo difference of the other paths.
+constexpr float kAnchorGapRatio2 = 16.0f;
+
 // Blocks per CU the register budget must allow: 5 with one target per lane
 // (<= 102 VGPRs), 3 with two (<= 170).
 template <int T>
 __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const EnsDesc *__restrict__ desc,
                                                            const PairItem *__restrict__ items) {
-    __shared__ float4 sA[kSrcTile], sB[kSrcTile], sC[kSrcTile];
+    // staged sources: sW = (w, fx) with w the anchored position, sF = (fy, fz,
+    // nx, ny), sN = (nz, lo), sH = (hi, 0)
+    __shared__ float4 sW[kSrcTile], sF[kSrcTile], sN[kSrcTile], sH[kSrcTile];
     __shared__ double sNear[6][T][kBlock];  // FP64 near-pair sums, one slot per lane and target
-    __shared__ float sBox[kSrcTile / kKahanBlock][6];  // hi-part box of every 64-source block
+    // per 64-source block: hi-part box lo, hi, anchor c, squared half-diagonal
+    __shared__ float sBox[kSrcTile / kKahanBlock][10];
     static_assert(kSrcTile / kKahanBlock == kBlock / 64, "one source block per wave");
     const PairItem it = items[blockIdx.x];
     const EnsDesc &E = desc[it.ens];
@@ -460,23 +481,34 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
     for (int base = 0; base < it.nsrc; base += kSrcTile) {
         __syncthreads();
         const int j = base + tid;
+        const bool real = j < it.nsrc;
         float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, cc = a;
-        if (j < it.nsrc) {
+        if (real) {
             const RecF32 r = rec[it.src0 + j];
             a = r.a; b = r.b; cc = r.c;
         }
-        sA[tid] = a; sB[tid] = b; sC[tid] = cc;
-        {
-            // this wave staged source block tid / 64: reduce its box (padding excluded)
-            const bool real = j < it.nsrc;
-            const float bx0 = wave_min(real ? a.x : INFINITY), by0 = wave_min(real ? a.y : INFINITY),
-                        bz0 = wave_min(real ? a.z : INFINITY);
-            const float bx1 = wave_max(real ? a.x : -INFINITY), by1 = wave_max(real ? a.y : -INFINITY),
-                        bz1 = wave_max(real ? a.z : -INFINITY);
-            if ((tid & 63) == 0) {
-                float *bx = sBox[tid >> 6];
-                bx[0] = bx0; bx[1] = by0; bx[2] = bz0; bx[3] = bx1; bx[4] = by1; bx[5] = bz1;
-            }
+        // this wave stages source block tid / 64: its box (padding excluded) and anchor
+        float lo[3], hi[3], ctr[3], hd2 = 0.0f;
+        lo[0] = wave_min(real ? a.x : INFINITY); lo[1] = wave_min(real ? a.y : INFINITY);
+        lo[2] = wave_min(real ? a.z : INFINITY);
+        hi[0] = wave_max(real ? a.x : -INFINITY); hi[1] = wave_max(real ? a.y : -INFINITY);
+        hi[2] = wave_max(real ? a.z : -INFINITY);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            // a block without a real source (never evaluated) gets a finite anchor
+            ctr[k] = lo[k] <= hi[k] ? 0.5f * (lo[k] + hi[k]) : 0.0f;
+            const float h = lo[k] <= hi[k] ? 0.5f * (hi[k] - lo[k]) : 0.0f;
+            hd2 = fmaf(h, h, hd2);
+        }
+        sW[tid] = make_float4((a.x - ctr[0]) + b.x, (a.y - ctr[1]) + b.y, (a.z - ctr[2]) + b.z, a.w);
+        sF[tid] = make_float4(b.w, cc.x, cc.y, cc.z);
+        sN[tid] = make_float4(cc.w, b.x, b.y, b.z);
+        sH[tid] = make_float4(a.x, a.y, a.z, 0.0f);
+        if ((tid & 63) == 0) {
+            float *bx = sBox[tid >> 6];
+#pragma unroll
+            for (int k = 0; k < 3; k++) { bx[k] = lo[k]; bx[3 + k] = hi[k]; bx[6 + k] = ctr[k]; }
+            bx[9] = hd2;
         }
         __syncthreads();
         const int cnt = min(kSrcTile, it.nsrc - base);
@@ -488,22 +520,51 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
 #pragma unroll
                 for (int k = 0; k < 6; k++) p[t][k] = 0.0f;
             const float *bx = sBox[sb / kKahanBlock];
-            if (box_gap2(tlo, thi, bx, bx + 3) > kFarBoxGap2) {
-                // wave-uniform: no source of this block is near any target of the wave
+            const float gap2 = box_gap2(tlo, thi, bx, bx + 3);
+            if (gap2 > kFarBoxGap2 && gap2 > kAnchorGapRatio2 * bx[9]) {
+                // wave-uniform: no near pair, separation from the block's anchor
+                float ux[T], uy[T], uz[T];
+#pragma unroll
+                for (int t = 0; t < T; t++) {
+                    ux[t] = (thx[t] - bx[6]) + tlx[t];
+                    uy[t] = (thy[t] - bx[7]) + tly[t];
+                    uz[t] = (thz[t] - bx[8]) + tlz[t];
+                }
 #pragma unroll 2
                 for (int jj = sb; jj < sb + kKahanBlock; jj++) {
-                    const float4 A = sA[jj], B = sB[jj], C = sC[jj];
+                    const float4 W = sW[jj], F = sF[jj], Nn = sN[jj];
 #pragma unroll
-                    for (int t = 0; t < T; t++)
-                        (void)pair_f32<false>(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], A, B, C, p[t]);
+                    for (int t = 0; t < T; t++) {
+                        const float rx = ux[t] - W.x, ry = uy[t] - W.y, rz = uz[t] - W.z;
+                        const float R2 = fmaf(rz, rz, fmaf(ry, ry, fmaf(rx, rx, 1.0f)));
+                        pair_core_f32<false>(rx, ry, rz, R2, W.w, F.x, F.y, F.z, F.w, Nn.x, p[t]);
+                    }
+                }
+            } else if (gap2 > kFarBoxGap2) {
+                // wave-uniform: no near pair, exact hi/lo separation
+#pragma unroll 2
+                for (int jj = sb; jj < sb + kKahanBlock; jj++) {
+                    const float4 W = sW[jj], F = sF[jj], Nn = sN[jj], H = sH[jj];
+#pragma unroll
+                    for (int t = 0; t < T; t++) {
+                        float rx, ry, rz;
+                        const float R2 = sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], H.x, H.y, H.z,
+                                                 Nn.y, Nn.z, Nn.w, rx, ry, rz);
+                        pair_core_f32<false>(rx, ry, rz, R2, W.w, F.x, F.y, F.z, F.w, Nn.x, p[t]);
+                    }
                 }
             } else {
 #pragma unroll 2
                 for (int jj = sb; jj < sb + kKahanBlock; jj++) {
-                    const float4 A = sA[jj], B = sB[jj], C = sC[jj];
+                    const float4 W = sW[jj], F = sF[jj], Nn = sN[jj], H = sH[jj];
 #pragma unroll
-                    for (int t = 0; t < T; t++)
-                        rmin = fminf(rmin, pair_f32<true>(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], A, B, C, p[t]));
+                    for (int t = 0; t < T; t++) {
+                        float rx, ry, rz;
+                        const float R2 = sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], H.x, H.y, H.z,
+                                                 Nn.y, Nn.z, Nn.w, rx, ry, rz);
+                        pair_core_f32<true>(rx, ry, rz, R2, W.w, F.x, F.y, F.z, F.w, Nn.x, p[t]);
+                        rmin = fminf(rmin, R2);
+                    }
                 }
             }
 #pragma unroll
@@ -513,15 +574,17 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
             if (rmin < kNearR2) {
                 // this lane met a near pair in the sub-block: evaluate those in FP64
                 for (int jj = sb; jj < sb + kKahanBlock; jj++) {
-                    const float4 A = sA[jj], B = sB[jj], C = sC[jj];
+                    const float4 W = sW[jj], F = sF[jj], Nn = sN[jj], H = sH[jj];
 #pragma unroll
                     for (int t = 0; t < T; t++) {
                         float rx, ry, rz;
-                        if (sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], A, B, rx, ry, rz) < kNearR2) {
+                        if (sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], H.x, H.y, H.z, Nn.y, Nn.z,
+                                    Nn.w, rx, ry, rz) < kNearR2) {
                             double pn[6];
 #pragma unroll
                             for (int k = 0; k < 6; k++) pn[k] = sNear[k][t][tid];
-                            near_pair_f64(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], A, B, C, pn);
+                            near_pair_f64(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], H.x, H.y, H.z, Nn.y,
+                                          Nn.z, Nn.w, W.w, F.x, F.y, F.z, F.w, Nn.x, pn);
 #pragma unroll
                             for (int k = 0; k < 6; k++) sNear[k][t][tid] = pn[k];
                         }
@@ -648,8 +711,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
 #pragma unroll
                     for (int t = 0; t < TW; t++) {
                         float rx, ry, rz;
-                        if (sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a, r.b, rx, ry, rz) < kNearR2)
-                            near_pair_f64(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a, r.b, r.c, pn[t]);
+                        if (sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a.x, r.a.y, r.a.z, r.b.x, r.b.y,
+                                    r.b.z, rx, ry, rz) < kNearR2)
+                            near_pair_f64(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a.x, r.a.y, r.a.z, r.b.x,
+                                          r.b.y, r.b.z, r.a.w, r.b.w, r.c.x, r.c.y, r.c.z, r.c.w, pn[t]);
                     }
                 }
             }

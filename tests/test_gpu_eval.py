@@ -173,3 +173,32 @@ def test_fp32c_near_pairs_across_filaments(mrs, tpl):
         _check(mrs, c, X, f, n, eps, 1.0, 1, f"crossing-tpl{tpl}")
     finally:
         mrs.mrs_context_destroy(c)
+
+
+@pytest.mark.parametrize("tpl", [1, 2])
+def test_fp32c_every_block_path_far_from_origin(mrs, tpl):
+    """Straight filaments at separations from under 4 eps to a few hundred
+    eps, 8,000 eps from the origin.  Pairs of a wave's targets and a 64-source
+    block take all three paths of the tiled FP32C kernel (masked with the FP64
+    near-pair rescan, far with the exact hi/lo separation, far relative to the
+    block's anchor); every target must match the oracle, near the origin and
+    shifted."""
+    c = mrs.mrs_context_create(0)
+    try:
+        rng = np.random.default_rng(41)
+        F, M = 40, 64
+        ds = 1.0 / M
+        eps = 1.5 * ds
+        X = []
+        for _ in range(F):
+            d = rng.normal(size=3)
+            d /= np.linalg.norm(d)
+            X.append(rng.uniform(0.0, 200.0 * eps, 3) + (np.arange(M) * ds)[:, None] * d[None, :])
+        X = np.concatenate(X)
+        f, n = rng.normal(size=X.shape), rng.normal(size=X.shape)
+        mrs.mrs_tune_set(c, len(X), 1, 0, tpl, 0)
+        _check(mrs, c, X, f, n, eps, 1.0, 1, f"paths-tpl{tpl}")
+        Xs = X + np.array([8000.0, -6000.0, 7000.0]) * eps
+        _check(mrs, c, Xs, f, n, eps, 1.0, 1, f"paths-shifted-tpl{tpl}")
+    finally:
+        mrs.mrs_context_destroy(c)
