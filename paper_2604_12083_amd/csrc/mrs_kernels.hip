@@ -802,6 +802,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int stage, int scheme, double
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (i < N) {
         const double *__restrict__ part = E.part;
+        // unrolled so that several chunks' loads are in flight; the sum
+        // order (k ascending) is unchanged
+#pragma unroll 4
         for (int k = k0; k < k1; k++)
 #pragma unroll
             for (int c = 0; c < 6; c++) acc[c] += part[((size_t)k * 6 + c) * N + i];

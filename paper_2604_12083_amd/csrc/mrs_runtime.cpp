@@ -102,7 +102,19 @@ static hipError_t upload_vec(DevBuf &d, const std::vector<T> &v) {
     return hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
+// Blocks whose source range overlaps their own targets in index order hold
+// the near pairs along each filament (masked path plus the FP64 rescan) and
+// run longest; dispatching them first keeps them off the tail of a launch.
+// The order of blocks does not change any result: each writes its own slots.
+void near_blocks_first(std::vector<PairItem> &v) {
+    std::stable_partition(v.begin(), v.end(), [](const PairItem &it) {
+        return it.src0 < it.tgt0 + it.ntgt + kKahanBlock && it.tgt0 < it.src0 + it.nsrc + kKahanBlock;
+    });
+}
+
 hipError_t finalize_plan(Plan &P) {
+    near_blocks_first(P.tile1);
+    near_blocks_first(P.tile2);
     hipError_t e;
     if ((e = upload_vec(P.d_desc, P.h_desc)) != hipSuccess) return e;
     if ((e = upload_vec(P.d_split, P.split)) != hipSuccess) return e;
@@ -482,6 +494,8 @@ mrs_status mrs_eval_device(mrs_context *ctx, int64_t n, const double *dX, const 
     Plan P;
     P.prec = p;
     add_items(P, 0, n, 0, c);
+    near_blocks_first(P.tile1);
+    near_blocks_first(P.tile2);
     // desc + items in one upload: [desc][split][tile1][tile2][pts]
     std::vector<char> blob;
     auto put = [&](const void *src, size_t bytes) {

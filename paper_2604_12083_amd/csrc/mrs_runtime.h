@@ -138,6 +138,9 @@ inline hipError_t timed(mrs_context *ctx, const char *name, hipStream_t s, F &&l
 
 
 PairCfg choose_cfg(mrs_context *ctx, int64_t N, int prec);
+// Reorders tiled pair blocks so that those with near pairs along a filament
+// (source range overlapping the target range) are dispatched first.
+void near_blocks_first(std::vector<PairItem> &v);
 // Power-of-two size class of the tuning table.
 int size_bucket(int64_t N);
 size_t ensemble_bytes(int64_t N, int n_fil, bool has_ext, int K64, int K32);
