@@ -303,6 +303,11 @@ mrs_status mrs_parareal(mrs_ensemble *ens, int32_t n_slices, mrs_integrator fine
  * events and returns the launch count and summed duration (milliseconds) of
  * the kernels whose name contains `kernel` (NULL or "" = all). */
 mrs_status mrs_profile_enable(mrs_context *ctx, int on);
+/* Restricts the bracketing to launches whose kernel name contains `kernel`
+ * (NULL or "" = every launch), so that timing one kernel adds no events
+ * around the others.  The string is copied.  Errors: MRS_EINVAL for a null
+ * context. */
+mrs_status mrs_profile_select(mrs_context *ctx, const char *kernel);
 mrs_status mrs_profile_reset(mrs_context *ctx);
 mrs_status mrs_profile_query(mrs_context *ctx, const char *kernel, int64_t *launches,
                              double *total_ms);

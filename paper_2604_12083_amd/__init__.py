@@ -120,6 +120,7 @@ _SIGS = {
     "mrs_parareal": (_int, [_vp, ctypes.c_int32, _int, _dbl, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dbl,
                             _int, _int, _vp, ctypes.POINTER(ctypes.c_int32)]),
     "mrs_profile_enable": (_int, [_vp, _int]),
+    "mrs_profile_select": (_int, [_vp, ctypes.c_char_p]),
     "mrs_profile_reset": (_int, [_vp]),
     "mrs_profile_query": (_int, [_vp, ctypes.c_char_p, ctypes.POINTER(_i64), ctypes.POINTER(_dbl)]),
 }
@@ -296,6 +297,10 @@ def mrs_batch_eval(ctx, ens_list, prec=MRS_FP32C, include_elastic=True) -> None:
 
 def mrs_profile_enable(ctx, on=True) -> None:
     _check(_lib.mrs_profile_enable(ctx, int(bool(on))), ctx)
+
+
+def mrs_profile_select(ctx, kernel="") -> None:
+    _check(_lib.mrs_profile_select(ctx, kernel.encode() if kernel else None), ctx)
 
 
 def mrs_profile_reset(ctx) -> None:

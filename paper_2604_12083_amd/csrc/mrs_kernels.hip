@@ -514,11 +514,14 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
         const int cnt = min(kSrcTile, it.nsrc - base);
         for (int sb = 0; sb < cnt; sb += kKahanBlock) {
             float p[T][6];
-            float rmin = kNearR2;
+            // bit j of near[t]: source sb + j is near target t (masked path only)
+            uint64_t near[T];
 #pragma unroll
-            for (int t = 0; t < T; t++)
+            for (int t = 0; t < T; t++) {
+                near[t] = 0;
 #pragma unroll
                 for (int k = 0; k < 6; k++) p[t][k] = 0.0f;
+            }
             const float *bx = sBox[sb / kKahanBlock];
             const float gap2 = box_gap2(tlo, thi, bx, bx + 3);
             if (gap2 > kFarBoxGap2 && gap2 > kAnchorGapRatio2 * bx[9]) {
@@ -563,7 +566,7 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
                         const float R2 = sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], H.x, H.y, H.z,
                                                  Nn.y, Nn.z, Nn.w, rx, ry, rz);
                         pair_core_f32<true>(rx, ry, rz, R2, W.w, F.x, F.y, F.z, F.w, Nn.x, p[t]);
-                        rmin = fminf(rmin, R2);
+                        near[t] |= (uint64_t)(R2 < kNearR2) << (jj - sb);
                     }
                 }
             }
@@ -571,24 +574,24 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
             for (int t = 0; t < T; t++)
 #pragma unroll
                 for (int k = 0; k < 6; k++) kahan_add(s[t][k], c[t][k], p[t][k]);
-            if (rmin < kNearR2) {
-                // this lane met a near pair in the sub-block: evaluate those in FP64
-                for (int jj = sb; jj < sb + kKahanBlock; jj++) {
-                    const float4 W = sW[jj], F = sF[jj], Nn = sN[jj], H = sH[jj];
+            // the pairs masked above, in FP64 on the exact hi/lo difference:
+            // each lane walks only its own near sources
 #pragma unroll
-                    for (int t = 0; t < T; t++) {
-                        float rx, ry, rz;
-                        if (sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], H.x, H.y, H.z, Nn.y, Nn.z,
-                                    Nn.w, rx, ry, rz) < kNearR2) {
-                            double pn[6];
+            for (int t = 0; t < T; t++) {
+                uint64_t m = near[t];
+                if (m) {
+                    double pn[6];
 #pragma unroll
-                            for (int k = 0; k < 6; k++) pn[k] = sNear[k][t][tid];
-                            near_pair_f64(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], H.x, H.y, H.z, Nn.y,
-                                          Nn.z, Nn.w, W.w, F.x, F.y, F.z, F.w, Nn.x, pn);
+                    for (int k = 0; k < 6; k++) pn[k] = sNear[k][t][tid];
+                    do {
+                        const int jj = sb + __builtin_ctzll(m);
+                        m &= m - 1;
+                        const float4 W = sW[jj], F = sF[jj], Nn = sN[jj], H = sH[jj];
+                        near_pair_f64(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], H.x, H.y, H.z, Nn.y, Nn.z,
+                                      Nn.w, W.w, F.x, F.y, F.z, F.w, Nn.x, pn);
+                    } while (m);
 #pragma unroll
-                            for (int k = 0; k < 6; k++) sNear[k][t][tid] = pn[k];
-                        }
-                    }
+                    for (int k = 0; k < 6; k++) sNear[k][t][tid] = pn[k];
                 }
             }
         }

@@ -888,6 +888,12 @@ mrs_status mrs_profile_enable(mrs_context *ctx, int on) {
     return MRS_OK;
 }
 
+mrs_status mrs_profile_select(mrs_context *ctx, const char *kernel) {
+    CHECK_CTX(ctx);
+    ctx->prof_sel = kernel ? kernel : "";
+    return MRS_OK;
+}
+
 mrs_status mrs_profile_reset(mrs_context *ctx) {
     CHECK_CTX(ctx);
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));

@@ -8,6 +8,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -87,6 +88,7 @@ struct mrs_context {
     bool stage_pending = false;
     // profiling
     bool prof_on = false;
+    std::string prof_sel;  // bracket only kernels whose name contains this (empty = all)
     std::vector<mrs::ProfRec> prof;
     std::vector<hipEvent_t> event_pool;
     // tuning table: (prec, log2 bucket of N) -> config
@@ -127,7 +129,7 @@ const char *epi_name(int epi);
 // Launch `launch()` on stream s; with profiling on, bracket it with events.
 template <class F>
 inline hipError_t timed(mrs_context *ctx, const char *name, hipStream_t s, F &&launch) {
-    if (!ctx->prof_on) return launch();
+    if (!ctx->prof_on || (!ctx->prof_sel.empty() && !std::strstr(name, ctx->prof_sel.c_str()))) return launch();
     hipEvent_t a = take_event(ctx), b = take_event(ctx);
     if (a) (void)hipEventRecord(a, s);
     hipError_t e = launch();
