@@ -66,8 +66,10 @@ struct RodItem {
     int32_t ens, fil;
 };
 
-// Points per block of the reduction/epilogue kernel.
+// Points per block of the reduction/epilogue kernel, and its threads: the
+// block's waves split the source chunks of its points.
 constexpr int kReducePoints = 64;
+constexpr int kReduceThreads = 256;
 
 // One block of the reduction/epilogue kernel: points [p0, p0 + kReducePoints).
 struct PointItem {

@@ -356,6 +356,20 @@ __global__ __launch_bounds__(kBlock) void k_rod_forces(int prec, int stage_state
     const int tid = threadIdx.x;
     if (elastic < 0) elastic = E.elastic;
     for (int c0 = 0; c0 < M; c0 += kBlock - 1) {
+        // this thread's node: its external loads and position, loaded before
+        // the segment work so that the two memory latencies overlap
+        const int k = c0 + tid;
+        const bool node = tid < kBlock - 1 && k < M;
+        const int p = k0 + (node ? k : 0);
+        double g[3] = {0.0, 0.0, 0.0}, m[3] = {0.0, 0.0, 0.0}, xp[3] = {0.0, 0.0, 0.0};
+        if (node) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                if (E.fext) g[c] = E.fext[(size_t)c * N + p];
+                if (E.next) m[c] = E.next[(size_t)c * N + p];
+                xp[c] = X[(size_t)c * N + p];
+            }
+        }
         if (elastic) {
             const int s = c0 - 1 + tid;
             double F[3] = {0.0, 0.0, 0.0}, Nv[3] = {0.0, 0.0, 0.0}, dX[3] = {0.0, 0.0, 0.0};
@@ -368,15 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_rod_forces(int prec, int stage_state
             }
             __syncthreads();
         }
-        const int k = c0 + tid;
-        if (tid < kBlock - 1 && k < M) {
-            const int p = k0 + k;
-            double g[3], m[3];
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                g[c] = E.fext ? E.fext[(size_t)c * N + p] : 0.0;
-                m[c] = E.next ? E.next[(size_t)c * N + p] : 0.0;
-            }
+        if (node) {
             if (elastic) {
                 // segment k+1/2 sits at LDS slot tid + 1, segment k-1/2 at slot tid
                 const double Fp[3] = {sF[0][tid + 1], sF[1][tid + 1], sF[2][tid + 1]};
@@ -393,8 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_rod_forces(int prec, int stage_state
                     m[c] += (sN[c][tid + 1] - sN[c][tid]) + 0.5 * (cp[c] + cm[c]);
                 }
             }
-            store_rec(prec, E.rec, p, X[p], X[(size_t)N + p], X[(size_t)2 * N + p], g[0], g[1],
-                      g[2], m[0], m[1], m[2], E.inv_eps);
+            store_rec(prec, E.rec, p, xp[0], xp[1], xp[2], g[0], g[1], g[2], m[0], m[1], m[2], E.inv_eps);
             if (E.g_out) {
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
@@ -771,38 +776,51 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
 __constant__ double kRkWeight[2][4] = {{1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0}, {0.0, 1.0, 0.0, 0.0}};
 __constant__ double kRkNextNode[2][3] = {{0.5, 0.5, 1.0}, {0.5, 0.0, 0.0}};
 
-__device__ __forceinline__ void rotate_frame(const double *__restrict__ Din, double *__restrict__ Dout,
-                                             int N, int i, double vx, double vy, double vz,
-                                             bool reorth) {
+__device__ __forceinline__ void rotate_frame(const double *din, double *__restrict__ Dout, int N, int i,
+                                             double vx, double vy, double vz, bool reorth) {
     double q[4], d[9];
     quat_from_rotvec(vx, vy, vz, q);
 #pragma unroll
-    for (int k = 0; k < 3; k++) {
-        const double v[3] = {Din[(size_t)(3 * k) * N + i], Din[(size_t)(3 * k + 1) * N + i],
-                             Din[(size_t)(3 * k + 2) * N + i]};
-        quat_rotate(q, v, d + 3 * k);
-    }
+    for (int k = 0; k < 3; k++) quat_rotate(q, din + 3 * k, d + 3 * k);
     if (reorth) reorthonormalize(d);
 #pragma unroll
     for (int k = 0; k < 9; k++) Dout[(size_t)k * N + i] = d[k];
 }
 
-// One block per kReducePoints points: the 4 waves each sum a fixed quarter of
-// the split-K chunks for the block's points (lane = point), the quarters are
+// One block per kReducePoints points: the waves each sum a fixed share of
+// the split-K chunks for the block's points (lane = point), the parts are
 // combined through LDS in wave order, and wave 0 runs the epilogue.
 template <int EPI>
-__global__ __launch_bounds__(kBlock) void k_reduce(int stage, int scheme, double dt,
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(int stage, int scheme, double dt,
                                                    const EnsDesc *__restrict__ desc,
                                                    const PointItem *__restrict__ items) {
-    __shared__ double sPart[kBlock / 64][6][64];
+    __shared__ double sPart[kReduceThreads / 64][6][64];
     const PointItem it = items[blockIdx.x];
     const EnsDesc &E = desc[it.ens];
     const int N = E.N;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = it.p0 + lane;
     const int K = E.K;
-    const int k0 = (K * w) / (kBlock / 64), k1 = (K * (w + 1)) / (kBlock / 64);
+    const int k0 = (K * w) / (kReduceThreads / 64), k1 = (K * (w + 1)) / (kReduceThreads / 64);
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // wave 0 loads the state its epilogue updates before the partial sums,
+    // so that the two memory latencies overlap
+    double xv[3] = {0.0, 0.0, 0.0}, dv[9], uav[3] = {0.0, 0.0, 0.0}, wav[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 9; k++) dv[k] = 0.0;
+    if (EPI != EPI_WRITE && w == 0 && i < N) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) xv[c] = E.X[(size_t)c * N + i];
+#pragma unroll
+        for (int k = 0; k < 9; k++) dv[k] = E.D[(size_t)k * N + i];
+        if (EPI != EPI_EULER && stage > 0) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                uav[c] = E.Ua[(size_t)c * N + i];
+                wav[c] = E.Wa[(size_t)c * N + i];
+            }
+        }
+    }
     if (i < N) {
         const double *__restrict__ part = E.part;
         // unrolled so that several chunks' loads are in flight; the sum
@@ -820,7 +838,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int stage, int scheme, double
     for (int c = 0; c < 6; c++) {
         double v = sPart[0][c][lane];
 #pragma unroll
-        for (int q = 1; q < kBlock / 64; q++) v += sPart[q][c][lane];
+        for (int q = 1; q < kReduceThreads / 64; q++) v += sPart[q][c][lane];
         acc[c] = v;
     }
     if (dt != dt) dt = E.dt;  // NaN: per-ensemble step size
@@ -841,9 +859,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int stage, int scheme, double
         for (int c = 0; c < 3; c++) {
             E.U[(size_t)c * N + i] = U[c];
             E.W[(size_t)c * N + i] = W[c];
-            E.X[(size_t)c * N + i] += dt * U[c];
+            E.X[(size_t)c * N + i] = xv[c] + dt * U[c];
         }
-        rotate_frame(E.D, E.D, N, i, dt * W[0], dt * W[1], dt * W[2], true);
+        rotate_frame(dv, E.D, N, i, dt * W[0], dt * W[1], dt * W[2], true);
         return;
     }
     // Runge-Kutta stage `stage` of `scheme`, evaluated at the stage state.
@@ -857,8 +875,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int stage, int scheme, double
             ua[c] = wgt * U[c];
             wa[c] = wgt * W[c];
         } else {
-            ua[c] = E.Ua[(size_t)c * N + i] + wgt * U[c];
-            wa[c] = E.Wa[(size_t)c * N + i] + wgt * W[c];
+            ua[c] = uav[c] + wgt * U[c];
+            wa[c] = wav[c] + wgt * W[c];
         }
     }
     if (EPI == EPI_RK_STAGE) {
@@ -867,13 +885,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int stage, int scheme, double
         for (int c = 0; c < 3; c++) {
             E.Ua[(size_t)c * N + i] = ua[c];
             E.Wa[(size_t)c * N + i] = wa[c];
-            E.Xs[(size_t)c * N + i] = E.X[(size_t)c * N + i] + h * U[c];
+            E.Xs[(size_t)c * N + i] = xv[c] + h * U[c];
         }
-        rotate_frame(E.D, E.Ds, N, i, h * W[0], h * W[1], h * W[2], false);
+        rotate_frame(dv, E.Ds, N, i, h * W[0], h * W[1], h * W[2], false);
     } else {
 #pragma unroll
-        for (int c = 0; c < 3; c++) E.X[(size_t)c * N + i] += dt * ua[c];
-        rotate_frame(E.D, E.D, N, i, dt * wa[0], dt * wa[1], dt * wa[2], true);
+        for (int c = 0; c < 3; c++) E.X[(size_t)c * N + i] = xv[c] + dt * ua[c];
+        rotate_frame(dv, E.D, N, i, dt * wa[0], dt * wa[1], dt * wa[2], true);
     }
 }
 
@@ -926,7 +944,7 @@ hipError_t launch_rod_forces(int prec, int stage_state, int elastic, const EnsDe
 hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, const PairItem *d_items,
                         int n_items, hipStream_t s) {
     if (n_items == 0) return hipSuccess;
-    const dim3 g(n_items), b(kBlock);
+    const dim3 g(n_items), b(kBlock);  // the pair kernels index LDS by threadIdx.x < kBlock
     if (mode == PAIR_SPLIT) {
         if (prec == 1) hipLaunchKernelGGL(k_pairs_split<1>, g, b, 0, s, d_desc, d_items);
         else hipLaunchKernelGGL(k_pairs_split<0>, g, b, 0, s, d_desc, d_items);
@@ -943,7 +961,7 @@ hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, cons
 hipError_t launch_reduce(int epi, int stage, int scheme, double dt, const EnsDesc *d_desc,
                          const PointItem *d_items, int n_items, hipStream_t s) {
     if (n_items == 0) return hipSuccess;
-    const dim3 g(n_items), b(kBlock);
+    const dim3 g(n_items), b(kReduceThreads);
     switch (epi) {
         case EPI_EULER: hipLaunchKernelGGL(k_reduce<EPI_EULER>, g, b, 0, s, stage, scheme, dt, d_desc, d_items); break;
         case EPI_RK_STAGE: hipLaunchKernelGGL(k_reduce<EPI_RK_STAGE>, g, b, 0, s, stage, scheme, dt, d_desc, d_items); break;
