@@ -31,7 +31,7 @@ FLOPS_PER_PAIR = 92       # algorithmic flops of one (target, source) evaluation
 # HBM bytes per pair-kernel launch from hardware counters (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, the factors a 256 MiB device copy reads), valid only for
 # the kernel source they were taken on: any other source reports null.
-KERNEL_SRC = os.path.join(ROOT, "paper_2604_12083_amd", "csrc", "mrs_kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2604_12083_amd", "csrc", "mrs_pairs.hip")
 MEASURED_TRAFFIC = {
     "a74fb21061ef44d7748cc63608aef990b738b1cc8cd6d02066b896b0560c7b17": {
         ("config2", "fp32c"): (2644.88 * 2.0 + 30000.0) * 1024,

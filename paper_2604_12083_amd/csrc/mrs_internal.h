@@ -86,7 +86,7 @@ enum Epilogue : int {
 // Runge-Kutta schemes of the stage epilogue.
 enum RkScheme : int { RK_SCHEME_RK4 = 0, RK_SCHEME_RK2 = 1 };
 
-// Launch wrappers (mrs_kernels.hip).  All return the launch's hipError_t.
+// Launch wrappers (mrs_pairs.hip, mrs_kernels.hip).  All return the launch's hipError_t.
 hipError_t launch_pack_aos(int prec, const EnsDesc *d_desc, const EnsDesc &h_desc,
                            hipStream_t s);
 // elastic < 0: every ensemble uses its own EnsDesc::elastic.

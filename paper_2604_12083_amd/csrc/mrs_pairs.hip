@@ -1,0 +1,525 @@
+// HIP kernels (gfx950) of the all-pairs MRS sum (Sec. II.C, Eqs.
+// velocity_field, angular_velocity_field, superposition).
+//
+//   k_pairs_tile_*    one lane per target (T targets per lane), sources
+//                     staged through LDS and broadcast to the wave, split-K
+//                     over source chunks
+//   k_pairs_split     small-ensemble form: a wave owns a few targets, its lanes
+//                     stride over the sources and the sums are combined with
+//                     wave shuffles
+//
+// Kernel functions.  With R^2 = r^2 + eps^2, Q = 1/R and H_i the kernel
+// functions of the blob phi_eps (Sec. II.C), 8 pi H_i are
+//   H1: Q + eps^2 Q^3            H2: Q^3
+//   H3: Q^3 + 1.5 eps^2 Q^5      H4: 3.75 eps^4 Q^7 - 0.75 eps^2 Q^5 - 0.5 Q^3
+//   H5: 1.5 Q^5 + 3.75 eps^2 Q^7
+// The FP32C form works in units of eps (rho = r/eps, f~ = f/eps,
+// n~ = n/eps^2), where the same expressions hold with eps = 1 and
+// U = sum/(8 pi mu), Omega = sum/(8 pi mu eps); this keeps every FP32
+// intermediate far from overflow and folds all constants into one FP64
+// scale per target.
+#include <hip/hip_runtime.h>
+
+#include "mrs_internal.h"
+
+namespace mrs {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ float rsq_f32(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Hardware reciprocal square root refined by one third-order step
+// q <- q (1 + e/2 + 3 e^2/8), e = 1 - x q^2, which takes the hardware
+// estimate to double precision.
+__device__ __forceinline__ double rsq_f64(double x) {
+    double q = __builtin_amdgcn_rsq(x);
+    double e = fma(-x, q * q, 1.0);
+    double p = fma(0.375, e, 0.5);
+    return fma(q * e, p, q);
+}
+
+__device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
+    float y = x - c;
+    float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Pairs closer than rho = r/eps < 4 (R^2 = rho^2 + 1 < 17) carry the largest
+// terms of every sum; the FP32C kernels evaluate them in FP64 (on the exact
+// hi/lo difference) and every other pair in FP32.
+constexpr float kNearR2 = 17.0f;
+
+// R^2 = rho^2 + 1 of a target (th + tl) and a source (sh + sl), in FP32.
+// Both the hot loop and the near-pair rescan use this one function, so they
+// take the same near/far decision bit for bit.
+__device__ __forceinline__ float sep_f32(float thx, float thy, float thz, float tlx, float tly,
+                                         float tlz, float shx, float shy, float shz, float slx,
+                                         float sly, float slz, float &rx, float &ry, float &rz) {
+    rx = (thx - shx) + (tlx - slx);
+    ry = (thy - shy) + (tly - sly);
+    rz = (thz - shz) + (tlz - slz);
+    return fmaf(rz, rz, fmaf(ry, ry, fmaf(rx, rx, 1.0f)));
+}
+
+// Contribution of one source at separation r (R2 = |r|^2 + 1) to p[0..5] =
+// (8 pi mu U, 8 pi mu eps Omega) of one target, in units of eps.  With MASK a
+// near pair adds exactly zero; without it the caller guarantees that no pair
+// is near.
+template <bool MASK>
+__device__ __forceinline__ void pair_core_f32(float rx, float ry, float rz, float R2, float fx,
+                                              float fy, float fz, float nx, float ny, float nz,
+                                              float *p) {
+    const float q = (MASK && R2 < kNearR2) ? 0.0f : rsq_f32(R2);
+    const float q2 = q * q, q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
+    const float h1 = q + q3;
+    const float t = 1.5f * q5;
+    const float h3 = q3 + t;
+    const float u = 3.75f * q7;
+    const float h5 = u + t;
+    const float h4 = fmaf(-0.5f, h3, u);
+    const float fr = fmaf(fz, rz, fmaf(fy, ry, fx * rx));
+    const float nr = fmaf(nz, rz, fmaf(ny, ry, nx * rx));
+    const float a = q3 * fr, b = h5 * nr;
+    // H3 (n x r) = n x g and H3 (f x r) = f x g with g = H3 r
+    const float gx = h3 * rx, gy = h3 * ry, gz = h3 * rz;
+    p[0] = fmaf(-nz, gy, fmaf(ny, gz, fmaf(a, rx, fmaf(h1, fx, p[0]))));
+    p[1] = fmaf(-nx, gz, fmaf(nz, gx, fmaf(a, ry, fmaf(h1, fy, p[1]))));
+    p[2] = fmaf(-ny, gx, fmaf(nx, gy, fmaf(a, rz, fmaf(h1, fz, p[2]))));
+    p[3] = fmaf(-fz, gy, fmaf(fy, gz, fmaf(b, rx, fmaf(h4, nx, p[3]))));
+    p[4] = fmaf(-fx, gz, fmaf(fz, gx, fmaf(b, ry, fmaf(h4, ny, p[4]))));
+    p[5] = fmaf(-fy, gx, fmaf(fx, gy, fmaf(b, rz, fmaf(h4, nz, p[5]))));
+}
+
+// The same for a source record (a = hi + fx, b = lo + fy, c = fz, n); returns R^2.
+template <bool MASK>
+__device__ __forceinline__ float pair_f32(float thx, float thy, float thz, float tlx, float tly,
+                                          float tlz, const float4 A, const float4 B,
+                                          const float4 C, float *p) {
+    float rx, ry, rz;
+    const float R2 = sep_f32(thx, thy, thz, tlx, tly, tlz, A.x, A.y, A.z, B.x, B.y, B.z, rx, ry, rz);
+    pair_core_f32<MASK>(rx, ry, rz, R2, A.w, B.w, C.x, C.y, C.z, C.w, p);
+    return R2;
+}
+
+// Same in FP64 for the separation r = x_target - X_source:
+// p += (8 pi mu U, 8 pi mu Omega) in unscaled units (e2 = eps^2, c375e2 =
+// 3.75 eps^2), or the eps-unit form with e2 = 1, c375e2 = 3.75.
+__device__ __forceinline__ void pair_f64_r(double rx, double ry, double rz, double fx, double fy,
+                                           double fz, double nx, double ny, double nz, double e2,
+                                           double c375e2, double *p) {
+    const double R2 = fma(rz, rz, fma(ry, ry, fma(rx, rx, e2)));
+    const double q = rsq_f64(R2);
+    const double q2 = q * q, q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
+    const double h1 = fma(e2, q3, q);
+    const double t = 1.5 * q5;
+    const double h3 = fma(e2, t, q3);
+    const double u = c375e2 * q7;
+    const double h5 = t + u;
+    const double h4 = fma(-0.5, h3, e2 * u);
+    const double fr = fma(fz, rz, fma(fy, ry, fx * rx));
+    const double nr = fma(nz, rz, fma(ny, ry, nx * rx));
+    const double a = q3 * fr, b = h5 * nr;
+    const double gx = h3 * rx, gy = h3 * ry, gz = h3 * rz;  // see pair_f32
+    p[0] = fma(-nz, gy, fma(ny, gz, fma(a, rx, fma(h1, fx, p[0]))));
+    p[1] = fma(-nx, gz, fma(nz, gx, fma(a, ry, fma(h1, fy, p[1]))));
+    p[2] = fma(-ny, gx, fma(nx, gy, fma(a, rz, fma(h1, fz, p[2]))));
+    p[3] = fma(-fz, gy, fma(fy, gz, fma(b, rx, fma(h4, nx, p[3]))));
+    p[4] = fma(-fx, gz, fma(fz, gx, fma(b, ry, fma(h4, ny, p[4]))));
+    p[5] = fma(-fy, gx, fma(fx, gy, fma(b, rz, fma(h4, nz, p[5]))));
+}
+
+__device__ __forceinline__ void pair_f64(double tx, double ty, double tz, double x, double y,
+                                         double z, double fx, double fy, double fz, double nx,
+                                         double ny, double nz, double e2, double c375e2,
+                                         double *p) {
+    pair_f64_r(tx - x, ty - y, tz - z, fx, fy, fz, nx, ny, nz, e2, c375e2, p);
+}
+
+// FP64 evaluation of a near pair from FP32 hi/lo positions: the hi and lo
+// differences are exact in FP64, the loads are the record's FP32 values.
+__device__ __forceinline__ void near_pair_f64(float thx, float thy, float thz, float tlx, float tly,
+                                              float tlz, float shx, float shy, float shz, float slx,
+                                              float sly, float slz, float fx, float fy, float fz,
+                                              float nx, float ny, float nz, double *p) {
+    const double rx = ((double)thx - (double)shx) + ((double)tlx - (double)slx);
+    const double ry = ((double)thy - (double)shy) + ((double)tly - (double)sly);
+    const double rz = ((double)thz - (double)shz) + ((double)tlz - (double)slz);
+    pair_f64_r(rx, ry, rz, fx, fy, fz, nx, ny, nz, 1.0, 3.75, p);
+}
+
+// ----------------------------------------------------------------- pairs
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Squared distance between the boxes [lo0, hi0] and [lo1, hi1] (0 if they overlap).
+__device__ __forceinline__ float box_gap2(const float *lo0, const float *hi0, const float *lo1, const float *hi1) {
+    float d2 = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const float g = fmaxf(0.0f, fmaxf(lo0[c] - hi1[c], lo1[c] - hi0[c]));
+        d2 = fmaf(g, g, d2);
+    }
+    return d2;
+}
+
+// A wave whose target box is farther than this (squared, in units of eps)
+// from a source block's box has no near pair in it: 17 > (4 + margin)^2 for
+// the hi-part rounding of the boxes (at most 2^-24 of 2^14 per coordinate).
+constexpr float kFarBoxGap2 = 17.0f;
+
+// Anchored far blocks.  Relative to the centre c of a 64-source block's box,
+// a source sits at w = (sh - c) + sl and a target at u = (th - c) + tl, both
+// rounded once to FP32, and r = u - w costs 3 instead of 9 operations.  Each
+// rounding is at most 2^-24 of |u| <= |r| + |w| or of |w|; with the gap
+// between the boxes at least 4 times the block's half-diagonal, |w| <= |r|/4
+// and r keeps a relative error below 2^-21, against 2^-23 for the exact
+// hi/lo difference of the other paths.
+constexpr float kAnchorGapRatio2 = 16.0f;
+
+// Blocks per CU the register budget must allow: 5 with one target per lane
+// (<= 102 VGPRs), 3 with two (<= 170).
+template <int T>
+__global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const EnsDesc *__restrict__ desc,
+                                                           const PairItem *__restrict__ items) {
+    // staged sources: sW = (w, fx) with w the anchored position, sF = (fy, fz,
+    // nx, ny), sN = (nz, lo), sH = (hi, 0)
+    __shared__ float4 sW[kSrcTile], sF[kSrcTile], sN[kSrcTile], sH[kSrcTile];
+    __shared__ double sNear[6][T][kBlock];  // FP64 near-pair sums, one slot per lane and target
+    // per 64-source block: hi-part box lo, hi, anchor c, squared half-diagonal
+    __shared__ float sBox[kSrcTile / kKahanBlock][10];
+    static_assert(kSrcTile / kKahanBlock == kBlock / 64, "one source block per wave");
+    const PairItem it = items[blockIdx.x];
+    const EnsDesc &E = desc[it.ens];
+    const RecF32 *__restrict__ rec = reinterpret_cast<const RecF32 *>(E.rec);
+    const int tid = threadIdx.x;
+    float thx[T], thy[T], thz[T], tlx[T], tly[T], tlz[T];
+    float s[T][6], c[T][6];
+    float tlo[3] = {INFINITY, INFINITY, INFINITY}, thi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int t = 0; t < T; t++) {
+        const int li = min(tid + t * kBlock, it.ntgt - 1);
+        const RecF32 r = rec[it.tgt0 + li];
+        thx[t] = r.a.x; thy[t] = r.a.y; thz[t] = r.a.z;
+        tlx[t] = r.b.x; tly[t] = r.b.y; tlz[t] = r.b.z;
+        tlo[0] = fminf(tlo[0], thx[t]); tlo[1] = fminf(tlo[1], thy[t]); tlo[2] = fminf(tlo[2], thz[t]);
+        thi[0] = fmaxf(thi[0], thx[t]); thi[1] = fmaxf(thi[1], thy[t]); thi[2] = fmaxf(thi[2], thz[t]);
+#pragma unroll
+        for (int k = 0; k < 6; k++) { s[t][k] = 0.0f; c[t][k] = 0.0f; sNear[k][t][tid] = 0.0; }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) { tlo[k] = wave_min(tlo[k]); thi[k] = wave_max(thi[k]); }
+    for (int base = 0; base < it.nsrc; base += kSrcTile) {
+        __syncthreads();
+        const int j = base + tid;
+        const bool real = j < it.nsrc;
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, cc = a;
+        if (real) {
+            const RecF32 r = rec[it.src0 + j];
+            a = r.a; b = r.b; cc = r.c;
+        }
+        // this wave stages source block tid / 64: its box (padding excluded) and anchor
+        float lo[3], hi[3], ctr[3], hd2 = 0.0f;
+        lo[0] = wave_min(real ? a.x : INFINITY); lo[1] = wave_min(real ? a.y : INFINITY);
+        lo[2] = wave_min(real ? a.z : INFINITY);
+        hi[0] = wave_max(real ? a.x : -INFINITY); hi[1] = wave_max(real ? a.y : -INFINITY);
+        hi[2] = wave_max(real ? a.z : -INFINITY);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            // a block without a real source (never evaluated) gets a finite anchor
+            ctr[k] = lo[k] <= hi[k] ? 0.5f * (lo[k] + hi[k]) : 0.0f;
+            const float h = lo[k] <= hi[k] ? 0.5f * (hi[k] - lo[k]) : 0.0f;
+            hd2 = fmaf(h, h, hd2);
+        }
+        sW[tid] = make_float4((a.x - ctr[0]) + b.x, (a.y - ctr[1]) + b.y, (a.z - ctr[2]) + b.z, a.w);
+        sF[tid] = make_float4(b.w, cc.x, cc.y, cc.z);
+        sN[tid] = make_float4(cc.w, b.x, b.y, b.z);
+        sH[tid] = make_float4(a.x, a.y, a.z, 0.0f);
+        if ((tid & 63) == 0) {
+            float *bx = sBox[tid >> 6];
+#pragma unroll
+            for (int k = 0; k < 3; k++) { bx[k] = lo[k]; bx[3 + k] = hi[k]; bx[6 + k] = ctr[k]; }
+            bx[9] = hd2;
+        }
+        __syncthreads();
+        const int cnt = min(kSrcTile, it.nsrc - base);
+        for (int sb = 0; sb < cnt; sb += kKahanBlock) {
+            float p[T][6];
+            // bit j of near[t]: source sb + j is near target t (masked path only)
+            uint64_t near[T];
+#pragma unroll
+            for (int t = 0; t < T; t++) {
+                near[t] = 0;
+#pragma unroll
+                for (int k = 0; k < 6; k++) p[t][k] = 0.0f;
+            }
+            const float *bx = sBox[sb / kKahanBlock];
+            const float gap2 = box_gap2(tlo, thi, bx, bx + 3);
+            if (gap2 > kFarBoxGap2 && gap2 > kAnchorGapRatio2 * bx[9]) {
+                // wave-uniform: no near pair, separation from the block's anchor
+                float ux[T], uy[T], uz[T];
+#pragma unroll
+                for (int t = 0; t < T; t++) {
+                    ux[t] = (thx[t] - bx[6]) + tlx[t];
+                    uy[t] = (thy[t] - bx[7]) + tly[t];
+                    uz[t] = (thz[t] - bx[8]) + tlz[t];
+                }
+#pragma unroll 2
+                for (int jj = sb; jj < sb + kKahanBlock; jj++) {
+                    const float4 W = sW[jj], F = sF[jj], Nn = sN[jj];
+#pragma unroll
+                    for (int t = 0; t < T; t++) {
+                        const float rx = ux[t] - W.x, ry = uy[t] - W.y, rz = uz[t] - W.z;
+                        const float R2 = fmaf(rz, rz, fmaf(ry, ry, fmaf(rx, rx, 1.0f)));
+                        pair_core_f32<false>(rx, ry, rz, R2, W.w, F.x, F.y, F.z, F.w, Nn.x, p[t]);
+                    }
+                }
+            } else if (gap2 > kFarBoxGap2) {
+                // wave-uniform: no near pair, exact hi/lo separation
+#pragma unroll 2
+                for (int jj = sb; jj < sb + kKahanBlock; jj++) {
+                    const float4 W = sW[jj], F = sF[jj], Nn = sN[jj], H = sH[jj];
+#pragma unroll
+                    for (int t = 0; t < T; t++) {
+                        float rx, ry, rz;
+                        const float R2 = sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], H.x, H.y, H.z,
+                                                 Nn.y, Nn.z, Nn.w, rx, ry, rz);
+                        pair_core_f32<false>(rx, ry, rz, R2, W.w, F.x, F.y, F.z, F.w, Nn.x, p[t]);
+                    }
+                }
+            } else {
+#pragma unroll 2
+                for (int jj = sb; jj < sb + kKahanBlock; jj++) {
+                    const float4 W = sW[jj], F = sF[jj], Nn = sN[jj], H = sH[jj];
+#pragma unroll
+                    for (int t = 0; t < T; t++) {
+                        float rx, ry, rz;
+                        const float R2 = sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], H.x, H.y, H.z,
+                                                 Nn.y, Nn.z, Nn.w, rx, ry, rz);
+                        pair_core_f32<true>(rx, ry, rz, R2, W.w, F.x, F.y, F.z, F.w, Nn.x, p[t]);
+                        near[t] |= (uint64_t)(R2 < kNearR2) << (jj - sb);
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < T; t++)
+#pragma unroll
+                for (int k = 0; k < 6; k++) kahan_add(s[t][k], c[t][k], p[t][k]);
+            // the pairs masked above, in FP64 on the exact hi/lo difference:
+            // each lane walks only its own near sources
+#pragma unroll
+            for (int t = 0; t < T; t++) {
+                uint64_t m = near[t];
+                if (m) {
+                    double pn[6];
+#pragma unroll
+                    for (int k = 0; k < 6; k++) pn[k] = sNear[k][t][tid];
+                    do {
+                        const int jj = sb + __builtin_ctzll(m);
+                        m &= m - 1;
+                        const float4 W = sW[jj], F = sF[jj], Nn = sN[jj], H = sH[jj];
+                        near_pair_f64(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], H.x, H.y, H.z, Nn.y, Nn.z,
+                                      Nn.w, W.w, F.x, F.y, F.z, F.w, Nn.x, pn);
+                    } while (m);
+#pragma unroll
+                    for (int k = 0; k < 6; k++) sNear[k][t][tid] = pn[k];
+                }
+            }
+        }
+    }
+    const int N = E.N;
+#pragma unroll
+    for (int t = 0; t < T; t++) {
+        const int li = tid + t * kBlock;
+        if (li < it.ntgt) {
+#pragma unroll
+            for (int k = 0; k < 6; k++)
+                E.part[((size_t)it.chunk * 6 + k) * N + it.tgt0 + li] =
+                    ((double)s[t][k] - (double)c[t][k]) + sNear[k][t][tid];
+        }
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(kBlock) void k_pairs_tile_f64(const EnsDesc *__restrict__ desc,
+                                                           const PairItem *__restrict__ items) {
+    __shared__ double2 s0[kSrcTile], s1[kSrcTile], s2[kSrcTile], s3[kSrcTile], s4[kSrcTile];
+    const PairItem it = items[blockIdx.x];
+    const EnsDesc &E = desc[it.ens];
+    const RecF64 *__restrict__ rec = reinterpret_cast<const RecF64 *>(E.rec);
+    const int tid = threadIdx.x;
+    const double e2 = E.eps * E.eps, c375e2 = 3.75 * e2;
+    double tx[T], ty[T], tz[T], acc[T][6];
+#pragma unroll
+    for (int t = 0; t < T; t++) {
+        const int li = min(tid + t * kBlock, it.ntgt - 1);
+        const RecF64 &r = rec[it.tgt0 + li];
+        tx[t] = r.x; ty[t] = r.y; tz[t] = r.z;
+#pragma unroll
+        for (int k = 0; k < 6; k++) acc[t][k] = 0.0;
+    }
+    const double2 *__restrict__ rw = reinterpret_cast<const double2 *>(rec);
+    for (int base = 0; base < it.nsrc; base += kSrcTile) {
+        __syncthreads();
+        const int j = base + tid;
+        double2 w0 = make_double2(0.0, 0.0), w1 = w0, w2 = w0, w3 = w0, w4 = w0;
+        if (j < it.nsrc) {
+            const double2 *src = rw + (size_t)(it.src0 + j) * 5;
+            w0 = src[0]; w1 = src[1]; w2 = src[2]; w3 = src[3]; w4 = src[4];
+        }
+        s0[tid] = w0; s1[tid] = w1; s2[tid] = w2; s3[tid] = w3; s4[tid] = w4;
+        __syncthreads();
+        const int cnt = min(kSrcTile, it.nsrc - base);
+#pragma unroll 2
+        for (int jj = 0; jj < cnt; jj++) {
+            const double2 a = s0[jj], b = s1[jj], cc = s2[jj], d = s3[jj], e = s4[jj];
+#pragma unroll
+            for (int t = 0; t < T; t++)
+                pair_f64(tx[t], ty[t], tz[t], a.x, a.y, b.x, b.y, cc.x, cc.y, d.x, d.y, e.x, e2, c375e2, acc[t]);
+        }
+    }
+    const int N = E.N;
+#pragma unroll
+    for (int t = 0; t < T; t++) {
+        const int li = tid + t * kBlock;
+        if (li < it.ntgt) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) E.part[((size_t)it.chunk * 6 + k) * N + it.tgt0 + li] = acc[t][k];
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Small-ensemble pair kernel: each wave owns kSplitTargetsPerWave targets and
+// its 64 lanes stride over the item's sources; per-lane sums are combined in
+// FP64 with a butterfly of wave shuffles in a fixed order.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restrict__ desc,
+                                                        const PairItem *__restrict__ items) {
+    constexpr int TW = kSplitTargetsPerWave;
+    const PairItem it = items[blockIdx.x];
+    const EnsDesc &E = desc[it.ens];
+    const int lane = threadIdx.x & 63;
+    const int tb = (threadIdx.x >> 6) * TW;
+    if (tb >= it.ntgt) return;  // whole wave idle (wave-uniform)
+    double out[TW][6];
+    if (PREC == 1) {
+        const RecF32 *__restrict__ rec = reinterpret_cast<const RecF32 *>(E.rec);
+        float thx[TW], thy[TW], thz[TW], tlx[TW], tly[TW], tlz[TW], s[TW][6], c[TW][6];
+        double pn[TW][6];
+#pragma unroll
+        for (int t = 0; t < TW; t++) {
+            const RecF32 r = rec[it.tgt0 + min(tb + t, it.ntgt - 1)];
+            thx[t] = r.a.x; thy[t] = r.a.y; thz[t] = r.a.z;
+            tlx[t] = r.b.x; tly[t] = r.b.y; tlz[t] = r.b.z;
+#pragma unroll
+            for (int k = 0; k < 6; k++) { s[t][k] = 0.f; c[t][k] = 0.f; pn[t][k] = 0.0; }
+        }
+        constexpr int kPerLane = 16;  // sources per lane between compensated updates
+        for (int j0 = 0; j0 < it.nsrc; j0 += 64 * kPerLane) {
+            float p[TW][6];
+            float rmin = kNearR2;
+#pragma unroll
+            for (int t = 0; t < TW; t++)
+#pragma unroll
+                for (int k = 0; k < 6; k++) p[t][k] = 0.f;
+            const int jend = min(j0 + 64 * kPerLane, it.nsrc);
+            for (int j = j0 + lane; j < jend; j += 64) {
+                const RecF32 r = rec[it.src0 + j];
+#pragma unroll
+                for (int t = 0; t < TW; t++)
+                    rmin = fminf(rmin, pair_f32<true>(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a, r.b, r.c, p[t]));
+            }
+#pragma unroll
+            for (int t = 0; t < TW; t++)
+#pragma unroll
+                for (int k = 0; k < 6; k++) kahan_add(s[t][k], c[t][k], p[t][k]);
+            if (rmin < kNearR2) {  // near pairs of this lane's sources: FP64
+                for (int j = j0 + lane; j < jend; j += 64) {
+                    const RecF32 r = rec[it.src0 + j];
+#pragma unroll
+                    for (int t = 0; t < TW; t++) {
+                        float rx, ry, rz;
+                        if (sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a.x, r.a.y, r.a.z, r.b.x, r.b.y,
+                                    r.b.z, rx, ry, rz) < kNearR2)
+                            near_pair_f64(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a.x, r.a.y, r.a.z, r.b.x,
+                                          r.b.y, r.b.z, r.a.w, r.b.w, r.c.x, r.c.y, r.c.z, r.c.w, pn[t]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < TW; t++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) out[t][k] = wave_sum(((double)s[t][k] - (double)c[t][k]) + pn[t][k]);
+    } else {
+        const RecF64 *__restrict__ rec = reinterpret_cast<const RecF64 *>(E.rec);
+        const double e2 = E.eps * E.eps, c375e2 = 3.75 * e2;
+        double tx[TW], ty[TW], tz[TW], acc[TW][6];
+#pragma unroll
+        for (int t = 0; t < TW; t++) {
+            const RecF64 &r = rec[it.tgt0 + min(tb + t, it.ntgt - 1)];
+            tx[t] = r.x; ty[t] = r.y; tz[t] = r.z;
+#pragma unroll
+            for (int k = 0; k < 6; k++) acc[t][k] = 0.0;
+        }
+        for (int j = lane; j < it.nsrc; j += 64) {
+            const RecF64 &r = rec[it.src0 + j];
+            const double x = r.x, y = r.y, z = r.z, fx = r.fx, fy = r.fy, fz = r.fz, nx = r.nx,
+                         ny = r.ny, nz = r.nz;
+#pragma unroll
+            for (int t = 0; t < TW; t++) pair_f64(tx[t], ty[t], tz[t], x, y, z, fx, fy, fz, nx, ny, nz, e2, c375e2, acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < TW; t++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) out[t][k] = wave_sum(acc[t][k]);
+    }
+    if (lane < 6) {
+        const int N = E.N;
+#pragma unroll
+        for (int t = 0; t < TW; t++) {
+            if (tb + t < it.ntgt) {
+                double v = out[t][0];
+#pragma unroll
+                for (int k = 1; k < 6; k++) v = (lane == k) ? out[t][k] : v;
+                E.part[((size_t)it.chunk * 6 + lane) * N + it.tgt0 + tb + t] = v;
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------- launch wrapper
+hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, const PairItem *d_items,
+                        int n_items, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const dim3 g(n_items), b(kBlock);  // the pair kernels index LDS by threadIdx.x < kBlock
+    if (mode == PAIR_SPLIT) {
+        if (prec == 1) hipLaunchKernelGGL(k_pairs_split<1>, g, b, 0, s, d_desc, d_items);
+        else hipLaunchKernelGGL(k_pairs_split<0>, g, b, 0, s, d_desc, d_items);
+    } else if (prec == 1) {
+        if (tpl == 2) hipLaunchKernelGGL(k_pairs_tile_f32<2>, g, b, 0, s, d_desc, d_items);
+        else hipLaunchKernelGGL(k_pairs_tile_f32<1>, g, b, 0, s, d_desc, d_items);
+    } else {
+        if (tpl == 2) hipLaunchKernelGGL(k_pairs_tile_f64<2>, g, b, 0, s, d_desc, d_items);
+        else hipLaunchKernelGGL(k_pairs_tile_f64<1>, g, b, 0, s, d_desc, d_items);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mrs
