@@ -21,6 +21,13 @@ listed in the tests under ``tests/test_oracle_*.py``):
                             energy dissipation under relaxation)
   step (Euler, RK2, RK4)    pinned (convergence orders 1, 2 and 4, reduction
                             of one RK stage to Euler, energy decay)
+  swimming waveform         pinned (a rod built in the preferred shape of
+                            time t carries no elastic load, and loads at
+                            other times; zero amplitude reduces to Omega_0)
+  lj_forces / lj_energy     pinned (closed-form pair force, force = minus the
+                            finite-difference gradient of the energy, cutoff,
+                            same-filament exclusion, zero total force and
+                            torque)
 Absolute U/Omega values of the configured workloads are "parity unpinned"
 by the paper itself, which prints none.
 """
@@ -72,6 +79,17 @@ def _load():
             lib.oracle_rodrigues.argtypes = [_d, _d, _d]
             lib.oracle_rod_forces.argtypes = [ctypes.c_int32, _i32, _d, _d, _d, _d, _d,
                                               ctypes.c_double, _d, _d, _d, _d]
+            lib.oracle_rod_forces_ex.argtypes = [ctypes.c_int32, _i32, _d, _d, _d, _d, _d, ctypes.c_double,
+                                                 _d, _d, _d, ctypes.c_double, _d, _d, _d]
+            lib.oracle_lj_forces.argtypes = [ctypes.c_int32, _i32, _d, _d, _d]
+            lib.oracle_lj_energy.restype = ctypes.c_double
+            lib.oracle_lj_energy.argtypes = [ctypes.c_int32, _i32, _d, _d]
+            lib.oracle_velocities_ex.argtypes = [ctypes.c_int32, _i32, _d, _d, _d, _d, _d, ctypes.c_double,
+                                                 _d, _d, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                 _d, ctypes.c_double, _d, _d, _d]
+            lib.oracle_step_ex.argtypes = [ctypes.c_int32, _i32, _d, _d, _d, _d, _d, ctypes.c_double, _d, _d,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_int32, ctypes.c_int, _d, _d, _d, _d, _d]
             lib.oracle_rod_energy.restype = ctypes.c_double
             lib.oracle_rod_energy.argtypes = [ctypes.c_int32, _i32, _d, _d, _d, _d, _d,
                                               ctypes.c_double]
@@ -169,19 +187,47 @@ def _rod_args(rod):
     return a, b, o, float(rod.ds)
 
 
-def rod_forces(offsets, X, D, rod, fext=None, next_=None):
-    """Point force g and torque m on the fluid per node (N x 3 each)."""
+def _wave(wave):
+    """(A, k, f) of the swimming waveform, or None."""
+    return None if wave is None else np.ascontiguousarray(wave, dtype=np.float64).reshape(3)
+
+
+def _lj(lj):
+    """(sigma, energy) of the Lennard-Jones repulsion, or None."""
+    return None if lj is None else np.ascontiguousarray(lj, dtype=np.float64).reshape(2)
+
+
+def rod_forces(offsets, X, D, rod, fext=None, next_=None, wave=None, t=0.0, lj=None):
+    """Point force g and torque m on the fluid per node (N x 3 each); with the
+    swimming waveform (A, k, f) at time t and the Lennard-Jones repulsion
+    (sigma, energy) when given."""
     off = np.ascontiguousarray(offsets, dtype=np.int32)
     X = _f64(X).reshape(-1, 3)
     D = _f64(D).reshape(-1, 9)
     a, b, o, ds = _rod_args(rod)
     fe = None if fext is None else _f64(fext).reshape(-1, 3)
     ne = None if next_ is None else _f64(next_).reshape(-1, 3)
+    wv, lp = _wave(wave), _lj(lj)
     g = np.zeros_like(X)
     m = np.zeros_like(X)
-    _load().oracle_rod_forces(len(off) - 1, off.ctypes.data_as(_i32), _p(X), _p(D), _p(a), _p(b),
-                              _p(o), ds, _p(fe), _p(ne), _p(g), _p(m))
+    _load().oracle_rod_forces_ex(len(off) - 1, off.ctypes.data_as(_i32), _p(X), _p(D), _p(a), _p(b),
+                                 _p(o), ds, _p(fe), _p(ne), _p(wv), float(t), _p(lp), _p(g), _p(m))
     return g, m
+
+
+def lj_forces(offsets, X, lj):
+    """Lennard-Jones force on every point from the points of other filaments."""
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    X = _f64(X).reshape(-1, 3)
+    F = np.zeros_like(X)
+    _load().oracle_lj_forces(len(off) - 1, off.ctypes.data_as(_i32), _p(X), _p(_lj(lj)), _p(F))
+    return F
+
+
+def lj_energy(offsets, X, lj) -> float:
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    X = _f64(X).reshape(-1, 3)
+    return _load().oracle_lj_energy(len(off) - 1, off.ctypes.data_as(_i32), _p(X), _p(_lj(lj)))
 
 
 def rod_energy(offsets, X, D, rod) -> float:
@@ -199,7 +245,7 @@ def reorthonormalize(D):
     return D
 
 
-def velocities(offsets, X, D, rod, fext, next_, eps, mu=1.0, include_elastic=True):
+def velocities(offsets, X, D, rod, fext, next_, eps, mu=1.0, include_elastic=True, wave=None, t=0.0, lj=None):
     off = np.ascontiguousarray(offsets, dtype=np.int32)
     X = _f64(X).reshape(-1, 3)
     D = _f64(D).reshape(-1, 9)
@@ -208,9 +254,10 @@ def velocities(offsets, X, D, rod, fext, next_, eps, mu=1.0, include_elastic=Tru
     ne = _f64(next_).reshape(-1, 3)
     U = np.zeros_like(X)
     W = np.zeros_like(X)
-    _load().oracle_velocities(len(off) - 1, off.ctypes.data_as(_i32), _p(X), _p(D), _p(a), _p(b),
-                              _p(o), ds, _p(fe), _p(ne), float(eps), float(mu),
-                              int(bool(include_elastic)), _p(U), _p(W))
+    _load().oracle_velocities_ex(len(off) - 1, off.ctypes.data_as(_i32), _p(X), _p(D), _p(a), _p(b),
+                                 _p(o), ds, _p(fe), _p(ne), float(eps), float(mu),
+                                 int(bool(include_elastic)), _p(_wave(wave)), float(t), _p(_lj(lj)),
+                                 _p(U), _p(W))
     return U, W
 
 
@@ -219,8 +266,10 @@ RK2 = 2
 RK4 = 4
 
 
-def step(offsets, X, D, rod, fext, next_, eps, mu, integrator, dt, nsteps, include_elastic=True):
-    """Advance (X, D) by nsteps; returns new X, D and first-stage U, Omega of the last step."""
+def step_ex(offsets, X, D, rod, fext, next_, eps, mu, integrator, dt, nsteps, include_elastic=True,
+            wave=None, t=0.0, lj=None):
+    """Advance (X, D) by nsteps from time t; returns new X, D, the first-stage
+    U, Omega of the last step and the new time (t advanced by dt per step)."""
     off = np.ascontiguousarray(offsets, dtype=np.int32)
     X = _f64(X).reshape(-1, 3).copy()
     D = _f64(D).reshape(-1, 9).copy()
@@ -229,9 +278,19 @@ def step(offsets, X, D, rod, fext, next_, eps, mu, integrator, dt, nsteps, inclu
     ne = _f64(next_).reshape(-1, 3)
     U = np.zeros_like(X)
     W = np.zeros_like(X)
-    _load().oracle_step(len(off) - 1, off.ctypes.data_as(_i32), _p(X), _p(D), _p(a), _p(b),
-                        _p(o), ds, _p(fe), _p(ne), float(eps), float(mu), int(integrator),
-                        float(dt), int(nsteps), int(bool(include_elastic)), _p(U), _p(W))
+    tt = np.array([float(t)])
+    _load().oracle_step_ex(len(off) - 1, off.ctypes.data_as(_i32), _p(X), _p(D), _p(a), _p(b),
+                           _p(o), ds, _p(fe), _p(ne), float(eps), float(mu), int(integrator),
+                           float(dt), int(nsteps), int(bool(include_elastic)), _p(_wave(wave)), _p(tt),
+                           _p(_lj(lj)), _p(U), _p(W))
+    return X, D, U, W, float(tt[0])
+
+
+def step(offsets, X, D, rod, fext, next_, eps, mu, integrator, dt, nsteps, include_elastic=True,
+         wave=None, t=0.0, lj=None):
+    """Advance (X, D) by nsteps; returns new X, D and first-stage U, Omega of the last step."""
+    X, D, U, W, _ = step_ex(offsets, X, D, rod, fext, next_, eps, mu, integrator, dt, nsteps, include_elastic,
+                            wave, t, lj)
     return X, D, U, W
 
 

@@ -25,6 +25,10 @@
  *   - Rodrigues frame update              Sec. III.B.3, Eqs. newx, newD
  *   - RK4 stage scheme                    Sec. III.A (fine propagator is an
  *                                         explicit Runge-Kutta method)
+ *   - swimming waveform                   Sec. IV (preferred strain-twist
+ *                                         vector (0, -k^2 A sin(ks + ft), 0))
+ *   - Lennard-Jones repulsion             Sec. IV (potential 4e((s/r)^12 -
+ *                                         (s/r)^6) below r_c = 2^(1/6) s)
  *
  * Layouts: positions, forces, torques, velocities are row-major n x 3.
  * Frames are n x 9 with D[9k + 3i + c] = component c of director D^{i+1}
@@ -274,9 +278,73 @@ void oracle_rodrigues(const double *v, const double *D, double *out) {
  * point force and torque the node exerts on the fluid are -ds f_k and
  * -ds n_k; the external point loads fext, next are added to them.
  */
-void oracle_rod_forces(int32_t nfil, const int32_t *off, const double *X, const double *D,
-                       const double *a, const double *b, const double *om0, double ds,
-                       const double *fext, const double *next, double *g, double *m) {
+/*
+ * Swimming (Sec. IV): with wave = (A, k, f), the preferred strain-twist
+ * vector of segment k+1/2 at time t is om0 + (0, -k^2 A sin(k s + f t), 0)
+ * with s = (k + 1/2) ds its arclength, the segment midpoint.
+ */
+static void preferred_strain(const double *om0, const double *wave, double t, double s, double *om) {
+    om[0] = om0[0];
+    om[1] = om0[1];
+    om[2] = om0[2];
+    if (wave) om[1] += -wave[1] * wave[1] * wave[0] * sin(wave[1] * s + wave[2] * t);
+}
+
+/*
+ * Lennard-Jones repulsion between points of different filaments (Sec. IV):
+ * U(r) = 4 e ((sig/r)^12 - (sig/r)^6) for r < r_c = 2^(1/6) sig, zero beyond,
+ * lj = (sig, e).  The force on point j is -grad_j of the pair energies,
+ *   F_j = sum_i 24 e (2 (sig/r)^12 - (sig/r)^6) (x_j - x_i) / r^2,
+ * over points i of other filaments with r = |x_j - x_i| < r_c.  It is a force
+ * on the rod point, which a massless point passes on to the fluid, so it is
+ * added to the point force on the fluid like an external load.
+ */
+void oracle_lj_forces(int32_t nfil, const int32_t *off, const double *X, const double *lj, double *F) {
+    const int64_t n = off[nfil];
+    const double sig = lj[0], e = lj[1], rc = pow(2.0, 1.0 / 6.0) * sig;
+    int32_t *fil = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int32_t fi = 0; fi < nfil; fi++)
+        for (int32_t k = off[fi]; k < off[fi + 1]; k++) fil[k] = fi;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; j++) {
+        double acc[3] = {0, 0, 0};
+        for (int64_t i = 0; i < n; i++) {
+            if (fil[i] == fil[j]) continue;
+            double r[3] = {X[3 * j] - X[3 * i], X[3 * j + 1] - X[3 * i + 1], X[3 * j + 2] - X[3 * i + 2]};
+            double r2 = dot3(r, r), rr = sqrt(r2);
+            if (rr >= rc) continue;
+            double s6 = pow(sig / rr, 6.0);
+            double c = 24.0 * e * (2.0 * s6 * s6 - s6) / r2;
+            for (int q = 0; q < 3; q++) acc[q] += c * r[q];
+        }
+        for (int q = 0; q < 3; q++) F[3 * j + q] = acc[q];
+    }
+    free(fil);
+}
+
+/* Total Lennard-Jones energy, each pair of points of different filaments once. */
+double oracle_lj_energy(int32_t nfil, const int32_t *off, const double *X, const double *lj) {
+    const double sig = lj[0], e = lj[1], rc = pow(2.0, 1.0 / 6.0) * sig;
+    double E = 0.0;
+    for (int32_t fa = 0; fa < nfil; fa++)
+        for (int32_t fb = fa + 1; fb < nfil; fb++)
+            for (int32_t i = off[fa]; i < off[fa + 1]; i++)
+                for (int32_t j = off[fb]; j < off[fb + 1]; j++) {
+                    double r[3] = {X[3 * j] - X[3 * i], X[3 * j + 1] - X[3 * i + 1], X[3 * j + 2] - X[3 * i + 2]};
+                    double rr = sqrt(dot3(r, r));
+                    if (rr >= rc) continue;
+                    double s6 = pow(sig / rr, 6.0);
+                    E += 4.0 * e * (s6 * s6 - s6);
+                }
+    return E;
+}
+
+/* oracle_rod_forces with the swimming waveform at time t (wave may be NULL)
+ * and the Lennard-Jones repulsion (lj may be NULL). */
+void oracle_rod_forces_ex(int32_t nfil, const int32_t *off, const double *X, const double *D,
+                          const double *a, const double *b, const double *om0, double ds,
+                          const double *fext, const double *next, const double *wave, double t,
+                          const double *lj, double *g, double *m) {
     for (int32_t fi = 0; fi < nfil; fi++) {
         int32_t k0 = off[fi], M = off[fi + 1] - off[fi];
         int32_t nseg = M > 1 ? M - 1 : 0;
@@ -304,11 +372,13 @@ void oracle_rod_forces(int32_t nfil, const int32_t *off, const double *X, const 
                                     (j == 2 ? 1.0 : 0.0));
                 for (int c = 0; c < 3; c++) F[c] += Fj * Dh[3 * j + c];
             }
+            double om[3];
+            preferred_strain(om0, wave, t, (k + 0.5) * ds, om);
             for (int i = 0; i < 3; i++) {
                 int j = (i + 1) % 3, l = (i + 2) % 3;
                 double dd[3];
                 for (int c = 0; c < 3; c++) dd[c] = (Dk1[3 * j + c] - Dk[3 * j + c]) / ds;
-                double Ni = a[i] * (dot3(dd, Dh + 3 * l) - om0[i]);
+                double Ni = a[i] * (dot3(dd, Dh + 3 * l) - om[i]);
                 for (int c = 0; c < 3; c++) Nv[c] += Ni * Dh[3 * i + c];
             }
             memcpy(Fs + 3 * k, F, sizeof F);
@@ -335,6 +405,19 @@ void oracle_rod_forces(int32_t nfil, const int32_t *off, const double *X, const 
         free(Ns);
         free(dXs);
     }
+    if (lj) {
+        const int64_t n = off[nfil];
+        double *F = malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+        oracle_lj_forces(nfil, off, X, lj, F);
+        for (int64_t i = 0; i < 3 * n; i++) g[i] += F[i];
+        free(F);
+    }
+}
+
+void oracle_rod_forces(int32_t nfil, const int32_t *off, const double *X, const double *D,
+                       const double *a, const double *b, const double *om0, double ds,
+                       const double *fext, const double *next, double *g, double *m) {
+    oracle_rod_forces_ex(nfil, off, X, D, a, b, om0, ds, fext, next, NULL, 0.0, NULL, g, m);
 }
 
 /* Elastic energy sum over segments ds (sum_j b_j e_j^2 + sum_i a_i k_i^2)/2 of
@@ -400,24 +483,42 @@ static void rotate_frames(int64_t n, const double *W, double h, const double *Di
 }
 
 /* Velocities of a rod state: rod forces plus external loads, then the MRS sum.
- * With include_elastic == 0 only the external loads drive the fluid. */
-void oracle_velocities(int32_t nfil, const int32_t *off, const double *X, const double *D,
-                       const double *a, const double *b, const double *om0, double ds,
-                       const double *fext, const double *next, double eps, double mu,
-                       int include_elastic, double *U, double *W) {
+ * With include_elastic == 0 only the external loads drive the fluid.  The
+ * _ex form adds the swimming waveform at time t (wave may be NULL) to the rod
+ * forces and the Lennard-Jones repulsion (lj may be NULL) to the point forces,
+ * the latter with or without the elastic forces. */
+void oracle_velocities_ex(int32_t nfil, const int32_t *off, const double *X, const double *D,
+                          const double *a, const double *b, const double *om0, double ds,
+                          const double *fext, const double *next, double eps, double mu,
+                          int include_elastic, const double *wave, double t, const double *lj,
+                          double *U, double *W) {
     int64_t n = off[nfil];
     double *g = malloc(sizeof(double) * 3 * (size_t)n), *m = malloc(sizeof(double) * 3 * (size_t)n);
     if (include_elastic) {
-        oracle_rod_forces(nfil, off, X, D, a, b, om0, ds, fext, next, g, m);
+        oracle_rod_forces_ex(nfil, off, X, D, a, b, om0, ds, fext, next, wave, t, NULL, g, m);
     } else {
         for (int64_t i = 0; i < 3 * n; i++) {
             g[i] = fext ? fext[i] : 0.0;
             m[i] = next ? next[i] : 0.0;
         }
     }
+    if (lj) {
+        double *F = malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+        oracle_lj_forces(nfil, off, X, lj, F);
+        for (int64_t i = 0; i < 3 * n; i++) g[i] += F[i];
+        free(F);
+    }
     oracle_mrs_eval(n, X, g, m, eps, mu, U, W);
     free(g);
     free(m);
+}
+
+void oracle_velocities(int32_t nfil, const int32_t *off, const double *X, const double *D,
+                       const double *a, const double *b, const double *om0, double ds,
+                       const double *fext, const double *next, double eps, double mu,
+                       int include_elastic, double *U, double *W) {
+    oracle_velocities_ex(nfil, off, X, D, a, b, om0, ds, fext, next, eps, mu, include_elastic, NULL, 0.0,
+                         NULL, U, W);
 }
 
 /*
@@ -433,20 +534,25 @@ void oracle_velocities(int32_t nfil, const int32_t *off, const double *X, const 
  *               propagator uses (Sec. III.A, n = 2), taken as the midpoint
  *               rule: nodes c = (0, 1/2), weights (0, 1), same stage form.
  * Every step ends with oracle_reorthonormalize.  U, W (may be NULL) receive
- * the velocities of the first stage of the last step.
+ * the velocities of the first stage of the last step.  The _ex form carries
+ * the time of the swimming waveform: stage s of a step that starts at time t
+ * is evaluated at t + c_s dt, and t advances by dt per step (t in/out, may be
+ * NULL for t = 0).
  */
-void oracle_step(int32_t nfil, const int32_t *off, double *X, double *D,
-                 const double *a, const double *b, const double *om0, double ds,
-                 const double *fext, const double *next, double eps, double mu,
-                 int integrator, double dt, int32_t nsteps, int include_elastic,
-                 double *Uout, double *Wout) {
+void oracle_step_ex(int32_t nfil, const int32_t *off, double *X, double *D,
+                    const double *a, const double *b, const double *om0, double ds,
+                    const double *fext, const double *next, double eps, double mu,
+                    int integrator, double dt, int32_t nsteps, int include_elastic,
+                    const double *wave, double *t, const double *lj, double *Uout, double *Wout) {
+    double tnow = t ? *t : 0.0;
     int64_t n = off[nfil];
     size_t v3 = sizeof(double) * 3 * (size_t)n, v9 = sizeof(double) * 9 * (size_t)n;
     double *U = malloc(v3), *W = malloc(v3), *Ua = malloc(v3), *Wa = malloc(v3);
     double *Xs = malloc(v3), *Ds = malloc(v9);
     for (int32_t step = 0; step < nsteps; step++) {
         if (integrator == 1) {
-            oracle_velocities(nfil, off, X, D, a, b, om0, ds, fext, next, eps, mu, include_elastic, U, W);
+            oracle_velocities_ex(nfil, off, X, D, a, b, om0, ds, fext, next, eps, mu, include_elastic, wave, tnow,
+                                 lj, U, W);
             if (Uout && step == nsteps - 1) memcpy(Uout, U, v3);
             if (Wout && step == nsteps - 1) memcpy(Wout, W, v3);
             for (int64_t i = 0; i < 3 * n; i++) X[i] += dt * U[i];
@@ -470,7 +576,8 @@ void oracle_step(int32_t nfil, const int32_t *off, double *X, double *D,
                     for (int64_t i = 0; i < 3 * n; i++) Xs[i] = X[i] + cnode[s] * dt * U[i];
                     rotate_frames(n, W, cnode[s] * dt, D, Ds);
                 }
-                oracle_velocities(nfil, off, Xs, Ds, a, b, om0, ds, fext, next, eps, mu, include_elastic, U, W);
+                oracle_velocities_ex(nfil, off, Xs, Ds, a, b, om0, ds, fext, next, eps, mu, include_elastic, wave,
+                                     tnow + cnode[s] * dt, lj, U, W);
                 if (s == 0 && step == nsteps - 1) {
                     if (Uout) memcpy(Uout, U, v3);
                     if (Wout) memcpy(Wout, W, v3);
@@ -485,6 +592,17 @@ void oracle_step(int32_t nfil, const int32_t *off, double *X, double *D,
             memcpy(D, Ds, v9);
         }
         oracle_reorthonormalize(n, D);
+        tnow += dt;
     }
+    if (t) *t = tnow;
     free(U); free(W); free(Ua); free(Wa); free(Xs); free(Ds);
+}
+
+void oracle_step(int32_t nfil, const int32_t *off, double *X, double *D,
+                 const double *a, const double *b, const double *om0, double ds,
+                 const double *fext, const double *next, double eps, double mu,
+                 int integrator, double dt, int32_t nsteps, int include_elastic,
+                 double *Uout, double *Wout) {
+    oracle_step_ex(nfil, off, X, D, a, b, om0, ds, fext, next, eps, mu, integrator, dt, nsteps, include_elastic,
+                   NULL, NULL, NULL, Uout, Wout);
 }
