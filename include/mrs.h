@@ -150,6 +150,24 @@ mrs_status mrs_ensemble_create(mrs_context *ctx, int32_t n_fil, const int32_t *o
 mrs_status mrs_ensemble_set_state(mrs_ensemble *ens, const double *X, const double *D);
 /* Number of points. */
 mrs_status mrs_ensemble_size(const mrs_ensemble *ens, int64_t *n);
+/* Swimming (Sec. IV).  wave = (A, k, f), or NULL to switch it off: the
+ * preferred strain-twist of segment k+1/2 becomes omega0 +
+ * (0, -k^2 A sin(k s + f t), 0) at its midpoint arclength s = (k + 1/2) ds
+ * and at the time t of the stage (step start + c_s dt for RK stage s).
+ * lj = (sigma, energy), or NULL to switch it off: points of different
+ * filaments closer than r_c = 2^(1/6) sigma repel with the force
+ * -grad of 4 energy ((sigma/r)^12 - (sigma/r)^6), added to the point force
+ * the node exerts on the fluid (with or without the elastic forces).
+ * Host arrays, copied.  Errors: MRS_EINVAL for non-finite values,
+ * sigma <= 0 or energy < 0; MRS_ENOMEM for the LJ buffers (3 doubles,
+ * one int32 per point).  Cached plans and graphs of the ensemble are rebuilt
+ * at its next launch. */
+mrs_status mrs_ensemble_set_swimming(mrs_ensemble *ens, const double *wave, const double *lj);
+/* The ensemble clock: the time of the start of its next step (0 at
+ * creation).  Every step advances it by dt on the device, so that graph
+ * replays and batched steps keep it; MRS_EINVAL for a non-finite t. */
+mrs_status mrs_ensemble_set_time(mrs_ensemble *ens, double t);
+mrs_status mrs_ensemble_get_time(mrs_ensemble *ens, double *t);
 /* U, Omega at the current state from the rod forces (if include_elastic)
  * plus the external loads. */
 mrs_status mrs_ensemble_eval(mrs_ensemble *ens, mrs_precision prec, int include_elastic);
@@ -291,7 +309,9 @@ mrs_status mrs_tune_set(mrs_context *ctx, int64_t n, mrs_precision prec, const m
  * at the end of the last slice; history (max_iter doubles, may be NULL)
  * receives the increments, *iters (may be NULL) the iterations done.  All
  * state stays on the device; one host copy of the positions per iteration
- * evaluates the increment. */
+ * evaluates the increment.  Each propagation of slice n starts at the slice
+ * boundary time (the ensemble clock plus n fine steps, accumulated as the
+ * serial run would), and the clock ends at the last boundary. */
 mrs_status mrs_parareal(mrs_ensemble *ens, int32_t n_slices, mrs_integrator fine_integ, double fine_dt,
                         int32_t fine_steps, int32_t coarse_steps, int32_t max_iter, double tol,
                         mrs_precision prec, int include_elastic, double *history, int32_t *iters);

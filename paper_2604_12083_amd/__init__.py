@@ -100,6 +100,9 @@ _SIGS = {
                                    ctypes.POINTER(mrs_rod_params), ctypes.POINTER(_vp)]),
     "mrs_ensemble_set_state": (_int, [_vp, _vp, _vp]),
     "mrs_ensemble_size": (_int, [_vp, ctypes.POINTER(_i64)]),
+    "mrs_ensemble_set_swimming": (_int, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
+    "mrs_ensemble_set_time": (_int, [_vp, _dbl]),
+    "mrs_ensemble_get_time": (_int, [_vp, ctypes.POINTER(_dbl)]),
     "mrs_ensemble_eval": (_int, [_vp, _int, _int]),
     "mrs_ensemble_step": (_int, [_vp, _int, _dbl, ctypes.c_int32, _int, _int]),
     "mrs_ensemble_get": (_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -257,6 +260,23 @@ def mrs_ensemble_size(ens) -> int:
     n = _i64()
     _check(_lib.mrs_ensemble_size(ens, ctypes.byref(n)))
     return int(n.value)
+
+
+def mrs_ensemble_set_swimming(ctx, ens, wave=None, lj=None) -> None:
+    """Swimming waveform (A, k, f) and Lennard-Jones repulsion (sigma, energy); None switches either off."""
+    w = None if wave is None else (_dbl * 3)(*[float(v) for v in wave])
+    l = None if lj is None else (_dbl * 2)(*[float(v) for v in lj])
+    _check(_lib.mrs_ensemble_set_swimming(ens, w, l), ctx)
+
+
+def mrs_ensemble_set_time(ctx, ens, t) -> None:
+    _check(_lib.mrs_ensemble_set_time(ens, float(t)), ctx)
+
+
+def mrs_ensemble_get_time(ctx, ens) -> float:
+    t = _dbl()
+    _check(_lib.mrs_ensemble_get_time(ens, ctypes.byref(t)), ctx)
+    return t.value
 
 
 def mrs_ensemble_eval(ctx, ens, prec=MRS_FP64, include_elastic=True) -> None:

@@ -52,8 +52,21 @@ struct EnsDesc {
     double a[3], b[3], om0[3], ds;
     double dt;         // step size used when a launch passes dt = NaN
     int32_t elastic;   // rod forces on/off used when a launch passes elastic < 0
+    // swimming (Sec. IV): waveform (A, k, f) added to the preferred
+    // strain-twist, Lennard-Jones repulsion between filaments
+    int32_t has_wave, has_lj;
     int32_t pad_;
+    double wave[3];
+    double lj_sig, lj_e, lj_rc;
+    double *clock;          // time at the start of the current step (one double)
+    const int32_t *fil;     // filament of each point (with LJ)
+    double *flj;            // LJ force on each point [3][N] (with LJ)
+    double *lj_box;         // per 64-point block: lo[3], hi[3] of the positions (with LJ)
+    int32_t *lj_flag;       // per 64-point block: 1 if a point of it feels a LJ force (with LJ)
 };
+
+// Points per box of the Lennard-Jones neighbour culling.
+constexpr int kLjBoxPoints = 64;
 
 // One block of a pair kernel: targets [tgt0, tgt0 + ntgt) against sources
 // [src0, src0 + nsrc) of ensemble `ens`, written to split-K chunk `chunk`.
@@ -89,9 +102,15 @@ enum RkScheme : int { RK_SCHEME_RK4 = 0, RK_SCHEME_RK2 = 1 };
 // Launch wrappers (mrs_pairs.hip, mrs_kernels.hip).  All return the launch's hipError_t.
 hipError_t launch_pack_aos(int prec, const EnsDesc *d_desc, const EnsDesc &h_desc,
                            hipStream_t s);
-// elastic < 0: every ensemble uses its own EnsDesc::elastic.
-hipError_t launch_rod_forces(int prec, int stage_state, int elastic, const EnsDesc *d_desc,
-                             const RodItem *d_items, int n_items, hipStream_t s);
+// elastic < 0: every ensemble uses its own EnsDesc::elastic.  The waveform
+// time of the launch is clock + c dt, c the node of RK stage `stage` of
+// `scheme` (0 for stage 0); dt = NaN: every ensemble uses its own dt.
+hipError_t launch_rod_forces(int prec, int stage_state, int elastic, int scheme, int stage, double dt,
+                             const EnsDesc *d_desc, const RodItem *d_items, int n_items, hipStream_t s);
+// Lennard-Jones forces of the ensembles with has_lj: boxes of every
+// kLjBoxPoints-point block, then the force on every point.  Items are
+// (ensemble, first point) of kBlock consecutive points.
+hipError_t launch_lj(int stage_state, const EnsDesc *d_desc, const PointItem *d_items, int n_items, hipStream_t s);
 hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, const PairItem *d_items,
                         int n_items, hipStream_t s);
 // dt = NaN: every ensemble uses its own EnsDesc::dt.

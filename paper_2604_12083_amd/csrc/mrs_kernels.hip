@@ -160,9 +160,26 @@ __global__ __launch_bounds__(kBlock) void k_pack_aos(int prec, const EnsDesc *__
 }
 
 // F and N of the segment between nodes ka and kb = ka + 1 (SoA state of N points).
+// Explicit Runge-Kutta schemes whose stage s + 1 depends on stage s only:
+// weights w_s and the node c_{s+1} of the next stage.  Scheme 0 is the
+// classical RK4, scheme 1 the midpoint RK2.
+__constant__ double kRkWeight[2][4] = {{1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0}, {0.0, 1.0, 0.0, 0.0}};
+__constant__ double kRkNextNode[2][3] = {{0.5, 0.5, 1.0}, {0.5, 0.0, 0.0}};
+
+// Preferred strain-twist of a segment at arclength s and time t: the
+// intrinsic vector plus, for a swimmer, (0, -k^2 A sin(k s + f t), 0)
+// (Sec. IV).
+__device__ __forceinline__ void preferred_strain(const EnsDesc &E, double s, double t, double *om) {
+    om[0] = E.om0[0];
+    om[1] = E.om0[1];
+    om[2] = E.om0[2];
+    if (E.has_wave) om[1] += -E.wave[1] * E.wave[1] * E.wave[0] * sin(E.wave[1] * s + E.wave[2] * t);
+}
+
+// Segment ka -> kb = ka + 1 at arclength s_mid (its midpoint) and time t.
 __device__ __forceinline__ void rod_segment(const EnsDesc &E, const double *__restrict__ X,
                                             const double *__restrict__ D, int N, int ka, int kb,
-                                            double *F, double *Nv, double *dX) {
+                                            double s_mid, double t, double *F, double *Nv, double *dX) {
     double Da[9], Db[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) {
@@ -193,11 +210,13 @@ __device__ __forceinline__ void rod_segment(const EnsDesc &E, const double *__re
         const double Fj = E.b[j] * str;
         F[0] += Fj * Dh[3 * j]; F[1] += Fj * Dh[3 * j + 1]; F[2] += Fj * Dh[3 * j + 2];
     }
+    double om[3];
+    preferred_strain(E, s_mid, t, om);
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         const int j = (i + 1) % 3, l = (i + 2) % 3;
         const double kap = ((Db[3 * j] - Da[3 * j]) * Dh[3 * l] + (Db[3 * j + 1] - Da[3 * j + 1]) * Dh[3 * l + 1] +
-                            (Db[3 * j + 2] - Da[3 * j + 2]) * Dh[3 * l + 2]) * ids - E.om0[i];
+                            (Db[3 * j + 2] - Da[3 * j + 2]) * Dh[3 * l + 2]) * ids - om[i];
         const double Ni = E.a[i] * kap;
         Nv[0] += Ni * Dh[3 * i]; Nv[1] += Ni * Dh[3 * i + 1]; Nv[2] += Ni * Dh[3 * i + 2];
     }
@@ -206,8 +225,8 @@ __device__ __forceinline__ void rod_segment(const EnsDesc &E, const double *__re
 // One block per filament; the filament is walked in chunks of kBlock - 1
 // nodes.  Thread t computes segment c0 - 1 + t into LDS, then node c0 + t
 // combines its two neighbouring segments.
-__global__ __launch_bounds__(kBlock) void k_rod_forces(int prec, int stage_state, int elastic,
-                                                       const EnsDesc *__restrict__ desc,
+__global__ __launch_bounds__(kBlock) void k_rod_forces(int prec, int stage_state, int elastic, int scheme,
+                                                       int stage, double dt, const EnsDesc *__restrict__ desc,
                                                        const RodItem *__restrict__ items) {
     __shared__ double sF[3][kBlock], sN[3][kBlock], sX[3][kBlock];
     const RodItem it = items[blockIdx.x];
@@ -219,6 +238,12 @@ __global__ __launch_bounds__(kBlock) void k_rod_forces(int prec, int stage_state
     const int M = E.off[it.fil + 1] - k0;
     const int tid = threadIdx.x;
     if (elastic < 0) elastic = E.elastic;
+    // waveform time of this stage: step start + c_stage dt
+    double t = 0.0;
+    if (E.has_wave) {
+        if (dt != dt) dt = E.dt;
+        t = *E.clock + (stage > 0 ? kRkNextNode[scheme][stage - 1] : 0.0) * dt;
+    }
     for (int c0 = 0; c0 < M; c0 += kBlock - 1) {
         // this thread's node: its external loads and position, loaded before
         // the segment work so that the two memory latencies overlap
@@ -231,13 +256,15 @@ __global__ __launch_bounds__(kBlock) void k_rod_forces(int prec, int stage_state
             for (int c = 0; c < 3; c++) {
                 if (E.fext) g[c] = E.fext[(size_t)c * N + p];
                 if (E.next) m[c] = E.next[(size_t)c * N + p];
+                if (E.has_lj) g[c] += E.flj[(size_t)c * N + p];
                 xp[c] = X[(size_t)c * N + p];
             }
         }
         if (elastic) {
             const int s = c0 - 1 + tid;
             double F[3] = {0.0, 0.0, 0.0}, Nv[3] = {0.0, 0.0, 0.0}, dX[3] = {0.0, 0.0, 0.0};
-            if (s >= 0 && s <= M - 2) rod_segment(E, X, D, N, k0 + s, k0 + s + 1, F, Nv, dX);
+            if (s >= 0 && s <= M - 2)
+                rod_segment(E, X, D, N, k0 + s, k0 + s + 1, (s + 0.5) * E.ds, t, F, Nv, dX);
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 sF[c][tid] = F[c];
@@ -276,13 +303,109 @@ __global__ __launch_bounds__(kBlock) void k_rod_forces(int prec, int stage_state
     }
 }
 
-// ------------------------------------------------------- reduce + epilogue
+// ------------------------------------------------------------ Lennard-Jones
 
-// Explicit Runge-Kutta schemes whose stage s + 1 depends on stage s only:
-// weights w_s and the node c_{s+1} of the next stage.  Scheme 0 is the
-// classical RK4, scheme 1 the midpoint RK2.
-__constant__ double kRkWeight[2][4] = {{1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0}, {0.0, 1.0, 0.0, 0.0}};
-__constant__ double kRkNextNode[2][3] = {{0.5, 0.5, 1.0}, {0.5, 0.0, 0.0}};
+__device__ __forceinline__ double wave_min_d(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Box of every kLjBoxPoints-point block of the (stage) positions: a block of
+// threads covers kBlock points, one box per wave.
+__global__ __launch_bounds__(kBlock) void k_lj_boxes(int stage_state, const EnsDesc *__restrict__ desc,
+                                                     const PointItem *__restrict__ items) {
+    const PointItem it = items[blockIdx.x];
+    const EnsDesc &E = desc[it.ens];
+    const int N = E.N;
+    const int wbase = it.p0 + (int)(threadIdx.x & ~63u);
+    if (wbase >= N) return;  // wave-uniform: no point of this wave exists
+    const double *__restrict__ X = stage_state ? E.Xs : E.X;
+    const int i = it.p0 + (int)threadIdx.x;
+    const bool real = i < N;
+    double lo[3], hi[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const double v = real ? X[(size_t)c * N + i] : 0.0;
+        lo[c] = wave_min_d(real ? v : INFINITY);
+        hi[c] = wave_max_d(real ? v : -INFINITY);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        double *bx = E.lj_box + 6 * (size_t)(wbase / kLjBoxPoints);
+#pragma unroll
+        for (int c = 0; c < 3; c++) { bx[c] = lo[c]; bx[3 + c] = hi[c]; }
+    }
+}
+
+// Lennard-Jones force on every point (Sec. IV): the sum over points of other
+// filaments closer than r_c of 24 e (2 (sig/r)^12 - (sig/r)^6) (x_i - x_j)/r^2,
+// in source order.  A wave skips every source block whose box lies at least
+// r_c from the box of its own 64 points.  It also flags its block when any of
+// its points is pushed: the FP32C pair kernels sum such source blocks in
+// FP64, since the equal and opposite contact forces largely cancel at a
+// distance and FP32 terms would leave their rounding behind.
+__global__ __launch_bounds__(kBlock) void k_lj_forces(int stage_state, const EnsDesc *__restrict__ desc,
+                                                      const PointItem *__restrict__ items) {
+    const PointItem it = items[blockIdx.x];
+    const EnsDesc &E = desc[it.ens];
+    const int N = E.N;
+    const int wbase = it.p0 + (int)(threadIdx.x & ~63u);
+    if (wbase >= N) return;  // wave-uniform
+    const double *__restrict__ X = stage_state ? E.Xs : E.X;
+    const int i = it.p0 + (int)threadIdx.x;
+    const bool real = i < N;
+    const int ii = real ? i : N - 1;
+    const double x0 = X[ii], x1 = X[(size_t)N + ii], x2 = X[2 * (size_t)N + ii];
+    const int fi = E.fil[ii];
+    const double xs[3] = {x0, x1, x2};
+    double lo[3], hi[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        lo[c] = wave_min_d(real ? xs[c] : INFINITY);
+        hi[c] = wave_max_d(real ? xs[c] : -INFINITY);
+    }
+    const double rc = E.lj_rc, rc2 = rc * rc, sig2 = E.lj_sig * E.lj_sig, c24 = 24.0 * E.lj_e;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int nb = (N + kLjBoxPoints - 1) / kLjBoxPoints;
+    for (int b = 0; b < nb; b++) {
+        const double *bx = E.lj_box + 6 * (size_t)b;
+        double gap2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const double g = fmax(0.0, fmax(lo[c] - bx[3 + c], bx[c] - hi[c]));
+            gap2 += g * g;
+        }
+        if (!(gap2 < rc2)) continue;  // wave-uniform
+        const int j1 = min(N, (b + 1) * kLjBoxPoints);
+        for (int j = b * kLjBoxPoints; j < j1; j++) {
+            if (E.fil[j] == fi) continue;
+            const double r0 = x0 - X[j], r1 = x1 - X[(size_t)N + j], r2 = x2 - X[2 * (size_t)N + j];
+            const double rr2 = r0 * r0 + r1 * r1 + r2 * r2;
+            if (!(sqrt(rr2) < rc)) continue;
+            const double s2 = sig2 / rr2, s6 = s2 * s2 * s2;
+            const double cf = c24 * (2.0 * s6 * s6 - s6) / rr2;
+            acc[0] += cf * r0;
+            acc[1] += cf * r1;
+            acc[2] += cf * r2;
+        }
+    }
+    if (real) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) E.flj[(size_t)c * N + i] = acc[c];
+    }
+    // this wave's 64 points are one block: flag it when any point is pushed
+    const bool pushed = real && (acc[0] != 0.0 || acc[1] != 0.0 || acc[2] != 0.0);
+    const int any = __any(pushed ? 1 : 0);
+    if ((threadIdx.x & 63) == 0) E.lj_flag[wbase / kLjBoxPoints] = any ? 1 : 0;
+}
+
+// ------------------------------------------------------- reduce + epilogue
 
 __device__ __forceinline__ void rotate_frame(const double *din, double *__restrict__ Dout, int N, int i,
                                              double vx, double vy, double vz, bool reorth) {
@@ -350,6 +473,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(int stage, int scheme
         acc[c] = v;
     }
     if (dt != dt) dt = E.dt;  // NaN: per-ensemble step size
+    // the step's last epilogue advances the ensemble clock (one writer)
+    if ((EPI == EPI_EULER || EPI == EPI_RK_FINAL) && i == 0 && E.clock) *E.clock += dt;
     const double U[3] = {acc[0] * E.cU, acc[1] * E.cU, acc[2] * E.cU};
     const double W[3] = {acc[3] * E.cW, acc[4] * E.cW, acc[5] * E.cW};
     if (EPI == EPI_WRITE) {
@@ -441,11 +566,20 @@ hipError_t launch_pack_aos(int prec, const EnsDesc *d_desc, const EnsDesc &h_des
     return hipGetLastError();
 }
 
-hipError_t launch_rod_forces(int prec, int stage_state, int elastic, const EnsDesc *d_desc,
-                             const RodItem *d_items, int n_items, hipStream_t s) {
+hipError_t launch_rod_forces(int prec, int stage_state, int elastic, int scheme, int stage, double dt,
+                             const EnsDesc *d_desc, const RodItem *d_items, int n_items, hipStream_t s) {
     if (n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rod_forces, dim3(n_items), dim3(kBlock), 0, s, prec, stage_state, elastic,
-                       d_desc, d_items);
+    hipLaunchKernelGGL(k_rod_forces, dim3(n_items), dim3(kBlock), 0, s, prec, stage_state, elastic, scheme,
+                       stage, dt, d_desc, d_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_lj(int stage_state, const EnsDesc *d_desc, const PointItem *d_items, int n_items, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lj_boxes, dim3(n_items), dim3(kBlock), 0, s, stage_state, d_desc, d_items);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lj_forces, dim3(n_items), dim3(kBlock), 0, s, stage_state, d_desc, d_items);
     return hipGetLastError();
 }
 

@@ -265,7 +265,12 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
             }
             const float *bx = sBox[sb / kKahanBlock];
             const float gap2 = box_gap2(tlo, thi, bx, bx + 3);
-            if (gap2 > kFarBoxGap2 && gap2 > kAnchorGapRatio2 * bx[9]) {
+            if (E.lj_flag && E.lj_flag[(it.src0 + base + sb) / kLjBoxPoints]) {
+                // a block carrying contact forces (wave-uniform): every pair
+                // goes to the FP64 pass below
+#pragma unroll
+                for (int t = 0; t < T; t++) near[t] = ~uint64_t(0);
+            } else if (gap2 > kFarBoxGap2 && gap2 > kAnchorGapRatio2 * bx[9]) {
                 // wave-uniform: no near pair, separation from the block's anchor
                 float ux[T], uy[T], uz[T];
 #pragma unroll
@@ -440,6 +445,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
                 for (int k = 0; k < 6; k++) p[t][k] = 0.f;
             const int jend = min(j0 + 64 * kPerLane, it.nsrc);
             for (int j = j0 + lane; j < jend; j += 64) {
+                if (E.lj_flag && E.lj_flag[(it.src0 + j) / kLjBoxPoints]) {
+                    rmin = 0.0f;  // a source of a block with contact forces: FP64 below
+                    continue;
+                }
                 const RecF32 r = rec[it.src0 + j];
 #pragma unroll
                 for (int t = 0; t < TW; t++)
@@ -449,14 +458,15 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
             for (int t = 0; t < TW; t++)
 #pragma unroll
                 for (int k = 0; k < 6; k++) kahan_add(s[t][k], c[t][k], p[t][k]);
-            if (rmin < kNearR2) {  // near pairs of this lane's sources: FP64
+            if (rmin < kNearR2) {  // near pairs and contact-force blocks of this lane's sources: FP64
                 for (int j = j0 + lane; j < jend; j += 64) {
                     const RecF32 r = rec[it.src0 + j];
+                    const bool strong = E.lj_flag && E.lj_flag[(it.src0 + j) / kLjBoxPoints];
 #pragma unroll
                     for (int t = 0; t < TW; t++) {
                         float rx, ry, rz;
-                        if (sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a.x, r.a.y, r.a.z, r.b.x, r.b.y,
-                                    r.b.z, rx, ry, rz) < kNearR2)
+                        if (strong || sep_f32(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a.x, r.a.y, r.a.z, r.b.x,
+                                              r.b.y, r.b.z, rx, ry, rz) < kNearR2)
                             near_pair_f64(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a.x, r.a.y, r.a.z, r.b.x,
                                           r.b.y, r.b.z, r.a.w, r.b.w, r.c.x, r.c.y, r.c.z, r.c.w, pn[t]);
                     }

@@ -79,8 +79,23 @@ extern "C" mrs_status mrs_parareal(mrs_ensemble *E, int32_t ns, mrs_integrator f
         return st;
     }
     mrs_ensemble *C = W[0];
-    auto coarse = [&](const double *X, const double *D, double *oX, double *oD) -> mrs_status {
-        if (copy_state(C->X.as<double>(), C->D.as<double>(), X, D, N, s) != hipSuccess)
+    // slice boundary times T[n], accumulated step by step exactly as the
+    // device clock of a serial fine run accumulates them
+    std::vector<double> T(ns + 1);
+    if (hipMemcpy(&T[0], E->clock.p, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+        cleanup();
+        return fail(ctx, MRS_EDEVICE, "parareal clock read");
+    }
+    for (int n = 1; n <= ns; n++) {
+        T[n] = T[n - 1];
+        for (int k = 0; k < fsteps; k++) T[n] += fdt;
+    }
+    auto set_clock = [&](mrs_ensemble *w, int n) {
+        return hipMemcpyAsync(w->clock.p, &T[n], sizeof(double), hipMemcpyHostToDevice, s);
+    };
+    auto coarse = [&](const double *X, const double *D, int n0, double *oX, double *oD) -> mrs_status {
+        if (copy_state(C->X.as<double>(), C->D.as<double>(), X, D, N, s) != hipSuccess ||
+            set_clock(C, n0) != hipSuccess)
             return fail(ctx, MRS_EDEVICE, "parareal copy");
         mrs_status r = mrs_ensemble_step(C, MRS_EULER, cdt, csteps, prec, el);
         if (r != MRS_OK) return r;
@@ -95,7 +110,7 @@ extern "C" mrs_status mrs_parareal(mrs_ensemble *E, int32_t ns, mrs_integrator f
         return fail(ctx, MRS_EDEVICE, "parareal copy");
     }
     for (int n = 1; n <= ns && st == MRS_OK; n++) {
-        st = coarse(U.X(n - 1), U.D(n - 1), Go.X(n), Go.D(n));
+        st = coarse(U.X(n - 1), U.D(n - 1), n - 1, Go.X(n), Go.D(n));
         if (st == MRS_OK && copy_state(U.X(n), U.D(n), Go.X(n), Go.D(n), N, s) != hipSuccess)
             st = fail(ctx, MRS_EDEVICE, "parareal copy");
     }
@@ -105,7 +120,8 @@ extern "C" mrs_status mrs_parareal(mrs_ensemble *E, int32_t ns, mrs_integrator f
         // fine propagations of slices k..ns from the previous iterate, batched (Eq. intermediate)
         std::vector<mrs_ensemble *> batch;
         for (int n = k; n <= ns; n++) {
-            if (copy_state(W[n]->X.as<double>(), W[n]->D.as<double>(), U.X(n - 1), U.D(n - 1), N, s) != hipSuccess) {
+            if (copy_state(W[n]->X.as<double>(), W[n]->D.as<double>(), U.X(n - 1), U.D(n - 1), N, s) != hipSuccess ||
+                set_clock(W[n], n - 1) != hipSuccess) {
                 st = fail(ctx, MRS_EDEVICE, "parareal copy");
                 break;
             }
@@ -126,7 +142,7 @@ extern "C" mrs_status mrs_parareal(mrs_ensemble *E, int32_t ns, mrs_integrator f
             if (copy_state(Gn.X(n), Gn.D(n), Go.X(n), Go.D(n), N, s) != hipSuccess) st = fail(ctx, MRS_EDEVICE, "copy");
         // serial correction (Eq. serial_correct)
         for (int n = k + 1; n <= ns && st == MRS_OK; n++) {
-            st = coarse(V.X(n - 1), V.D(n - 1), Gn.X(n), Gn.D(n));
+            st = coarse(V.X(n - 1), V.D(n - 1), n - 1, Gn.X(n), Gn.D(n));
             if (st != MRS_OK) break;
             hipError_t he = timed(ctx, "parareal_correct", s, [&] {
                 return launch_parareal_correct((int)N, Fv.X(n), Fv.D(n), Gn.X(n), Gn.D(n), Go.X(n), Go.D(n), V.X(n),
@@ -157,7 +173,7 @@ extern "C" mrs_status mrs_parareal(mrs_ensemble *E, int32_t ns, mrs_integrator f
     }
     if (st == MRS_OK) {
         if (copy_state(E->X.as<double>(), E->D.as<double>(), U.X(ns), U.D(ns), N, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
+            set_clock(E, ns) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             st = fail(ctx, MRS_EDEVICE, "parareal result copy");
     }
     if (iters) *iters = done;

@@ -112,6 +112,11 @@ void near_blocks_first(std::vector<PairItem> &v) {
     });
 }
 
+void add_lj_items(Plan &P, int e, const mrs_ensemble *E) {
+    if (!E->has_lj) return;
+    for (int64_t p0 = 0; p0 < E->N; p0 += kBlock) P.lj.push_back({e, (int)p0});
+}
+
 hipError_t finalize_plan(Plan &P) {
     near_blocks_first(P.tile1);
     near_blocks_first(P.tile2);
@@ -121,6 +126,7 @@ hipError_t finalize_plan(Plan &P) {
     if ((e = upload_vec(P.d_tile1, P.tile1)) != hipSuccess) return e;
     if ((e = upload_vec(P.d_tile2, P.tile2)) != hipSuccess) return e;
     if ((e = upload_vec(P.d_rods, P.rods)) != hipSuccess) return e;
+    if ((e = upload_vec(P.d_lj, P.lj)) != hipSuccess) return e;
     return upload_vec(P.d_pts, P.pts);
 }
 
@@ -158,6 +164,17 @@ static EnsDesc ensemble_desc(mrs_ensemble *E, int prec, const PairCfg &c) {
     d.ds = E->rod.ds;
     d.dt = 0.0;
     d.elastic = 1;
+    d.clock = E->clock.as<double>();
+    d.has_wave = E->has_wave ? 1 : 0;
+    for (int i = 0; i < 3; i++) d.wave[i] = E->wave[i];
+    d.has_lj = E->has_lj ? 1 : 0;
+    d.lj_sig = E->lj[0];
+    d.lj_e = E->lj[1];
+    d.lj_rc = std::pow(2.0, 1.0 / 6.0) * E->lj[0];
+    d.fil = E->has_lj ? E->fil.as<int32_t>() : nullptr;
+    d.flj = E->has_lj ? E->flj.as<double>() : nullptr;
+    d.lj_box = E->has_lj ? E->lj_box.as<double>() : nullptr;
+    d.lj_flag = E->has_lj ? E->lj_flag.as<int32_t>() : nullptr;
     return d;
 }
 
@@ -174,6 +191,7 @@ mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out) {
         P->cfg = c;
         P->h_desc.push_back(ensemble_desc(E, prec, c));
         add_items(*P, 0, E->N, E->n_fil, c);
+        add_lj_items(*P, 0, E);
         hipError_t e = finalize_plan(*P);
         if (e != hipSuccess) return fail(ctx, MRS_EDEVICE, "plan upload: %s", hipGetErrorString(e));
         E->plan[prec] = std::move(P);
@@ -229,9 +247,16 @@ const char *epi_name(int epi) {
 
 hipError_t run_stage(mrs_context *ctx, Plan &P, int stage_state, int elastic, int epi, int stage, int scheme,
                      double dt, hipStream_t s) {
-    hipError_t e = timed(ctx, "rod_forces", s, [&] {
-        return launch_rod_forces(P.prec, stage_state, elastic, P.d_desc.as<EnsDesc>(), P.d_rods.as<RodItem>(),
-                                 (int)P.rods.size(), s);
+    hipError_t e = hipSuccess;
+    if (!P.lj.empty()) {
+        e = timed(ctx, "lj_forces", s, [&] {
+            return launch_lj(stage_state, P.d_desc.as<EnsDesc>(), P.d_lj.as<PointItem>(), (int)P.lj.size(), s);
+        });
+        if (e != hipSuccess) return e;
+    }
+    e = timed(ctx, "rod_forces", s, [&] {
+        return launch_rod_forces(P.prec, stage_state, elastic, scheme, stage, dt, P.d_desc.as<EnsDesc>(),
+                                 P.d_rods.as<RodItem>(), (int)P.rods.size(), s);
     });
     if (e != hipSuccess) return e;
     if ((e = run_pairs(ctx, P, s)) != hipSuccess) return e;
@@ -347,12 +372,32 @@ mrs_status ensemble_alloc(mrs_context *ctx, int32_t n_fil, const int32_t *offset
               E->D.reserve(v9) == hipSuccess && E->U.reserve(v3) == hipSuccess && E->W.reserve(v3) == hipSuccess &&
               E->Xs.reserve(v3) == hipSuccess && E->Ds.reserve(v9) == hipSuccess &&
               E->Ua.reserve(v3) == hipSuccess && E->Wa.reserve(v3) == hipSuccess &&
-              E->rec.reserve((size_t)n * sizeof(RecF64)) == hipSuccess;
+              E->rec.reserve((size_t)n * sizeof(RecF64)) == hipSuccess && E->clock.reserve(sizeof(double)) == hipSuccess;
     if (ok && has_ext) ok = E->fext.reserve(v3) == hipSuccess && E->next.reserve(v3) == hipSuccess;
     if (!ok) return fail(ctx, MRS_ENOMEM, "ensemble allocation (%lld points)", (long long)n);
+    const double t0 = 0.0;
     if (hipMemcpy(E->off.p, offsets, (n_fil + 1) * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(E->clock.p, &t0, sizeof t0, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(E->U.p, 0, v3) != hipSuccess || hipMemset(E->W.p, 0, v3) != hipSuccess)
         return fail(ctx, MRS_EDEVICE, "ensemble initialisation");
+    return MRS_OK;
+}
+
+// Buffers of the Lennard-Jones repulsion: the filament of every point, the
+// force per point and the box of every kLjBoxPoints-point block.
+static mrs_status lj_buffers(mrs_ensemble *E) {
+    mrs_context *ctx = E->ctx;
+    const int64_t n = E->N, nb = (n + kLjBoxPoints - 1) / kLjBoxPoints;
+    if (E->fil.reserve((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)) != hipSuccess ||
+        E->flj.reserve((size_t)std::max<int64_t>(n, 1) * 3 * sizeof(double)) != hipSuccess ||
+        E->lj_box.reserve((size_t)std::max<int64_t>(nb, 1) * 6 * sizeof(double)) != hipSuccess ||
+        E->lj_flag.reserve((size_t)std::max<int64_t>(nb, 1) * sizeof(int32_t)) != hipSuccess)
+        return fail(ctx, MRS_ENOMEM, "Lennard-Jones buffers");
+    std::vector<int32_t> fil((size_t)std::max<int64_t>(n, 1), 0);
+    for (int32_t f = 0; f < E->n_fil; f++)
+        for (int32_t k = E->offsets[f]; k < E->offsets[f + 1]; k++) fil[k] = f;
+    if (hipMemcpy(E->fil.p, fil.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(ctx, MRS_EDEVICE, "Lennard-Jones filament index upload");
     return MRS_OK;
 }
 
@@ -364,8 +409,14 @@ mrs_status ensemble_clone(mrs_ensemble *S, mrs_ensemble **out) {
     if (st != MRS_OK) return st;
     const size_t v3 = (size_t)S->N * 3 * sizeof(double), v9 = 3 * v3;
     hipStream_t s = ctx->stream;
+    E->has_wave = S->has_wave;
+    E->has_lj = S->has_lj;
+    for (int i = 0; i < 3; i++) E->wave[i] = S->wave[i];
+    for (int i = 0; i < 2; i++) E->lj[i] = S->lj[i];
+    if (E->has_lj && (st = lj_buffers(E.get())) != MRS_OK) return st;
     if (hipMemcpyAsync(E->X.p, S->X.p, v3, hipMemcpyDeviceToDevice, s) != hipSuccess ||
         hipMemcpyAsync(E->D.p, S->D.p, v9, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(E->clock.p, S->clock.p, sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
         (S->has_ext && (hipMemcpyAsync(E->fext.p, S->fext.p, v3, hipMemcpyDeviceToDevice, s) != hipSuccess ||
                         hipMemcpyAsync(E->next.p, S->next.p, v3, hipMemcpyDeviceToDevice, s) != hipSuccess)) ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -649,7 +700,7 @@ mrs_status mrs_rod_forces_device(mrs_context *ctx, int32_t n_fil, const int32_t 
     HIPCHK(ctx, ctx->eval_rod.reserve(blob.size()));
     HIPCHK(ctx, upload(ctx, ctx->eval_rod.p, blob.data(), blob.size(), s));
     HIPCHK(ctx, timed(ctx, "rod_forces", s, [&] {
-        return launch_rod_forces(MRS_FP64, 0, 1, ctx->eval_rod.as<EnsDesc>(),
+        return launch_rod_forces(MRS_FP64, 0, 1, 0, 0, 0.0, ctx->eval_rod.as<EnsDesc>(),
                                  reinterpret_cast<const RodItem *>(ctx->eval_rod.as<char>() + items_off), n_fil, s);
     }));
     // temporaries are freed by DevBuf destructors: wait for the kernel first
@@ -742,6 +793,62 @@ mrs_status mrs_ensemble_size(const mrs_ensemble *E, int64_t *n) {
     return MRS_OK;
 }
 
+// Drops every cached plan that holds this ensemble's descriptor and gives it
+// a new identity, so that the next launch rebuilds them.
+static void invalidate_plans(mrs_ensemble *E) {
+    static std::atomic<uint64_t> next_gen{1};
+    mrs_context *ctx = E->ctx;
+    for (auto it = ctx->batch_plans.begin(); it != ctx->batch_plans.end();) {
+        const auto &v = it->first.first;
+        if (std::find(v.begin(), v.end(), E->uid) != v.end()) it = ctx->batch_plans.erase(it);
+        else ++it;
+    }
+    E->plan[0].reset();
+    E->plan[1].reset();
+    E->uid = (uint64_t(1) << 63) | next_gen.fetch_add(1);
+}
+
+mrs_status mrs_ensemble_set_swimming(mrs_ensemble *E, const double *wave, const double *lj) {
+    if (!E) return MRS_EINVAL;
+    mrs_context *ctx = E->ctx;
+    if (wave && !(std::isfinite(wave[0]) && std::isfinite(wave[1]) && std::isfinite(wave[2])))
+        return fail(ctx, MRS_EINVAL, "waveform (A, k, f) must be finite");
+    if (lj && !(finite_pos(lj[0]) && std::isfinite(lj[1]) && lj[1] >= 0.0))
+        return fail(ctx, MRS_EINVAL, "Lennard-Jones sigma must be > 0 and the energy >= 0");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    E->has_wave = wave != nullptr;
+    for (int i = 0; i < 3; i++) E->wave[i] = wave ? wave[i] : 0.0;
+    E->has_lj = lj != nullptr;
+    E->lj[0] = lj ? lj[0] : 0.0;
+    E->lj[1] = lj ? lj[1] : 0.0;
+    if (E->has_lj) {
+        mrs_status st = lj_buffers(E);
+        if (st != MRS_OK) return st;
+    }
+    invalidate_plans(E);
+    return MRS_OK;
+}
+
+mrs_status mrs_ensemble_set_time(mrs_ensemble *E, double t) {
+    if (!E) return MRS_EINVAL;
+    mrs_context *ctx = E->ctx;
+    if (!std::isfinite(t)) return fail(ctx, MRS_EINVAL, "time must be finite");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(E->clock.p, &t, sizeof t, hipMemcpyHostToDevice));
+    return MRS_OK;
+}
+
+mrs_status mrs_ensemble_get_time(mrs_ensemble *E, double *t) {
+    if (!E || !t) return MRS_EINVAL;
+    mrs_context *ctx = E->ctx;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(t, E->clock.p, sizeof *t, hipMemcpyDeviceToHost));
+    return MRS_OK;
+}
+
 mrs_status mrs_ensemble_eval(mrs_ensemble *E, mrs_precision prec, int include_elastic) {
     if (!E) return MRS_EINVAL;
     mrs_context *ctx = E->ctx;
@@ -829,6 +936,7 @@ static mrs_status batch_plan(mrs_context *ctx, int32_t n_ens, mrs_ensemble *cons
             if (st != MRS_OK) return st;
             P->h_desc.push_back(single->h_desc[0]);
             add_items(*P, e, E->N, E->n_fil, single->cfg);
+            add_lj_items(*P, e, E);
         }
         hipError_t e = finalize_plan(*P);
         if (e != hipSuccess) return fail(ctx, MRS_EDEVICE, "batch plan upload: %s", hipGetErrorString(e));

@@ -58,7 +58,8 @@ struct Plan {
     std::vector<PairItem> split, tile1, tile2;
     std::vector<RodItem> rods;
     std::vector<PointItem> pts;
-    DevBuf d_desc, d_split, d_tile1, d_tile2, d_rods, d_pts;
+    std::vector<PointItem> lj;  // kBlock-point blocks of the ensembles with LJ repulsion
+    DevBuf d_desc, d_split, d_tile1, d_tile2, d_rods, d_pts, d_lj;
     // cached graphs: key = (integrator, dt bits, steps, elastic)
     std::map<std::tuple<int, uint64_t, int, int>, hipGraphExec_t> graphs;
     int64_t pairs_per_eval = 0;
@@ -108,7 +109,12 @@ struct mrs_ensemble {
     double eps = 0, mu = 0;
     mrs_rod_params rod{};
     bool has_ext = false;
+    // swimming (Sec. IV): waveform (A, k, f) and Lennard-Jones (sigma, energy)
+    bool has_wave = false, has_lj = false;
+    double wave[3] = {0, 0, 0}, lj[2] = {0, 0};
     mrs::DevBuf off, X, D, U, W, Xs, Ds, Ua, Wa, fext, next, rec, part;
+    mrs::DevBuf clock;              // time at the start of the next step (one double)
+    mrs::DevBuf fil, flj, lj_box, lj_flag;  // with LJ: filament per point, forces, block boxes and flags
     std::unique_ptr<mrs::Plan> plan[2];  // per precision
 };
 
@@ -118,6 +124,8 @@ namespace mrs {
 mrs_status fail(mrs_context *ctx, mrs_status st, const char *fmt, ...);
 mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out);
 void add_items(Plan &P, int e, int64_t N, int n_fil, const PairCfg &c);
+// Lennard-Jones blocks of ensemble e of plan P when it has the repulsion on.
+void add_lj_items(Plan &P, int e, const mrs_ensemble *E);
 hipError_t finalize_plan(Plan &P);
 hipError_t run_pairs(mrs_context *ctx, Plan &P, hipStream_t s);
 hipEvent_t take_event(mrs_context *ctx);

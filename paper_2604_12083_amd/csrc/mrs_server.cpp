@@ -191,7 +191,7 @@ hipError_t launch_tick(mrs_server *S) {
     hipStream_t s = ctx->stream;
     const double nan = std::nan("");
     hipError_t e = timed(ctx, "rod_forces", s, [&] {
-        return launch_rod_forces(S->prec, 0, -1, T.all.d_desc.as<EnsDesc>(), T.all.d_rods.as<RodItem>(),
+        return launch_rod_forces(S->prec, 0, -1, 0, 0, nan, T.all.d_desc.as<EnsDesc>(), T.all.d_rods.as<RodItem>(),
                                  (int)T.all.rods.size(), s);
     });
     if (e == hipSuccess) e = run_pairs(ctx, T.all, s);

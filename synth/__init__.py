@@ -199,6 +199,68 @@ def config3(n_slices: int = 16, F: int = 32, M: int = 100, box: float = 10.0, se
 
 
 @dataclasses.dataclass
+class SwimParams:
+    """Parameters of the swimming workload (Sec. IV): waveform (A, k, f) of
+    the preferred strain-twist (0, -k^2 A sin(k s + f t), 0), Lennard-Jones
+    (sigma, energy) with sigma = 3 eps, rod moduli and the fine time step."""
+
+    wave: tuple
+    lj: tuple
+    rod: RodParams
+    dt: float
+
+
+def swimmers(F: int, M: int = 51, box: float = 3.0, seed=11, height: float = 1.0, spread: float = 0.2,
+             min_gap: float = 0.2, max_tries: int = 1000) -> Ensemble:
+    """F straight swimmers of length 1 (M points, ds = 1/(M - 1)), lying
+    parallel to the plane z = 0.
+
+    Draw order from one default_rng(seed), per swimmer: centre (x, y) uniform
+    in [0, box]^2, height uniform in [height - spread/2, height + spread/2],
+    in-plane direction angle uniform on [0, 2 pi).  A swimmer with a point
+    closer than min_gap to a point of an earlier one is drawn again (at most
+    max_tries times).  Frames: D3 along the rod, D2 = e_z, D1 = D2 x D3, so
+    the waveform bends the rod in the plane parallel to z = 0.  eps = 4 ds,
+    mu = 1, no external loads (the waveform drives the swimmer).
+    """
+    rng = seed if isinstance(seed, np.random.Generator) else np.random.default_rng(seed)
+    ds = 1.0 / (M - 1)
+    s = np.arange(M) * ds - 0.5
+    reach = 1.0 + min_gap
+    cells = {}
+    Xs, Ds = [], []
+    for i in range(F):
+        for _ in range(max_tries):
+            cx, cy = rng.uniform(0.0, box, size=2)
+            cz = rng.uniform(height - 0.5 * spread, height + 0.5 * spread)
+            ang = rng.uniform(0.0, 2.0 * math.pi)
+            d = np.array([math.cos(ang), math.sin(ang), 0.0])
+            X = np.array([cx, cy, cz]) + s[:, None] * d[None, :]
+            key = (int(cx // reach), int(cy // reach))
+            near = [j for dx in (-1, 0, 1) for dy in (-1, 0, 1) for j in cells.get((key[0] + dx, key[1] + dy), [])]
+            if all(np.min(np.linalg.norm(X[:, None, :] - Xs[j][None, :, :], axis=-1)) >= min_gap for j in near):
+                break
+        else:
+            raise ValueError("swimmers: box too crowded for min_gap")
+        cells.setdefault(key, []).append(i)
+        d1 = np.cross([0.0, 0.0, 1.0], d)
+        D = np.tile(np.concatenate([d1, [0.0, 0.0, 1.0], d]), (M, 1))
+        Xs.append(X)
+        Ds.append(D)
+    N = F * M
+    offsets = (np.arange(F + 1, dtype=np.int64) * M).astype(np.int32)
+    return Ensemble(offsets, np.concatenate(Xs), np.concatenate(Ds), np.zeros((N, 3)), np.zeros((N, 3)),
+                    eps=4.0 * ds, mu=1.0, ds=ds)
+
+
+def swim_params(e: Ensemble, amplitude: float = 0.05, wavelength: float = 1.0, frequency: float = 20.0 * math.pi,
+                lj_energy: float = 1e-4, a=(1e-3, 1e-3, 1e-3), b=(1.0, 1.0, 1.0), dt: float = 1e-6) -> SwimParams:
+    """Waveform, Lennard-Jones and moduli of the swimming workload for ensemble e."""
+    return SwimParams(wave=(amplitude, 2.0 * math.pi / wavelength, frequency), lj=(3.0 * e.eps, lj_energy),
+                      rod=e.rod(a=a, b=b), dt=dt)
+
+
+@dataclasses.dataclass
 class RequestSpec:
     n_fil: int
     M: int

@@ -1,0 +1,200 @@
+"""GPU parity of the swimming workload (Sec. IV): the time-dependent
+preferred strain-twist and the Lennard-Jones repulsion between filaments,
+against the FP64 oracle; the device clock through steps, batches, graph
+replays and Parareal.
+
+Error metric: the paper's relative error form (Eq. true_err); tolerances
+1e-12 (MRS_FP64) and 1e-5 (MRS_FP32C), on single evaluations and on
+teacher-forced single steps."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import rod_of, say, step_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def mrs():
+    import paper_2604_12083_amd as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mrs):
+    c = mrs.mrs_context_create(0)
+    yield c
+    mrs.mrs_context_destroy(c)
+
+
+def _swim(F=8, box=2.0, seed=3):
+    e = synth.swimmers(F, box=box, seed=seed)
+    p = synth.swim_params(e)
+    return e, p
+
+
+def _create(mrs, ctx, e, p, t0=0.0):
+    ens = mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, p.rod))
+    mrs.mrs_ensemble_set_swimming(ctx, ens, p.wave, p.lj)
+    mrs.mrs_ensemble_set_time(ctx, ens, t0)
+    return ens
+
+
+def _frame_err(Da, Db):
+    return float(np.max(np.linalg.norm((Da - Db).reshape(-1, 3, 3), axis=2)))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("F,box", [(8, 2.0), (40, 4.0)])
+def test_swim_eval_matches_oracle(mrs, ctx, prec, F, box):
+    e, p = _swim(F=F, box=box)
+    F = oracle.lj_forces(e.offsets, e.X, p.lj)
+    assert np.count_nonzero(np.abs(F).sum(axis=1)) >= 4, "the geometry must bring filaments within r_c"
+    t = 0.0371
+    ens = _create(mrs, ctx, e, p, t)
+    try:
+        mrs.mrs_ensemble_eval(ctx, ens, prec, True)
+        _, _, U, W = mrs.mrs_ensemble_get(ctx, ens)
+    finally:
+        mrs.mrs_ensemble_destroy(ens)
+    Uo, Wo = oracle.velocities(e.offsets, e.X, e.D, p.rod, e.f, e.n, e.eps, e.mu, True, wave=p.wave, t=t, lj=p.lj)
+    eu, ew = oracle.rel_err(U, Uo), oracle.rel_err(W, Wo)
+    say(f"swim eval prec={prec}: U {eu:.3e} W {ew:.3e}")
+    assert eu <= TOL[prec] and ew <= TOL[prec]
+    # the waveform matters: at another time the answer differs
+    Ut, _ = oracle.velocities(e.offsets, e.X, e.D, p.rod, e.f, e.n, e.eps, e.mu, True, wave=p.wave,
+                              t=t + 0.5 * math.pi / p.wave[2], lj=p.lj)
+    assert oracle.rel_err(Ut, Uo) > 1e-3
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lj_without_elastic_forces(mrs, ctx, prec):
+    e, p = _swim(seed=4)
+    ens = _create(mrs, ctx, e, p)
+    try:
+        mrs.mrs_ensemble_eval(ctx, ens, prec, False)
+        _, _, U, W = mrs.mrs_ensemble_get(ctx, ens)
+    finally:
+        mrs.mrs_ensemble_destroy(ens)
+    Uo, Wo = oracle.velocities(e.offsets, e.X, e.D, p.rod, e.f, e.n, e.eps, e.mu, False, lj=p.lj)
+    assert np.abs(Uo).max() > 0
+    eu = oracle.rel_err(U[np.linalg.norm(Uo, axis=1) > 0], Uo[np.linalg.norm(Uo, axis=1) > 0])
+    say(f"lj only prec={prec}: U {eu:.3e}")
+    assert eu <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("integ", ["EULER", "RK2", "RK4"])
+def test_swim_teacher_forced_steps(mrs, ctx, prec, integ):
+    e, p = _swim(seed=5)
+    dt, t0 = 1e-4, 0.125
+    ens = _create(mrs, ctx, e, p, t0)
+    try:
+        X, D, _, _ = mrs.mrs_ensemble_get(ctx, ens)
+        t = t0
+        for step in range(3):
+            Xo, Do, _, _, to = oracle.step_ex(e.offsets, X, D, p.rod, e.f, e.n, e.eps, e.mu, getattr(oracle, integ),
+                                              dt, 1, wave=p.wave, t=t, lj=p.lj)
+            mrs.mrs_ensemble_step(ctx, ens, getattr(mrs, "MRS_" + integ), dt, 1, prec, True)
+            X1, D1, _, _ = mrs.mrs_ensemble_get(ctx, ens)
+            t1 = mrs.mrs_ensemble_get_time(ctx, ens)
+            ex, ed = step_err(X1, Xo, X), _frame_err(D1, Do)
+            say(f"swim {integ} prec={prec} step {step}: dX {ex:.3e} D {ed:.3e} t {t1!r}")
+            assert ex <= TOL[prec] and ed <= TOL[prec]
+            assert t1 == to
+            X, D, t = X1, D1, t1
+    finally:
+        mrs.mrs_ensemble_destroy(ens)
+
+
+def test_clock_through_batches_and_graphs(mrs, ctx):
+    """A swimmer ensemble batched with a plain one, 70 RK2 steps replayed from
+    HIP graphs (two graphs of 50 and 20 steps), equals each ensemble stepped
+    alone; the clock advances by dt per step on the device."""
+    e, p = _swim(F=6, seed=6)
+    plain = synth.filaments(5, 40, 2.0, 8)
+    dt, n = 1e-5, 70
+    a_sw = _create(mrs, ctx, e, p, 0.5)
+    a_pl = mrs.mrs_ensemble_create(ctx, plain.offsets, plain.X, plain.D, plain.f, plain.n, plain.eps, plain.mu,
+                                   rod_of(mrs, plain.rod()))
+    b_sw = _create(mrs, ctx, e, p, 0.5)
+    b_pl = mrs.mrs_ensemble_create(ctx, plain.offsets, plain.X, plain.D, plain.f, plain.n, plain.eps, plain.mu,
+                                   rod_of(mrs, plain.rod()))
+    try:
+        for h in (a_sw, a_pl):
+            mrs.mrs_ensemble_step(ctx, h, mrs.MRS_RK2, dt, n, mrs.MRS_FP32C, True)
+        mrs.mrs_batch_step(ctx, [b_sw, b_pl], mrs.MRS_RK2, dt, n, mrs.MRS_FP32C, True, use_graph=True)
+        for a, b in ((a_sw, b_sw), (a_pl, b_pl)):
+            Xa, Da, _, _ = mrs.mrs_ensemble_get(ctx, a)
+            Xb, Db, _, _ = mrs.mrs_ensemble_get(ctx, b)
+            np.testing.assert_array_equal(Xa, Xb)
+            np.testing.assert_array_equal(Da, Db)
+            assert mrs.mrs_ensemble_get_time(ctx, a) == mrs.mrs_ensemble_get_time(ctx, b)
+        t = 0.5
+        for _ in range(n):
+            t += dt
+        assert mrs.mrs_ensemble_get_time(ctx, b_sw) == t
+    finally:
+        for h in (a_sw, a_pl, b_sw, b_pl):
+            mrs.mrs_ensemble_destroy(h)
+
+
+def test_switching_swimming_off_rebuilds_plans(mrs, ctx):
+    e, p = _swim(F=4, seed=7)
+    ens = _create(mrs, ctx, e, p)
+    ref = mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, p.rod))
+    try:
+        mrs.mrs_ensemble_eval(ctx, ens, mrs.MRS_FP64, True)  # builds the swimming plan
+        mrs.mrs_ensemble_set_swimming(ctx, ens, None, None)
+        mrs.mrs_ensemble_eval(ctx, ens, mrs.MRS_FP64, True)
+        mrs.mrs_ensemble_eval(ctx, ref, mrs.MRS_FP64, True)
+        _, _, U, W = mrs.mrs_ensemble_get(ctx, ens)
+        _, _, Ur, Wr = mrs.mrs_ensemble_get(ctx, ref)
+        np.testing.assert_array_equal(U, Ur)
+        np.testing.assert_array_equal(W, Wr)
+    finally:
+        mrs.mrs_ensemble_destroy(ens)
+        mrs.mrs_ensemble_destroy(ref)
+
+
+def test_swim_parareal_full_iterations_equal_serial_fine(mrs, ctx):
+    e, p = _swim(F=4, seed=9)
+    dt, fsteps, ns = 1e-5, 20, 4
+    par = _create(mrs, ctx, e, p, 0.25)
+    ser = _create(mrs, ctx, e, p, 0.25)
+    try:
+        iters, hist = mrs.mrs_parareal(ctx, par, ns, mrs.MRS_RK2, dt, fsteps, 2, ns, 0.0, mrs.MRS_FP64, True)
+        assert iters == ns
+        mrs.mrs_ensemble_step(ctx, ser, mrs.MRS_RK2, dt, ns * fsteps, mrs.MRS_FP64, True)
+        Xp, Dp, _, _ = mrs.mrs_ensemble_get(ctx, par)
+        Xs, Ds, _, _ = mrs.mrs_ensemble_get(ctx, ser)
+        np.testing.assert_array_equal(Xp, Xs)
+        np.testing.assert_array_equal(Dp, Ds)
+        assert mrs.mrs_ensemble_get_time(ctx, par) == mrs.mrs_ensemble_get_time(ctx, ser)
+    finally:
+        mrs.mrs_ensemble_destroy(par)
+        mrs.mrs_ensemble_destroy(ser)
+
+
+def test_invalid_swimming_arguments(mrs, ctx):
+    e, p = _swim(F=2, seed=10)
+    ens = mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, p.rod))
+    try:
+        with pytest.raises(mrs.MrsError):
+            mrs.mrs_ensemble_set_swimming(ctx, ens, (float("nan"), 1.0, 1.0), None)
+        with pytest.raises(mrs.MrsError):
+            mrs.mrs_ensemble_set_swimming(ctx, ens, None, (-1.0, 1.0))
+        with pytest.raises(mrs.MrsError):
+            mrs.mrs_ensemble_set_swimming(ctx, ens, None, (0.1, -1.0))
+        with pytest.raises(mrs.MrsError):
+            mrs.mrs_ensemble_set_time(ctx, ens, float("inf"))
+        assert mrs.mrs_ensemble_get_time(ctx, ens) == 0.0
+    finally:
+        mrs.mrs_ensemble_destroy(ens)
