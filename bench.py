@@ -59,31 +59,42 @@ def log(*a):
 
 
 def workload(name):
+    """(ensemble, description, swimming parameters or None)."""
     import synth
 
     if name == "config1":
-        return synth.config1(), "1 filament x 64 points, eps = 1.5/64"
+        return synth.config1(), "1 filament x 64 points, eps = 1.5/64", None
     if name == "config2":
-        return synth.config2(), "100 filaments x 128 points (12,800 points) in [0,10]^3, eps = 1.5/128"
+        return synth.config2(), "100 filaments x 128 points (12,800 points) in [0,10]^3, eps = 1.5/128", None
     if name == "config5":
-        return synth.config5(), "1,000 filaments x 256 points (256,000 points) in [0,50]^3, eps = 1.5/256"
+        return synth.config5(), "1,000 filaments x 256 points (256,000 points) in [0,50]^3, eps = 1.5/256", None
+    if name == "swim":
+        e = synth.swimmers(1000, box=40.0, seed=12)
+        p = synth.swim_params(e)
+        return e, ("1,000 straight swimmers x 51 points (51,000 points), length 1, eps = 4 ds, in [0,40]^2 at "
+                   f"z = 1 +- 0.1; waveform A={p.wave[0]}, k=2 pi, f={p.wave[2]:.4g}; Lennard-Jones sigma = 3 eps, "
+                   f"energy {p.lj[1]}"), p
     raise SystemExit(f"unknown workload {name}")
 
 
-def measure(mrs, ctx, e, prec, steps, warmup, dt):
+def measure(mrs, ctx, e, prec, steps, warmup, dt, integ=None, swim=None):
     """Timed eager steps; HIP events on the launch stream bracket the
     dominant pair kernel inside the timed region."""
     import torch
 
-    rod = mrs.rod_params(*(getattr(e.rod(), k) for k in ("a", "b", "omega0", "ds")))
+    integ = mrs.MRS_EULER if integ is None else integ
+    rp = swim.rod if swim is not None else e.rod()
+    rod = mrs.rod_params(*(getattr(rp, k) for k in ("a", "b", "omega0", "ds")))
     ens = mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod)
+    if swim is not None:
+        mrs.mrs_ensemble_set_swimming(ctx, ens, swim.wave, swim.lj)
     try:
-        mrs.mrs_ensemble_step(ctx, ens, mrs.MRS_EULER, dt, warmup, prec, True)
+        mrs.mrs_ensemble_step(ctx, ens, integ, dt, warmup, prec, True)
         # latency of single synchronous steps
         lat = []
         for _ in range(max(steps, 20)):
             t0 = time.perf_counter()
-            mrs.mrs_ensemble_step(ctx, ens, mrs.MRS_EULER, dt, 1, prec, True)
+            mrs.mrs_ensemble_step(ctx, ens, integ, dt, 1, prec, True)
             lat.append((time.perf_counter() - t0) * 1e3)
         # throughput: K steps queued back to back; HIP events bracket the
         # dominant pair kernel only, on the stream it is launched on
@@ -95,7 +106,7 @@ def measure(mrs, ctx, e, prec, steps, warmup, dt):
         torch.cuda.synchronize()
         mrs.mrs_context_synchronize(ctx)
         t0 = time.perf_counter()
-        mrs.mrs_ensemble_step(ctx, ens, mrs.MRS_EULER, dt, steps, prec, True)
+        mrs.mrs_ensemble_step(ctx, ens, integ, dt, steps, prec, True)
         mrs.mrs_context_synchronize(ctx)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -105,18 +116,19 @@ def measure(mrs, ctx, e, prec, steps, warmup, dt):
         mrs.mrs_profile_reset(ctx)
         mrs.mrs_profile_select(ctx, "")
         mrs.mrs_profile_enable(ctx, True)
-        mrs.mrs_ensemble_step(ctx, ens, mrs.MRS_EULER, dt, min(steps, 20), prec, True)
+        mrs.mrs_ensemble_step(ctx, ens, integ, dt, min(steps, 20), prec, True)
         mrs.mrs_profile_enable(ctx, False)
         kernels = {}
-        for k in ("rod_forces", "pairs_tile", "pairs_split", "reduce_euler"):
+        for k in ("lj_forces", "rod_forces", "pairs_tile", "pairs_split", "reduce_euler", "reduce_rk_stage",
+                  "reduce_rk_final"):
             n, ms = mrs.mrs_profile_query(ctx, k)
             if n:
                 kernels[k] = {"launches": n, "avg_us": 1e3 * ms / n}
         mrs.mrs_profile_reset(ctx)
         # graph-replayed steps (one HIP graph launch per 50 steps)
-        mrs.mrs_batch_step(ctx, [ens], mrs.MRS_EULER, dt, steps, prec, True, use_graph=True)
+        mrs.mrs_batch_step(ctx, [ens], integ, dt, steps, prec, True, use_graph=True)
         t0 = time.perf_counter()
-        mrs.mrs_batch_step(ctx, [ens], mrs.MRS_EULER, dt, steps, prec, True, use_graph=True)
+        mrs.mrs_batch_step(ctx, [ens], integ, dt, steps, prec, True, use_graph=True)
         wall_graph = time.perf_counter() - t0
         Xg, Dg, _, _ = mrs.mrs_ensemble_get(ctx, ens)
         return {
@@ -133,7 +145,7 @@ def measure(mrs, ctx, e, prec, steps, warmup, dt):
         mrs.mrs_ensemble_destroy(ens)
 
 
-def cpu_baseline(mrs, ctx, e, prec_list):
+def cpu_baseline(mrs, ctx, e, prec_list, swim=None):
     """The FP64 oracle as it stands, on this host's cores, on a bounded sample:
     the rod forces of the whole ensemble plus the MRS sum for a subset of
     targets; also the GPU's max relative error on that subset."""
@@ -141,10 +153,12 @@ def cpu_baseline(mrs, ctx, e, prec_list):
 
     n_t = min(e.N, 1024)
     idx = np.sort(np.random.default_rng(7).choice(e.N, n_t, replace=False))
+    rp = swim.rod if swim is not None else e.rod()
+    kw = {} if swim is None else {"wave": swim.wave, "t": 0.0, "lj": swim.lj}
     t0 = time.perf_counter()
     reps = 0
     while True:
-        g, m = oracle.rod_forces(e.offsets, e.X, e.D, e.rod(), e.f, e.n)
+        g, m = oracle.rod_forces(e.offsets, e.X, e.D, rp, e.f, e.n, **kw)
         Uo, Wo = oracle.mrs_field(e.X[idx], e.X, g, m, e.eps, e.mu)
         reps += 1
         if time.perf_counter() - t0 > 10.0 or reps >= 5000:
@@ -152,8 +166,10 @@ def cpu_baseline(mrs, ctx, e, prec_list):
     dt = time.perf_counter() - t0
     pairs = reps * n_t * e.N
     errs = {}
-    rod = mrs.rod_params(*(getattr(e.rod(), k) for k in ("a", "b", "omega0", "ds")))
+    rod = mrs.rod_params(*(getattr(rp, k) for k in ("a", "b", "omega0", "ds")))
     ens = mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod)
+    if swim is not None:
+        mrs.mrs_ensemble_set_swimming(ctx, ens, swim.wave, swim.lj)
     try:
         for prec in prec_list:
             mrs.mrs_ensemble_eval(ctx, ens, prec, True)
@@ -336,7 +352,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="config2",
-                    choices=["config1", "config2", "config5", "config3", "config4", "parareal", "copy"])
+                    choices=["config1", "config2", "config5", "swim", "config3", "config4", "parareal", "copy"])
     ap.add_argument("--requests", type=int, default=32, help="config4: prefix of the request sequence")
     ap.add_argument("--rates", default="10,100,1000", help="config4: Poisson arrival rates (req/s)")
     ap.add_argument("--slots", type=int, default=64)
@@ -415,18 +431,21 @@ def main():
             mrs.mrs_context_destroy(ctx)
         print(json.dumps(line), flush=True)
         return
-    e, desc = workload(args.workload)
+    e, desc, swim = workload(args.workload)
+    # the swimming workload steps with the paper's fine propagator (RK2, 2 stages)
+    integ, stages, step_name = ((mrs.MRS_RK2, 2, "midpoint RK2") if swim is not None else
+                                (mrs.MRS_EULER, 1, "forward-Euler"))
     ctx = mrs.mrs_context_create(0)
     try:
-        pairs_step = e.N * e.N
+        pairs_step = stages * e.N * e.N
         res = {}
         for prec, tag in ((mrs.MRS_FP32C, "fp32c"), (mrs.MRS_FP64, "fp64")):
             log(f"measure {tag} N={e.N} steps={args.steps}")
-            res[tag] = measure(mrs, ctx, e, prec, args.steps, args.warmup, args.dt)
+            res[tag] = measure(mrs, ctx, e, prec, args.steps, args.warmup, args.dt, integ, swim)
         cpu, errs = (None, None)
         if not args.no_cpu:
             log("cpu baseline (oracle)")
-            cpu, errs = cpu_baseline(mrs, ctx, e, [mrs.MRS_FP32C, mrs.MRS_FP64])
+            cpu, errs = cpu_baseline(mrs, ctx, e, [mrs.MRS_FP32C, mrs.MRS_FP64], swim)
     finally:
         mrs.mrs_context_destroy(ctx)
 
@@ -437,7 +456,7 @@ def main():
             "ms_per_step": 1e3 * r["wall_s"] / args.steps,
             "ms_per_step_graph": 1e3 * r["wall_graph_s"] / args.steps,
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-            "roofline": roofline(pairs_step, r["kernel_avg_s"], peak, measured_traffic(args.workload, tag)),
+            "roofline": roofline(e.N * e.N, r["kernel_avg_s"], peak, measured_traffic(args.workload, tag)),
             "kernels_avg_us": {k: round(v["avg_us"], 2) for k, v in r["kernels"].items()},
             "frame_update_GBps": frame_update_gbps(e.N, r["kernels"]),
         }
@@ -457,8 +476,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32c",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}; one forward-Euler step (rod forces + MRS U/Omega "
-                               f"+ frame update), dt={args.dt}",
+        "config": {"workload": f"{args.workload}: {desc}; one {step_name} step ({stages} x (rod forces + MRS "
+                               f"U/Omega) + frame update), dt={args.dt}",
                    "n_points": e.N, "pairs_per_step": pairs_step, "precision": "fp32c"},
         "latency_ms": s32["latency_ms"],
         "ms_per_step_graph": s32["ms_per_step_graph"],

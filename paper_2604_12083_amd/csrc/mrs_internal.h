@@ -55,18 +55,22 @@ struct EnsDesc {
     // swimming (Sec. IV): waveform (A, k, f) added to the preferred
     // strain-twist, Lennard-Jones repulsion between filaments
     int32_t has_wave, has_lj;
-    int32_t pad_;
+    int32_t n_ljblk;        // source blocks of the LJ pass (with LJ)
     double wave[3];
     double lj_sig, lj_e, lj_rc;
     double *clock;          // time at the start of the current step (one double)
     const int32_t *fil;     // filament of each point (with LJ)
     double *flj;            // LJ force on each point [3][N] (with LJ)
-    double *lj_box;         // per 64-point block: lo[3], hi[3] of the positions (with LJ)
-    int32_t *lj_flag;       // per 64-point block: 1 if a point of it feels a LJ force (with LJ)
+    const int32_t *lj_blk;  // per LJ source block: first point, end, filament (with LJ)
+    double *lj_box;         // per LJ source block: lo[3], hi[3] of its positions (with LJ)
+    uint64_t *lj_mask;      // per aligned 64-point block: bit j set when point 64 b + j
+                            // feels a LJ force (with LJ)
 };
 
-// Points per box of the Lennard-Jones neighbour culling.
-constexpr int kLjBoxPoints = 64;
+// Source blocks of the Lennard-Jones pass hold at most this many consecutive
+// points of one filament; the LJ mask covers aligned blocks of 64 points.
+constexpr int kLjBlockPoints = 64;
+constexpr int kLjMaskPoints = 64;
 
 // One block of a pair kernel: targets [tgt0, tgt0 + ntgt) against sources
 // [src0, src0 + nsrc) of ensemble `ens`, written to split-K chunk `chunk`.
@@ -107,10 +111,12 @@ hipError_t launch_pack_aos(int prec, const EnsDesc *d_desc, const EnsDesc &h_des
 // `scheme` (0 for stage 0); dt = NaN: every ensemble uses its own dt.
 hipError_t launch_rod_forces(int prec, int stage_state, int elastic, int scheme, int stage, double dt,
                              const EnsDesc *d_desc, const RodItem *d_items, int n_items, hipStream_t s);
-// Lennard-Jones forces of the ensembles with has_lj: boxes of every
-// kLjBoxPoints-point block, then the force on every point.  Items are
-// (ensemble, first point) of kBlock consecutive points.
-hipError_t launch_lj(int stage_state, const EnsDesc *d_desc, const PointItem *d_items, int n_items, hipStream_t s);
+// Lennard-Jones forces of the ensembles with has_lj: the box of every LJ
+// source block (box items: (ensemble, first of kBlock / 64 blocks)), then the
+// force on every point and the LJ masks (target items: (ensemble, first of
+// kBlock consecutive points)).
+hipError_t launch_lj(int stage_state, const EnsDesc *d_desc, const PointItem *d_box_items, int n_box_items,
+                     const PointItem *d_items, int n_items, hipStream_t s);
 hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, const PairItem *d_items,
                         int n_items, hipStream_t s);
 // dt = NaN: every ensemble uses its own EnsDesc::dt.

@@ -317,27 +317,27 @@ __device__ __forceinline__ double wave_max_d(double v) {
     return v;
 }
 
-// Box of every kLjBoxPoints-point block of the (stage) positions: a block of
-// threads covers kBlock points, one box per wave.
+// Box of every LJ source block (at most kLjBlockPoints consecutive points of
+// one filament) of the (stage) positions: one wave per block.
 __global__ __launch_bounds__(kBlock) void k_lj_boxes(int stage_state, const EnsDesc *__restrict__ desc,
                                                      const PointItem *__restrict__ items) {
     const PointItem it = items[blockIdx.x];
     const EnsDesc &E = desc[it.ens];
+    const int b = it.p0 + (int)(threadIdx.x >> 6);
+    if (b >= E.n_ljblk) return;  // wave-uniform
     const int N = E.N;
-    const int wbase = it.p0 + (int)(threadIdx.x & ~63u);
-    if (wbase >= N) return;  // wave-uniform: no point of this wave exists
     const double *__restrict__ X = stage_state ? E.Xs : E.X;
-    const int i = it.p0 + (int)threadIdx.x;
-    const bool real = i < N;
+    const int k = E.lj_blk[3 * b] + (int)(threadIdx.x & 63);
+    const bool real = k < E.lj_blk[3 * b + 1];
     double lo[3], hi[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        const double v = real ? X[(size_t)c * N + i] : 0.0;
+        const double v = real ? X[(size_t)c * N + k] : 0.0;
         lo[c] = wave_min_d(real ? v : INFINITY);
         hi[c] = wave_max_d(real ? v : -INFINITY);
     }
     if ((threadIdx.x & 63) == 0) {
-        double *bx = E.lj_box + 6 * (size_t)(wbase / kLjBoxPoints);
+        double *bx = E.lj_box + 6 * (size_t)b;
 #pragma unroll
         for (int c = 0; c < 3; c++) { bx[c] = lo[c]; bx[3 + c] = hi[c]; }
     }
@@ -345,64 +345,71 @@ __global__ __launch_bounds__(kBlock) void k_lj_boxes(int stage_state, const EnsD
 
 // Lennard-Jones force on every point (Sec. IV): the sum over points of other
 // filaments closer than r_c of 24 e (2 (sig/r)^12 - (sig/r)^6) (x_i - x_j)/r^2,
-// in source order.  A wave skips every source block whose box lies at least
-// r_c from the box of its own 64 points.  It also flags its block when any of
-// its points is pushed: the FP32C pair kernels sum such source blocks in
-// FP64, since the equal and opposite contact forces largely cancel at a
-// distance and FP32 terms would leave their rounding behind.
+// in source order.  The boxes of the LJ source blocks are staged through LDS;
+// a wave visits a block only when one of its lanes lies within r_c of the
+// block's box.  Each wave also writes the LJ mask of its 64 points: the FP32C
+// pair kernels evaluate those sources in FP64, since the equal and opposite
+// contact forces largely cancel at a distance and FP32 terms would leave
+// their rounding behind.
 __global__ __launch_bounds__(kBlock) void k_lj_forces(int stage_state, const EnsDesc *__restrict__ desc,
                                                       const PointItem *__restrict__ items) {
+    __shared__ double sBox[kBlock][6];
+    __shared__ int sBlk[kBlock][3];
     const PointItem it = items[blockIdx.x];
     const EnsDesc &E = desc[it.ens];
     const int N = E.N;
-    const int wbase = it.p0 + (int)(threadIdx.x & ~63u);
-    if (wbase >= N) return;  // wave-uniform
     const double *__restrict__ X = stage_state ? E.Xs : E.X;
-    const int i = it.p0 + (int)threadIdx.x;
+    const int tid = threadIdx.x;
+    const int i = it.p0 + tid;
     const bool real = i < N;
     const int ii = real ? i : N - 1;
     const double x0 = X[ii], x1 = X[(size_t)N + ii], x2 = X[2 * (size_t)N + ii];
     const int fi = E.fil[ii];
-    const double xs[3] = {x0, x1, x2};
-    double lo[3], hi[3];
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        lo[c] = wave_min_d(real ? xs[c] : INFINITY);
-        hi[c] = wave_max_d(real ? xs[c] : -INFINITY);
-    }
     const double rc = E.lj_rc, rc2 = rc * rc, sig2 = E.lj_sig * E.lj_sig, c24 = 24.0 * E.lj_e;
     double acc[3] = {0.0, 0.0, 0.0};
-    const int nb = (N + kLjBoxPoints - 1) / kLjBoxPoints;
-    for (int b = 0; b < nb; b++) {
-        const double *bx = E.lj_box + 6 * (size_t)b;
-        double gap2 = 0.0;
+    const int nblk = E.n_ljblk;
+    for (int b0 = 0; b0 < nblk; b0 += kBlock) {
+        __syncthreads();
+        if (b0 + tid < nblk) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) {
-            const double g = fmax(0.0, fmax(lo[c] - bx[3 + c], bx[c] - hi[c]));
-            gap2 += g * g;
+            for (int c = 0; c < 6; c++) sBox[tid][c] = E.lj_box[6 * (size_t)(b0 + tid) + c];
+#pragma unroll
+            for (int c = 0; c < 3; c++) sBlk[tid][c] = E.lj_blk[3 * (b0 + tid) + c];
         }
-        if (!(gap2 < rc2)) continue;  // wave-uniform
-        const int j1 = min(N, (b + 1) * kLjBoxPoints);
-        for (int j = b * kLjBoxPoints; j < j1; j++) {
-            if (E.fil[j] == fi) continue;
-            const double r0 = x0 - X[j], r1 = x1 - X[(size_t)N + j], r2 = x2 - X[2 * (size_t)N + j];
-            const double rr2 = r0 * r0 + r1 * r1 + r2 * r2;
-            if (!(sqrt(rr2) < rc)) continue;
-            const double s2 = sig2 / rr2, s6 = s2 * s2 * s2;
-            const double cf = c24 * (2.0 * s6 * s6 - s6) / rr2;
-            acc[0] += cf * r0;
-            acc[1] += cf * r1;
-            acc[2] += cf * r2;
+        __syncthreads();
+        const int cnt = min(kBlock, nblk - b0);
+        for (int bb = 0; bb < cnt; bb++) {
+            double gap2 = 0.0;
+            const double xs[3] = {x0, x1, x2};
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const double g = fmax(0.0, fmax(sBox[bb][c] - xs[c], xs[c] - sBox[bb][3 + c]));
+                gap2 += g * g;
+            }
+            const bool near = real && gap2 < rc2 && sBlk[bb][2] != fi;
+            if (!__any(near ? 1 : 0)) continue;  // wave-uniform
+            if (!near) continue;
+            const int j1 = sBlk[bb][1];
+            for (int j = sBlk[bb][0]; j < j1; j++) {
+                const double r0 = x0 - X[j], r1 = x1 - X[(size_t)N + j], r2 = x2 - X[2 * (size_t)N + j];
+                const double rr2 = r0 * r0 + r1 * r1 + r2 * r2;
+                if (!(sqrt(rr2) < rc)) continue;
+                const double s2 = sig2 / rr2, s6 = s2 * s2 * s2;
+                const double cf = c24 * (2.0 * s6 * s6 - s6) / rr2;
+                acc[0] += cf * r0;
+                acc[1] += cf * r1;
+                acc[2] += cf * r2;
+            }
         }
     }
     if (real) {
 #pragma unroll
         for (int c = 0; c < 3; c++) E.flj[(size_t)c * N + i] = acc[c];
     }
-    // this wave's 64 points are one block: flag it when any point is pushed
     const bool pushed = real && (acc[0] != 0.0 || acc[1] != 0.0 || acc[2] != 0.0);
-    const int any = __any(pushed ? 1 : 0);
-    if ((threadIdx.x & 63) == 0) E.lj_flag[wbase / kLjBoxPoints] = any ? 1 : 0;
+    const uint64_t mask = __ballot(pushed ? 1 : 0);
+    const int wbase = it.p0 + (tid & ~63);
+    if ((tid & 63) == 0 && wbase < N) E.lj_mask[wbase / kLjMaskPoints] = mask;
 }
 
 // ------------------------------------------------------- reduce + epilogue
@@ -574,9 +581,10 @@ hipError_t launch_rod_forces(int prec, int stage_state, int elastic, int scheme,
     return hipGetLastError();
 }
 
-hipError_t launch_lj(int stage_state, const EnsDesc *d_desc, const PointItem *d_items, int n_items, hipStream_t s) {
+hipError_t launch_lj(int stage_state, const EnsDesc *d_desc, const PointItem *d_box_items, int n_box_items,
+                     const PointItem *d_items, int n_items, hipStream_t s) {
     if (n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lj_boxes, dim3(n_items), dim3(kBlock), 0, s, stage_state, d_desc, d_items);
+    hipLaunchKernelGGL(k_lj_boxes, dim3(n_box_items), dim3(kBlock), 0, s, stage_state, d_desc, d_box_items);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lj_forces, dim3(n_items), dim3(kBlock), 0, s, stage_state, d_desc, d_items);

@@ -241,9 +241,16 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
             const float h = lo[k] <= hi[k] ? 0.5f * (hi[k] - lo[k]) : 0.0f;
             hd2 = fmaf(h, h, hd2);
         }
-        sW[tid] = make_float4((a.x - ctr[0]) + b.x, (a.y - ctr[1]) + b.y, (a.z - ctr[2]) + b.z, a.w);
-        sF[tid] = make_float4(b.w, cc.x, cc.y, cc.z);
-        sN[tid] = make_float4(cc.w, b.x, b.y, b.z);
+        // a source with contact forces enters the FP32 sums with zero loads;
+        // the FP64 pass evaluates it with its own loads
+        bool contact = false;
+        if (E.lj_mask && real) {
+            const int jg = it.src0 + j;
+            contact = (E.lj_mask[jg / kLjMaskPoints] >> (jg % kLjMaskPoints)) & 1;
+        }
+        sW[tid] = make_float4((a.x - ctr[0]) + b.x, (a.y - ctr[1]) + b.y, (a.z - ctr[2]) + b.z, contact ? 0.0f : a.w);
+        sF[tid] = contact ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(b.w, cc.x, cc.y, cc.z);
+        sN[tid] = make_float4(contact ? 0.0f : cc.w, b.x, b.y, b.z);
         sH[tid] = make_float4(a.x, a.y, a.z, 0.0f);
         if ((tid & 63) == 0) {
             float *bx = sBox[tid >> 6];
@@ -265,12 +272,9 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
             }
             const float *bx = sBox[sb / kKahanBlock];
             const float gap2 = box_gap2(tlo, thi, bx, bx + 3);
-            if (E.lj_flag && E.lj_flag[(it.src0 + base + sb) / kLjBoxPoints]) {
-                // a block carrying contact forces (wave-uniform): every pair
-                // goes to the FP64 pass below
-#pragma unroll
-                for (int t = 0; t < T; t++) near[t] = ~uint64_t(0);
-            } else if (gap2 > kFarBoxGap2 && gap2 > kAnchorGapRatio2 * bx[9]) {
+            // sources of this block that carry contact forces (wave-uniform)
+            const uint64_t ljm = E.lj_mask ? E.lj_mask[(it.src0 + base + sb) / kLjMaskPoints] : 0;
+            if (gap2 > kFarBoxGap2 && gap2 > kAnchorGapRatio2 * bx[9]) {
                 // wave-uniform: no near pair, separation from the block's anchor
                 float ux[T], uy[T], uz[T];
 #pragma unroll
@@ -316,6 +320,9 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
                     }
                 }
             }
+            // the sources with contact forces join the FP64 pass for every target
+#pragma unroll
+            for (int t = 0; t < T; t++) near[t] |= ljm;
 #pragma unroll
             for (int t = 0; t < T; t++)
 #pragma unroll
@@ -333,8 +340,13 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
                         const int jj = sb + __builtin_ctzll(m);
                         m &= m - 1;
                         const float4 W = sW[jj], F = sF[jj], Nn = sN[jj], H = sH[jj];
+                        float fx = W.w, fy = F.x, fz = F.y, nx = F.z, ny = F.w, nz = Nn.x;
+                        if ((ljm >> (jj - sb)) & 1) {  // staged with zero loads: take them from the record
+                            const RecF32 r = rec[it.src0 + base + jj];
+                            fx = r.a.w; fy = r.b.w; fz = r.c.x; nx = r.c.y; ny = r.c.z; nz = r.c.w;
+                        }
                         near_pair_f64(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], H.x, H.y, H.z, Nn.y, Nn.z,
-                                      Nn.w, W.w, F.x, F.y, F.z, F.w, Nn.x, pn);
+                                      Nn.w, fx, fy, fz, nx, ny, nz, pn);
                     } while (m);
 #pragma unroll
                     for (int k = 0; k < 6; k++) sNear[k][t][tid] = pn[k];
@@ -445,8 +457,9 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
                 for (int k = 0; k < 6; k++) p[t][k] = 0.f;
             const int jend = min(j0 + 64 * kPerLane, it.nsrc);
             for (int j = j0 + lane; j < jend; j += 64) {
-                if (E.lj_flag && E.lj_flag[(it.src0 + j) / kLjBoxPoints]) {
-                    rmin = 0.0f;  // a source of a block with contact forces: FP64 below
+                const int jg = it.src0 + j;
+                if (E.lj_mask && ((E.lj_mask[jg / kLjMaskPoints] >> (jg % kLjMaskPoints)) & 1)) {
+                    rmin = 0.0f;  // a source with contact forces: FP64 below
                     continue;
                 }
                 const RecF32 r = rec[it.src0 + j];
@@ -461,7 +474,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
             if (rmin < kNearR2) {  // near pairs and contact-force blocks of this lane's sources: FP64
                 for (int j = j0 + lane; j < jend; j += 64) {
                     const RecF32 r = rec[it.src0 + j];
-                    const bool strong = E.lj_flag && E.lj_flag[(it.src0 + j) / kLjBoxPoints];
+                    const int jg = it.src0 + j;
+                    const bool strong = E.lj_mask && ((E.lj_mask[jg / kLjMaskPoints] >> (jg % kLjMaskPoints)) & 1);
 #pragma unroll
                     for (int t = 0; t < TW; t++) {
                         float rx, ry, rz;

@@ -115,6 +115,7 @@ void near_blocks_first(std::vector<PairItem> &v) {
 void add_lj_items(Plan &P, int e, const mrs_ensemble *E) {
     if (!E->has_lj) return;
     for (int64_t p0 = 0; p0 < E->N; p0 += kBlock) P.lj.push_back({e, (int)p0});
+    for (int b0 = 0; b0 < E->n_ljblk; b0 += kBlock / 64) P.ljb.push_back({e, b0});
 }
 
 hipError_t finalize_plan(Plan &P) {
@@ -127,6 +128,7 @@ hipError_t finalize_plan(Plan &P) {
     if ((e = upload_vec(P.d_tile2, P.tile2)) != hipSuccess) return e;
     if ((e = upload_vec(P.d_rods, P.rods)) != hipSuccess) return e;
     if ((e = upload_vec(P.d_lj, P.lj)) != hipSuccess) return e;
+    if ((e = upload_vec(P.d_ljb, P.ljb)) != hipSuccess) return e;
     return upload_vec(P.d_pts, P.pts);
 }
 
@@ -173,8 +175,10 @@ static EnsDesc ensemble_desc(mrs_ensemble *E, int prec, const PairCfg &c) {
     d.lj_rc = std::pow(2.0, 1.0 / 6.0) * E->lj[0];
     d.fil = E->has_lj ? E->fil.as<int32_t>() : nullptr;
     d.flj = E->has_lj ? E->flj.as<double>() : nullptr;
+    d.n_ljblk = E->has_lj ? E->n_ljblk : 0;
+    d.lj_blk = E->has_lj ? E->lj_blk.as<int32_t>() : nullptr;
     d.lj_box = E->has_lj ? E->lj_box.as<double>() : nullptr;
-    d.lj_flag = E->has_lj ? E->lj_flag.as<int32_t>() : nullptr;
+    d.lj_mask = E->has_lj ? E->lj_mask.as<uint64_t>() : nullptr;
     return d;
 }
 
@@ -250,7 +254,8 @@ hipError_t run_stage(mrs_context *ctx, Plan &P, int stage_state, int elastic, in
     hipError_t e = hipSuccess;
     if (!P.lj.empty()) {
         e = timed(ctx, "lj_forces", s, [&] {
-            return launch_lj(stage_state, P.d_desc.as<EnsDesc>(), P.d_lj.as<PointItem>(), (int)P.lj.size(), s);
+            return launch_lj(stage_state, P.d_desc.as<EnsDesc>(), P.d_ljb.as<PointItem>(), (int)P.ljb.size(),
+                             P.d_lj.as<PointItem>(), (int)P.lj.size(), s);
         });
         if (e != hipSuccess) return e;
     }
@@ -384,20 +389,27 @@ mrs_status ensemble_alloc(mrs_context *ctx, int32_t n_fil, const int32_t *offset
 }
 
 // Buffers of the Lennard-Jones repulsion: the filament of every point, the
-// force per point and the box of every kLjBoxPoints-point block.
+// force per point, the source blocks (at most kLjBlockPoints consecutive
+// points of one filament) with their boxes, and the per-64-point masks.
 static mrs_status lj_buffers(mrs_ensemble *E) {
     mrs_context *ctx = E->ctx;
-    const int64_t n = E->N, nb = (n + kLjBoxPoints - 1) / kLjBoxPoints;
+    const int64_t n = E->N, nm = (n + kLjMaskPoints - 1) / kLjMaskPoints;
+    std::vector<int32_t> fil((size_t)std::max<int64_t>(n, 1), 0), blk;
+    for (int32_t f = 0; f < E->n_fil; f++) {
+        for (int32_t k = E->offsets[f]; k < E->offsets[f + 1]; k++) fil[k] = f;
+        for (int32_t k = E->offsets[f]; k < E->offsets[f + 1]; k += kLjBlockPoints)
+            blk.insert(blk.end(), {k, std::min(k + kLjBlockPoints, E->offsets[f + 1]), f});
+    }
+    E->n_ljblk = (int32_t)(blk.size() / 3);
     if (E->fil.reserve((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)) != hipSuccess ||
         E->flj.reserve((size_t)std::max<int64_t>(n, 1) * 3 * sizeof(double)) != hipSuccess ||
-        E->lj_box.reserve((size_t)std::max<int64_t>(nb, 1) * 6 * sizeof(double)) != hipSuccess ||
-        E->lj_flag.reserve((size_t)std::max<int64_t>(nb, 1) * sizeof(int32_t)) != hipSuccess)
+        E->lj_blk.reserve(std::max<size_t>(blk.size(), 1) * sizeof(int32_t)) != hipSuccess ||
+        E->lj_box.reserve((size_t)std::max<int32_t>(E->n_ljblk, 1) * 6 * sizeof(double)) != hipSuccess ||
+        E->lj_mask.reserve((size_t)std::max<int64_t>(nm, 1) * sizeof(uint64_t)) != hipSuccess)
         return fail(ctx, MRS_ENOMEM, "Lennard-Jones buffers");
-    std::vector<int32_t> fil((size_t)std::max<int64_t>(n, 1), 0);
-    for (int32_t f = 0; f < E->n_fil; f++)
-        for (int32_t k = E->offsets[f]; k < E->offsets[f + 1]; k++) fil[k] = f;
-    if (hipMemcpy(E->fil.p, fil.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
-        return fail(ctx, MRS_EDEVICE, "Lennard-Jones filament index upload");
+    if (hipMemcpy(E->fil.p, fil.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(E->lj_blk.p, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(ctx, MRS_EDEVICE, "Lennard-Jones index upload");
     return MRS_OK;
 }
 

@@ -58,8 +58,9 @@ struct Plan {
     std::vector<PairItem> split, tile1, tile2;
     std::vector<RodItem> rods;
     std::vector<PointItem> pts;
-    std::vector<PointItem> lj;  // kBlock-point blocks of the ensembles with LJ repulsion
-    DevBuf d_desc, d_split, d_tile1, d_tile2, d_rods, d_pts, d_lj;
+    std::vector<PointItem> lj;   // kBlock-point target blocks of the ensembles with LJ repulsion
+    std::vector<PointItem> ljb;  // their LJ source blocks, kBlock / 64 per item
+    DevBuf d_desc, d_split, d_tile1, d_tile2, d_rods, d_pts, d_lj, d_ljb;
     // cached graphs: key = (integrator, dt bits, steps, elastic)
     std::map<std::tuple<int, uint64_t, int, int>, hipGraphExec_t> graphs;
     int64_t pairs_per_eval = 0;
@@ -114,7 +115,9 @@ struct mrs_ensemble {
     double wave[3] = {0, 0, 0}, lj[2] = {0, 0};
     mrs::DevBuf off, X, D, U, W, Xs, Ds, Ua, Wa, fext, next, rec, part;
     mrs::DevBuf clock;              // time at the start of the next step (one double)
-    mrs::DevBuf fil, flj, lj_box, lj_flag;  // with LJ: filament per point, forces, block boxes and flags
+    int32_t n_ljblk = 0;
+    mrs::DevBuf fil, flj, lj_blk, lj_box, lj_mask;  // with LJ: filament per point, forces, source
+                                                    // blocks and their boxes, masks
     std::unique_ptr<mrs::Plan> plan[2];  // per precision
 };
 
