@@ -308,6 +308,7 @@ def bench_config4(mrs, ctx, n_req, rates, slots, budget, tick_pairs=0):
     rods = [mrs.rod_params(*(getattr(e.rod(), k) for k in ("a", "b", "omega0", "ds"))) for e in ens]
 
     def run(rate, nslots):
+        log(f"serving {n_req} requests at {rate} req/s with {nslots} slots")
         arr = synth.poisson_arrivals(n_req, rate)
         srv = mrs.mrs_server_start(ctx, mrs.MRS_FP32C, budget, nslots)
         mrs.mrs_server_set_tick_pairs(srv, int(tick_pairs) if nslots > 1 else 0)
