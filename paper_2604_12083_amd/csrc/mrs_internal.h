@@ -114,7 +114,7 @@ hipError_t launch_rod_forces(int prec, int stage_state, int elastic, int scheme,
 // Lennard-Jones forces of the ensembles with has_lj: the box of every LJ
 // source block (box items: (ensemble, first of kBlock / 64 blocks)), then the
 // force on every point and the LJ masks (target items: (ensemble, first of
-// kBlock consecutive points)).
+// kLjMaskPoints consecutive points)).
 hipError_t launch_lj(int stage_state, const EnsDesc *d_desc, const PointItem *d_box_items, int n_box_items,
                      const PointItem *d_items, int n_items, hipStream_t s);
 hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, const PairItem *d_items,

@@ -344,23 +344,26 @@ __global__ __launch_bounds__(kBlock) void k_lj_boxes(int stage_state, const EnsD
 }
 
 // Lennard-Jones force on every point (Sec. IV): the sum over points of other
-// filaments closer than r_c of 24 e (2 (sig/r)^12 - (sig/r)^6) (x_i - x_j)/r^2,
-// in source order.  The boxes of the LJ source blocks are staged through LDS;
-// a wave visits a block only when one of its lanes lies within r_c of the
-// block's box.  Each wave also writes the LJ mask of its 64 points: the FP32C
-// pair kernels evaluate those sources in FP64, since the equal and opposite
-// contact forces largely cancel at a distance and FP32 terms would leave
-// their rounding behind.
+// filaments closer than r_c of 24 e (2 (sig/r)^12 - (sig/r)^6) (x_i - x_j)/r^2.
+// A block owns 64 points (one per lane); its 4 waves split the LJ source
+// blocks (wave w takes every 4th staged box), visit a block only when one of
+// their lanes lies within r_c of its box, and their partial forces are added
+// in wave order.  The block also writes the LJ mask of its 64 points: the
+// FP32C pair kernels evaluate those sources in FP64, since the equal and
+// opposite contact forces largely cancel at a distance and FP32 terms would
+// leave their rounding behind.
 __global__ __launch_bounds__(kBlock) void k_lj_forces(int stage_state, const EnsDesc *__restrict__ desc,
                                                       const PointItem *__restrict__ items) {
+    constexpr int kWaves = kBlock / 64;
     __shared__ double sBox[kBlock][6];
     __shared__ int sBlk[kBlock][3];
+    __shared__ double sPart[kWaves][3][64];
     const PointItem it = items[blockIdx.x];
     const EnsDesc &E = desc[it.ens];
     const int N = E.N;
     const double *__restrict__ X = stage_state ? E.Xs : E.X;
-    const int tid = threadIdx.x;
-    const int i = it.p0 + tid;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int i = it.p0 + lane;
     const bool real = i < N;
     const int ii = real ? i : N - 1;
     const double x0 = X[ii], x1 = X[(size_t)N + ii], x2 = X[2 * (size_t)N + ii];
@@ -378,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_lj_forces(int stage_state, const Ens
         }
         __syncthreads();
         const int cnt = min(kBlock, nblk - b0);
-        for (int bb = 0; bb < cnt; bb++) {
+        for (int bb = w; bb < cnt; bb += kWaves) {
             double gap2 = 0.0;
             const double xs[3] = {x0, x1, x2};
 #pragma unroll
@@ -402,14 +405,24 @@ __global__ __launch_bounds__(kBlock) void k_lj_forces(int stage_state, const Ens
             }
         }
     }
+#pragma unroll
+    for (int c = 0; c < 3; c++) sPart[w][c][lane] = acc[c];
+    __syncthreads();
+    if (w != 0) return;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        double v = sPart[0][c][lane];
+#pragma unroll
+        for (int q = 1; q < kWaves; q++) v += sPart[q][c][lane];
+        acc[c] = v;
+    }
     if (real) {
 #pragma unroll
         for (int c = 0; c < 3; c++) E.flj[(size_t)c * N + i] = acc[c];
     }
     const bool pushed = real && (acc[0] != 0.0 || acc[1] != 0.0 || acc[2] != 0.0);
     const uint64_t mask = __ballot(pushed ? 1 : 0);
-    const int wbase = it.p0 + (tid & ~63);
-    if ((tid & 63) == 0 && wbase < N) E.lj_mask[wbase / kLjMaskPoints] = mask;
+    if (lane == 0 && it.p0 < N) E.lj_mask[it.p0 / kLjMaskPoints] = mask;
 }
 
 // ------------------------------------------------------- reduce + epilogue

@@ -114,7 +114,7 @@ void near_blocks_first(std::vector<PairItem> &v) {
 
 void add_lj_items(Plan &P, int e, const mrs_ensemble *E) {
     if (!E->has_lj) return;
-    for (int64_t p0 = 0; p0 < E->N; p0 += kBlock) P.lj.push_back({e, (int)p0});
+    for (int64_t p0 = 0; p0 < E->N; p0 += kLjMaskPoints) P.lj.push_back({e, (int)p0});
     for (int b0 = 0; b0 < E->n_ljblk; b0 += kBlock / 64) P.ljb.push_back({e, b0});
 }
 

@@ -58,7 +58,7 @@ struct Plan {
     std::vector<PairItem> split, tile1, tile2;
     std::vector<RodItem> rods;
     std::vector<PointItem> pts;
-    std::vector<PointItem> lj;   // kBlock-point target blocks of the ensembles with LJ repulsion
+    std::vector<PointItem> lj;   // 64-point target blocks of the ensembles with LJ repulsion
     std::vector<PointItem> ljb;  // their LJ source blocks, kBlock / 64 per item
     DevBuf d_desc, d_split, d_tile1, d_tile2, d_rods, d_pts, d_lj, d_ljb;
     // cached graphs: key = (integrator, dt bits, steps, elastic)
