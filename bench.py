@@ -145,25 +145,40 @@ def measure(mrs, ctx, e, prec, steps, warmup, dt, integ=None, swim=None):
         mrs.mrs_ensemble_destroy(ens)
 
 
-def cpu_baseline(mrs, ctx, e, prec_list, swim=None):
+def cpu_baseline(mrs, ctx, e, prec_list, swim=None, workload_name=""):
     """The FP64 oracle as it stands, on this host's cores, on a bounded sample:
     the rod forces of the whole ensemble plus the MRS sum for a subset of
-    targets; also the GPU's max relative error on that subset."""
+    targets (the 2,048-target check subset at 256,000 points, else 1,024
+    seeded targets); also the same on one core, and the GPU's max relative
+    error on that subset."""
     import oracle
+    import synth
 
-    n_t = min(e.N, 1024)
-    idx = np.sort(np.random.default_rng(7).choice(e.N, n_t, replace=False))
+    if workload_name == "config5":
+        idx = synth.config5_subset(e.N)
+    else:
+        idx = np.sort(np.random.default_rng(7).choice(e.N, min(e.N, 1024), replace=False))
+    n_t = len(idx)
     rp = swim.rod if swim is not None else e.rod()
     kw = {} if swim is None else {"wave": swim.wave, "t": 0.0, "lj": swim.lj}
-    t0 = time.perf_counter()
-    reps = 0
-    while True:
-        g, m = oracle.rod_forces(e.offsets, e.X, e.D, rp, e.f, e.n, **kw)
-        Uo, Wo = oracle.mrs_field(e.X[idx], e.X, g, m, e.eps, e.mu)
-        reps += 1
-        if time.perf_counter() - t0 > 10.0 or reps >= 5000:
-            break
-    dt = time.perf_counter() - t0
+
+    def timed_reps(limit_s):
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            g, m = oracle.rod_forces(e.offsets, e.X, e.D, rp, e.f, e.n, **kw)
+            Uo, Wo = oracle.mrs_field(e.X[idx], e.X, g, m, e.eps, e.mu)
+            reps += 1
+            if time.perf_counter() - t0 > limit_s or reps >= 5000:
+                return reps, time.perf_counter() - t0, Uo, Wo
+
+    cores = oracle.num_threads()
+    reps, dt, Uo, Wo = timed_reps(10.0)
+    oracle.set_num_threads(1)
+    try:
+        reps1, dt1, _, _ = timed_reps(3.0)
+    finally:
+        oracle.set_num_threads(cores)
     pairs = reps * n_t * e.N
     errs = {}
     rod = mrs.rod_params(*(getattr(rp, k) for k in ("a", "b", "omega0", "ds")))
@@ -178,15 +193,20 @@ def cpu_baseline(mrs, ctx, e, prec_list, swim=None):
                 "U": oracle.rel_err(U[idx], Uo), "Omega": oracle.rel_err(W[idx], Wo)}
     finally:
         mrs.mrs_ensemble_destroy(ens)
-    return {
+    out = {
         "value": pairs / dt,
         "unit": "pairs/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"rod forces of all {e.N} points + MRS sum for {n_t} seeded targets x {e.N} sources, "
                   f"repeated {reps}x ({dt:.1f} s)",
+        "value_1core": reps1 * n_t * e.N / dt1,
         "cpu": cpu_model(),
-    }, errs
+    }
+    if n_t < e.N:
+        # time of one full N^2 evaluation at the measured rate (not measured)
+        out["extrapolated_full_eval_s"] = e.N * e.N / out["value"]
+    return out, errs
 
 
 def cpu_model():
@@ -446,7 +466,7 @@ def main():
         cpu, errs = (None, None)
         if not args.no_cpu:
             log("cpu baseline (oracle)")
-            cpu, errs = cpu_baseline(mrs, ctx, e, [mrs.MRS_FP32C, mrs.MRS_FP64], swim)
+            cpu, errs = cpu_baseline(mrs, ctx, e, [mrs.MRS_FP32C, mrs.MRS_FP64], swim, args.workload)
     finally:
         mrs.mrs_context_destroy(ctx)
 
