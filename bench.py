@@ -34,10 +34,10 @@ FLOPS_PER_PAIR = 92       # algorithmic flops of one (target, source) evaluation
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_12083_amd", "csrc", "mrs_pairs.hip")
 MEASURED_TRAFFIC = {
     "0397d2201a897893c80851214f38ac91811750e8221b642e13d82cdf0b244fb6": {
-        ("config2", "fp32c"): (2653.83 * 2.0 + 30000.0) * 1024,
-        ("config2", "fp64"): (4134.46 * 2.0 + 30000.0) * 1024,
-        ("config5", "fp32c"): (271870.97 * 2.0 + 204000.0) * 1024,
-        ("config5", "fp64"): (849082.72 * 2.0 + 396000.0) * 1024,
+        ("ens12800", "fp32c"): (2653.83 * 2.0 + 30000.0) * 1024,
+        ("ens12800", "fp64"): (4134.46 * 2.0 + 30000.0) * 1024,
+        ("ens256000", "fp32c"): (271870.97 * 2.0 + 204000.0) * 1024,
+        ("ens256000", "fp64"): (849082.72 * 2.0 + 396000.0) * 1024,
     },
 }
 
@@ -62,12 +62,12 @@ def workload(name):
     """(ensemble, description, swimming parameters or None)."""
     import synth
 
-    if name == "config1":
-        return synth.config1(), "1 filament x 64 points, eps = 1.5/64", None
-    if name == "config2":
-        return synth.config2(), "100 filaments x 128 points (12,800 points) in [0,10]^3, eps = 1.5/128", None
-    if name == "config5":
-        return synth.config5(), "1,000 filaments x 256 points (256,000 points) in [0,50]^3, eps = 1.5/256", None
+    if name == "rod64":
+        return synth.rod64(), "1 filament x 64 points, eps = 1.5/64", None
+    if name == "ens12800":
+        return synth.ens12800(), "100 filaments x 128 points (12,800 points) in [0,10]^3, eps = 1.5/128", None
+    if name == "ens256000":
+        return synth.ens256000(), "1,000 filaments x 256 points (256,000 points) in [0,50]^3, eps = 1.5/256", None
     if name == "swim":
         e = synth.swimmers(1000, box=40.0, seed=12)
         p = synth.swim_params(e)
@@ -154,8 +154,8 @@ def cpu_baseline(mrs, ctx, e, prec_list, swim=None, workload_name=""):
     import oracle
     import synth
 
-    if workload_name == "config5":
-        idx = synth.config5_subset(e.N)
+    if workload_name == "ens256000":
+        idx = synth.ens256000_subset(e.N)
     else:
         idx = np.sort(np.random.default_rng(7).choice(e.N, min(e.N, 1024), replace=False))
     n_t = len(idx)
@@ -241,13 +241,13 @@ def roofline(pairs_per_launch, avg_s, peak_tflops, traffic=None):
             "frac": round(ach / peak_tflops, 4), "traffic": traffic}
 
 
-def bench_config3(mrs, ctx, steps, args):
+def bench_slices(mrs, ctx, steps, args):
     """16 Parareal fine slices (32 x 100 points each), RK4 at dt = 1e-5, FP32C:
     one batched launch sequence replayed from HIP graphs vs one launch per
     kernel per slice per stage."""
     import synth
 
-    base, slices = synth.config3()
+    base, slices = synth.slices()
     rod = mrs.rod_params(*(getattr(base.rod(), k) for k in ("a", "b", "omega0", "ds")))
 
     def make():
@@ -284,7 +284,7 @@ def bench_parareal(mrs, ctx, prec, tol, coarse_steps):
     fine solve of the same 3,200 steps."""
     import synth
 
-    base, _ = synth.config3(n_slices=1)
+    base, _ = synth.slices(n_slices=1)
     rod = mrs.rod_params(*(getattr(base.rod(), k) for k in ("a", "b", "omega0", "ds")))
     # external torques scaled by 1e-2: with N(0,1) torques the frames spin at
     # ~3e4 rad/s and no explicit-Euler coarse step of the slice is meaningful
@@ -317,12 +317,12 @@ def bench_parareal(mrs, ctx, prec, tol, coarse_steps):
             "eta_vs_serial_fine": eta, "error_relative_to_displacement": eta_disp}
 
 
-def bench_config4(mrs, ctx, n_req, rates, slots, budget, tick_pairs=0):
+def bench_serving(mrs, ctx, n_req, rates, slots, budget, tick_pairs=0):
     """Serving: the fixed request sequence at Poisson arrival rates; continuous
     batching (many slots) vs one request at a time (one slot)."""
     import synth
 
-    reqs = synth.config4_requests()[:n_req]
+    reqs = synth.serving_requests()[:n_req]
     ens = [synth.filaments(r.n_fil, r.M, 10.0, r.seed) for r in reqs]
     out = {"requests": n_req, "points": [e.N for e in ens], "kinds": [r.kind for r in reqs]}
     rods = [mrs.rod_params(*(getattr(e.rod(), k) for k in ("a", "b", "omega0", "ds"))) for e in ens]
@@ -372,18 +372,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="config2",
-                    choices=["config1", "config2", "config5", "swim", "config3", "config4", "parareal", "copy"])
-    ap.add_argument("--requests", type=int, default=32, help="config4: prefix of the request sequence")
-    ap.add_argument("--rates", default="10,100,1000", help="config4: Poisson arrival rates (req/s)")
+    ap.add_argument("--workload", default="ens12800",
+                    choices=["rod64", "ens12800", "ens256000", "swim", "slices", "serving", "parareal", "copy"])
+    ap.add_argument("--requests", type=int, default=32, help="serving: prefix of the request sequence")
+    ap.add_argument("--rates", default="10,100,1000", help="serving: Poisson arrival rates (req/s)")
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--budget-gb", type=float, default=64.0)
-    ap.add_argument("--tick-pairs", type=float, default=2e10, help="config4: pair budget of one serving tick")
-    ap.add_argument("--dt", type=float, default=None, help="time step (default 1e-4 for config1, else 1e-6)")
+    ap.add_argument("--tick-pairs", type=float, default=2e10, help="serving: pair budget of one serving tick")
+    ap.add_argument("--dt", type=float, default=None, help="time step (default 1e-4 for rod64, else 1e-6)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     if args.dt is None:
-        args.dt = 1e-4 if args.workload == "config1" else 1e-6
+        args.dt = 1e-4 if args.workload == "rod64" else 1e-6
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the library is single-GPU; see the sharding notes)", file=sys.stderr)
@@ -414,7 +414,7 @@ def main():
                           "config": {"workload": "copy of 256 MiB float64", "bytes_read": nbytes,
                                      "bytes_written": nbytes}}), flush=True)
         return
-    if args.workload in ("config3", "config4", "parareal"):
+    if args.workload in ("slices", "serving", "parareal"):
         ctx = mrs.mrs_context_create(0)
         try:
             if args.workload == "parareal":
@@ -427,27 +427,27 @@ def main():
                         "data": "synthetic",
                         "config": {"workload": "parareal: 32 filaments x 100 points (torques x 1e-2), 16 slices"},
                         "parareal": r}
-            elif args.workload == "config3":
-                r = bench_config3(mrs, ctx, args.steps, args)
+            elif args.workload == "slices":
+                r = bench_slices(mrs, ctx, args.steps, args)
                 line = {"metric": METRIC, "value": r["batched_pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
                         "steps": args.steps, "warmup": args.warmup,
                         "ms_per_step": 1e3 * r["batched_graph_s"] / args.steps, "higher_is_better": True,
                         "scaling": "weak", "vs_baseline": None, "dtype": "f32c", "data": "synthetic",
-                        "config": {"workload": "config3: 16 Parareal fine slices x (32 filaments x 100 points), "
+                        "config": {"workload": "slices: 16 Parareal fine slices x (32 filaments x 100 points), "
                                                "RK4 dt=1e-5, batched + HIP graph vs plain per-slice launches"},
-                        "config3": r}
+                        "slices": r}
             else:
                 rates = [float(x) for x in args.rates.split(",")]
-                r = bench_config4(mrs, ctx, args.requests, rates, args.slots, int(args.budget_gb * (1 << 30)),
+                r = bench_serving(mrs, ctx, args.requests, rates, args.slots, int(args.budget_gb * (1 << 30)),
                                   args.tick_pairs)
                 best = r["batched"][str(rates[-1])]
                 line = {"metric": METRIC, "value": best["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
                         "steps": args.requests, "warmup": 0, "ms_per_step": best["p50_ms"],
                         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32c",
                         "data": "synthetic",
-                        "config": {"workload": f"config4: first {args.requests} requests of the serving sequence, "
+                        "config": {"workload": f"serving: first {args.requests} requests of the serving sequence, "
                                                "Poisson arrivals, continuous batching"},
-                        "config4": r}
+                        "serving": r}
         finally:
             mrs.mrs_context_destroy(ctx)
         print(json.dumps(line), flush=True)

@@ -38,12 +38,12 @@ __all__ = [
     "RodParams",
     "DEFAULT_ROD",
     "filaments",
-    "config1",
-    "config2",
-    "config3",
-    "config4_requests",
-    "config5",
-    "config5_subset",
+    "rod64",
+    "ens12800",
+    "slices",
+    "serving_requests",
+    "ens256000",
+    "ens256000_subset",
     "poisson_arrivals",
 ]
 
@@ -146,7 +146,7 @@ def filaments(F: int, M: int, box: float, seed, draw_loads: bool = True):
                     eps=1.5 * ds, mu=1.0, ds=ds)
 
 
-def config1() -> Ensemble:
+def rod64() -> Ensemble:
     """One filament of 64 points, X_k = (s_k, 0.1 sin 2 pi s_k, 0), s_k = k/64.
 
     Frames with plane normal e_z; eps = 1.5/64; mu = 1; f then n drawn
@@ -161,23 +161,23 @@ def config1() -> Ensemble:
     return Ensemble(np.array([0, M], dtype=np.int32), X, D, f, n, eps=1.5 * ds, mu=1.0, ds=ds)
 
 
-def config2() -> Ensemble:
+def ens12800() -> Ensemble:
     """100 filaments x 128 points in [0,10]^3 (12,800 points), seed 2."""
     return filaments(100, 128, 10.0, 2)
 
 
-def config5() -> Ensemble:
+def ens256000() -> Ensemble:
     """1,000 filaments x 256 points in [0,50]^3 (256,000 points), seed 5."""
     return filaments(1000, 256, 50.0, 5)
 
 
-def config5_subset(N: int = 256_000, k: int = 2048) -> np.ndarray:
+def ens256000_subset(N: int = 256_000, k: int = 2048) -> np.ndarray:
     """Seeded check subset of targets for the 256,000-point ensemble."""
     return np.sort(np.random.default_rng(55).choice(N, k, replace=False)).astype(np.int64)
 
 
-def config3(n_slices: int = 16, F: int = 32, M: int = 100, box: float = 10.0, seed: int = 3,
-            sigma: float = 1e-3):
+def slices(n_slices: int = 16, F: int = 32, M: int = 100, box: float = 10.0, seed: int = 3,
+           sigma: float = 1e-3):
     """Base ensemble (32 filaments x 100 points, seed 3) and n_slices perturbed copies.
 
     After the base draws, the same rng draws per slice: a position
@@ -268,7 +268,7 @@ class RequestSpec:
     seed: int
 
 
-def config4_requests(n_req: int = 256, seed: int = 4):
+def serving_requests(n_req: int = 256, seed: int = 4):
     """Fixed request sequence of the serving workload.
 
     Per request, drawn in this order from default_rng(seed): filament count

@@ -56,7 +56,7 @@ def test_batch_equals_alone_mixed_sizes(mrs, ctx, prec):
 
 @pytest.mark.parametrize("prec", [1, 0])
 def test_graph_replays_equal_eager(mrs, ctx, prec):
-    base, slices = synth.config3(n_slices=4)
+    base, slices = synth.slices(n_slices=4)
     g = [_create(mrs, ctx, e) for e in slices]
     h = [_create(mrs, ctx, e) for e in slices]
     try:
@@ -78,7 +78,7 @@ def test_graph_replays_equal_eager(mrs, ctx, prec):
 
 def test_batched_slices_parity_one_step(mrs, ctx):
     """Config-3 slices: one batched RK4 step of every slice against the oracle."""
-    base, slices = synth.config3(n_slices=16)
+    base, slices = synth.slices(n_slices=16)
     hs = [_create(mrs, ctx, e) for e in slices]
     try:
         mrs.mrs_batch_step(ctx, hs, mrs.MRS_RK4, 1e-5, 1, mrs.MRS_FP32C, True, use_graph=True)
@@ -90,7 +90,7 @@ def test_batched_slices_parity_one_step(mrs, ctx):
             ex = step_err(X1, Xo, e.X)
             worst = max(worst, ex)
             assert ex <= 1e-5
-        say(f"config3 batched RK4 step: worst dX rel err {worst:.3e}")
+        say(f"slices batched RK4 step: worst dX rel err {worst:.3e}")
     finally:
         for x in hs:
             mrs.mrs_ensemble_destroy(x)

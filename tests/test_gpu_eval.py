@@ -46,9 +46,9 @@ def _check(mrs, ctx, X, f, n, eps, mu, prec, tag, oracle_UW=None):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_config1_eval(mrs, ctx, prec):
-    e = synth.config1()
-    _check(mrs, ctx, e.X, e.f, e.n, e.eps, e.mu, prec, "config1")
+def test_rod64_eval(mrs, ctx, prec):
+    e = synth.rod64()
+    _check(mrs, ctx, e.X, e.f, e.n, e.eps, e.mu, prec, "rod64")
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -59,9 +59,9 @@ def test_sizes_and_ragged_tails(mrs, ctx, prec, N):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_config2_full(mrs, ctx, prec):
-    e = synth.config2()
-    _check(mrs, ctx, e.X, e.f, e.n, e.eps, e.mu, prec, "config2")
+def test_ens12800_full(mrs, ctx, prec):
+    e = synth.ens12800()
+    _check(mrs, ctx, e.X, e.f, e.n, e.eps, e.mu, prec, "ens12800")
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -115,12 +115,12 @@ def test_invalid_arguments(mrs, ctx):
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-def test_config5_full_size_sampled(mrs, ctx, prec):
+def test_ens256000_full_size_sampled(mrs, ctx, prec):
     """256,000 points, all targets evaluated on the GPU, 2,048 seeded targets
     checked one by one against the oracle."""
-    e = synth.config5()
-    sub = synth.config5_subset(e.N)
-    say(f"config5 N={e.N} prec={prec}")
+    e = synth.ens256000()
+    sub = synth.ens256000_subset(e.N)
+    say(f"ens256000 N={e.N} prec={prec}")
     U, W = eval_dev(mrs, ctx, e.X, e.f, e.n, e.eps, e.mu, prec)
     Uo, Wo = oracle.mrs_field(e.X[sub], e.X, e.f, e.n, e.eps, e.mu)
     eu, ew = oracle.rel_err(U[sub], Uo), oracle.rel_err(W[sub], Wo)

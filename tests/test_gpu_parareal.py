@@ -71,12 +71,12 @@ def test_parareal_converges_and_stops_at_tolerance(mrs, ctx):
     """Config-3 geometry with the external torques scaled by 1e-2 (smooth
     enough for a coarse Euler propagator): the increments fall by orders of
     magnitude per iteration and the iteration stops at the tolerance."""
-    base, slices = synth.config3(n_slices=1)
+    base, slices = synth.slices(n_slices=1)
     e = slices[0]
     h = mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, 1e-2 * e.n, e.eps, e.mu, rod_of(mrs, e.rod()))
     try:
         it, hist = mrs.mrs_parareal(ctx, h, 8, mrs.MRS_RK4, 1e-5, 20, 2, 8, 1e-11, mrs.MRS_FP64, True)
-        say(f"config3 slice (torques x 1e-2), 8 slices: {it} iterations, increments {hist}")
+        say(f"slices slice (torques x 1e-2), 8 slices: {it} iterations, increments {hist}")
         assert it < 8 and hist[-1] <= 1e-11
         assert np.all(np.diff(np.log10(hist)) < -1.0)
     finally:

@@ -87,12 +87,12 @@ def _perturb(e, seed, sx=2e-3, sr=0.05):
     return e
 
 
-@pytest.mark.parametrize("case", ["config1", "config2", "long300", "tiny", "bigturn"])
+@pytest.mark.parametrize("case", ["rod64", "ens12800", "long300", "tiny", "bigturn"])
 def test_rod_forces_parity(mrs, ctx, case):
-    if case == "config1":
-        e = _perturb(synth.config1(), 1)
-    elif case == "config2":
-        e = _perturb(synth.config2(), 2)
+    if case == "rod64":
+        e = _perturb(synth.rod64(), 1)
+    elif case == "ens12800":
+        e = _perturb(synth.ens12800(), 2)
     elif case == "long300":  # longer than one block chunk of nodes
         e = _perturb(synth.filaments(3, 300, 1.0, 3, draw_loads=True), 3)
     elif case == "tiny":  # filaments of 1 and 2 points

@@ -47,7 +47,7 @@ def _frame_err(Da, Db):
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("elastic", [True, False])
 def test_ensemble_eval(mrs, ctx, prec, elastic):
-    e = synth.config2()
+    e = synth.ens12800()
     ens = _create(mrs, ctx, e)
     try:
         mrs.mrs_ensemble_eval(ctx, ens, prec, elastic)
@@ -61,9 +61,9 @@ def test_ensemble_eval(mrs, ctx, prec, elastic):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_config1_euler_teacher_forced(mrs, ctx, prec):
+def test_rod64_euler_teacher_forced(mrs, ctx, prec):
     """Config 1: 64 points, 100 forward-Euler steps at dt = 1e-4."""
-    e = synth.config1()
+    e = synth.rod64()
     rod = e.rod()
     dt = 1e-4
     ens = _create(mrs, ctx, e)
@@ -80,7 +80,7 @@ def test_config1_euler_teacher_forced(mrs, ctx, prec):
             worst = [max(worst[0], ex), max(worst[1], ed), max(worst[2], eu)]
             assert ex <= TOL[prec] and ed <= TOL[prec] and eu <= TOL[prec], (step, ex, ed, eu)
             X, D = X1, D1
-        say(f"config1 euler prec={prec}: worst step dX {worst[0]:.3e} D {worst[1]:.3e} U/W {worst[2]:.3e}")
+        say(f"rod64 euler prec={prec}: worst step dX {worst[0]:.3e} D {worst[1]:.3e} U/W {worst[2]:.3e}")
         # frames stay orthonormal
         Dm = D.reshape(-1, 3, 3)
         assert np.abs(np.einsum("kij,klj->kil", Dm, Dm) - np.eye(3)).max() < 1e-14
@@ -92,7 +92,7 @@ def test_config1_euler_teacher_forced(mrs, ctx, prec):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_rk_teacher_forced(mrs, ctx, prec, integ):
     """Config-3 geometry (32 filaments x 100 points), RK4 / RK2 at dt = 1e-5."""
-    base, slices = synth.config3(n_slices=1)
+    base, slices = synth.slices(n_slices=1)
     e = slices[0]
     rod = e.rod()
     dt = 1e-5
@@ -111,10 +111,10 @@ def test_rk_teacher_forced(mrs, ctx, prec, integ):
         mrs.mrs_ensemble_destroy(ens)
 
 
-def test_free_running_config1_fp64(mrs, ctx):
+def test_free_running_rod64_fp64(mrs, ctx):
     """100 free-running Euler steps: reported against the oracle's own
     spread under a 1-ulp perturbation of the input."""
-    e = synth.config1()
+    e = synth.rod64()
     ens = _create(mrs, ctx, e)
     try:
         mrs.mrs_ensemble_step(ctx, ens, mrs.MRS_EULER, 1e-4, 100, mrs.MRS_FP64, True)
@@ -131,7 +131,7 @@ def test_free_running_config1_fp64(mrs, ctx):
 
 
 def test_invalid_step_arguments(mrs, ctx):
-    e = synth.config1()
+    e = synth.rod64()
     ens = _create(mrs, ctx, e)
     try:
         with pytest.raises(mrs.MrsError):

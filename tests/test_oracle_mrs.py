@@ -189,15 +189,15 @@ def test_bruteforce_mobility_matrix(oracle_mod, N):
 
 
 def test_config_shapes_and_frames():
-    e = synth.config1()
+    e = synth.rod64()
     assert e.N == 64 and e.eps == pytest.approx(1.5 / 64)
-    e2 = synth.config2()
+    e2 = synth.ens12800()
     assert e2.N == 12800 and e2.n_fil == 100
     for ens in (e, e2):
         D = ens.D.reshape(-1, 3, 3)
         np.testing.assert_allclose(np.einsum("kij,klj->kil", D, D), np.broadcast_to(np.eye(3), D.shape), atol=1e-14)
         np.testing.assert_allclose(np.linalg.det(D), 1.0, atol=1e-14)
-    again = synth.config2()
+    again = synth.ens12800()
     assert np.array_equal(again.X, e2.X) and np.array_equal(again.f, e2.f)
-    sub = synth.config5_subset()
+    sub = synth.ens256000_subset()
     assert len(sub) == 2048 and len(np.unique(sub)) == 2048

@@ -48,7 +48,7 @@ def test_convergence_orders(oracle_mod):
 
 
 def test_euler_step_composition(oracle_mod):
-    e = synth.config1()
+    e = synth.rod64()
     rod = e.rod()
     dt = 1e-4
     g, m = oracle_mod.rod_forces(e.offsets, e.X, e.D, rod, e.f, e.n)
@@ -77,7 +77,7 @@ def test_rk4_single_stage_quantities(oracle_mod):
 
 
 def test_frames_stay_orthonormal(oracle_mod):
-    e = synth.config1()
+    e = synth.rod64()
     X, D, _, _ = oracle_mod.step(e.offsets, e.X, e.D, e.rod(), e.f, e.n, e.eps, e.mu, oracle_mod.EULER, 1e-4, 20)
     Dm = D.reshape(-1, 3, 3)
     np.testing.assert_allclose(np.einsum("kij,klj->kil", Dm, Dm), np.broadcast_to(np.eye(3), Dm.shape), atol=1e-14)
