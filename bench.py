@@ -278,7 +278,7 @@ def bench_slices(mrs, ctx, steps, args):
 
 
 def bench_parareal(mrs, ctx, prec, tol, coarse_steps):
-    """Parareal on one GPU for the config-3 base ensemble (external torques
+    """Parareal on one GPU for the 3,200-point slice base ensemble (external torques
     scaled by 1e-2): 16 slices of 200 RK4 steps at dt = 1e-5 (fine), forward
     Euler with `coarse_steps` steps per slice (coarse), against the serial
     fine solve of the same 3,200 steps."""
@@ -300,6 +300,16 @@ def bench_parareal(mrs, ctx, prec, tol, coarse_steps):
         t0 = time.perf_counter()
         it, hist = mrs.mrs_parareal(ctx, a, 16, mrs.MRS_RK4, 1e-5, 200, coarse_steps, 16, tol, prec, True)
         tpar = time.perf_counter() - t0
+        c = mk()
+        try:
+            t0 = time.perf_counter()
+            itp, histp = mrs.mrs_parareal_pipelined(ctx, c, 16, mrs.MRS_RK4, 1e-5, 200, coarse_steps, 16, tol, prec,
+                                                    True)
+            tpipe = time.perf_counter() - t0
+            same = itp == it and np.array_equal(histp, hist) and np.array_equal(
+                mrs.mrs_ensemble_get(ctx, c)[0], mrs.mrs_ensemble_get(ctx, a)[0])
+        finally:
+            mrs.mrs_ensemble_destroy(c)
         t0 = time.perf_counter()
         mrs.mrs_ensemble_step(ctx, b, mrs.MRS_RK4, 1e-5, 16 * 200, prec, True)
         tser = time.perf_counter() - t0
@@ -313,8 +323,37 @@ def bench_parareal(mrs, ctx, prec, tol, coarse_steps):
         mrs.mrs_ensemble_destroy(b)
     return {"slices": 16, "fine": "RK4 x 200 at dt=1e-5 per slice", "coarse": f"Euler x {coarse_steps} per slice",
             "iterations": it, "increments": [float(x) for x in hist], "tol": tol, "parareal_s": tpar,
+            "pipelined_s": tpipe, "pipelined_identical": bool(same),
             "serial_fine_s": tser, "speedup_vs_serial": tser / tpar,
             "eta_vs_serial_fine": eta, "error_relative_to_displacement": eta_disp}
+
+
+def bench_schedules(mrs, ctx, prec, iters=4, fine_steps=(5, 20, 50, 200), coarse_steps=10):
+    """Regular against pipelined Parareal (Sec. II.D) on one GPU for several
+    fine/coarse cost ratios r: 16 slices of the 3,200-point slice ensemble,
+    fine RK4 x fine_steps, coarse Euler x coarse_steps, a fixed number of
+    iterations (tol = 0), so both schedules do the same work."""
+    import synth
+
+    base, _ = synth.slices(n_slices=1)
+    rod = mrs.rod_params(*(getattr(base.rod(), k) for k in ("a", "b", "omega0", "ds")))
+    tq = 1e-2 * base.n
+    mk = lambda: mrs.mrs_ensemble_create(ctx, base.offsets, base.X, base.D, base.f, tq, base.eps, base.mu, rod)
+    out = []
+    for fs in fine_steps:
+        row = {"fine_steps": fs, "coarse_steps": coarse_steps, "r_evals": 4 * fs / coarse_steps}
+        for name, fn, kw in (("regular", mrs.mrs_parareal, {}), ("pipelined", mrs.mrs_parareal_pipelined, {}),
+                             ("pipelined_g1", mrs.mrs_parareal_pipelined, {"group": 1})):
+            log(f"parareal schedules: {name} fine_steps={fs}")
+            h = mk()
+            try:
+                t0 = time.perf_counter()
+                fn(ctx, h, 16, mrs.MRS_RK4, 1e-5, fs, coarse_steps, iters, 0.0, prec, True, **kw)
+                row[name + "_s"] = time.perf_counter() - t0
+            finally:
+                mrs.mrs_ensemble_destroy(h)
+        out.append(row)
+    return out
 
 
 def bench_serving(mrs, ctx, n_req, rates, slots, budget, tick_pairs=0):
@@ -420,7 +459,8 @@ def main():
             if args.workload == "parareal":
                 r = {tag: bench_parareal(mrs, ctx, p, tol, 10) for tag, p, tol in
                      (("fp64", mrs.MRS_FP64, 1e-12), ("fp32c", mrs.MRS_FP32C, 1e-6))}
-                line = {"metric": "Parareal wall time on one GPU vs serial fine (config-3 base ensemble)",
+                r["schedules_fp32c"] = bench_schedules(mrs, ctx, mrs.MRS_FP32C)
+                line = {"metric": "Parareal wall time on one GPU vs serial fine (32 filaments x 100 points, 16 slices)",
                         "value": r["fp32c"]["speedup_vs_serial"], "unit": "x", "n_gpus": 1, "steps": 3200,
                         "warmup": 1, "ms_per_step": 1e3 * r["fp32c"]["parareal_s"] / 3200,
                         "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f32c",

@@ -316,6 +316,24 @@ mrs_status mrs_parareal(mrs_ensemble *ens, int32_t n_slices, mrs_integrator fine
                         int32_t fine_steps, int32_t coarse_steps, int32_t max_iter, double tol,
                         mrs_precision prec, int include_elastic, double *history, int32_t *iters);
 
+/* Parareal as mrs_parareal with the pipelined schedule of Sec. II.D (the
+ * fine solve of a slice starts as soon as the coarse sweep has produced its
+ * initial state): the slices are split into groups of `group` consecutive
+ * slices (group 0: ceil(n_slices / 4)); a group's fine propagations run as
+ * one batched launch sequence on one of up to three further streams of the
+ * context (default priority) as soon as the sweep has produced their start
+ * states, and the next sweep corrects
+ * each slice as soon as its group is done, so the serial coarse sweep
+ * overlaps the fine work.  The fine groups of iteration k + 1 start during
+ * sweep k only once the increment of the slices swept so far exceeds tol (so
+ * that no work is done that mrs_parareal would not do).  Same arguments,
+ * results (bit for bit: iterates, increments, iteration count) and errors as
+ * mrs_parareal, plus MRS_EINVAL for group outside [0, n_slices]. */
+mrs_status mrs_parareal_pipelined(mrs_ensemble *ens, int32_t n_slices, mrs_integrator fine_integ,
+                                  double fine_dt, int32_t fine_steps, int32_t coarse_steps, int32_t max_iter,
+                                  double tol, mrs_precision prec, int include_elastic, int32_t group,
+                                  double *history, int32_t *iters);
+
 /* ---- kernel timing ---------------------------------------------------- */
 
 /* When enabled, every kernel launch of the context is bracketed by HIP events

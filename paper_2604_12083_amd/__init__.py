@@ -122,6 +122,9 @@ _SIGS = {
     "mrs_tune_set": (_int, [_vp, _i64, _int, ctypes.POINTER(mrs_pair_config)]),
     "mrs_parareal": (_int, [_vp, ctypes.c_int32, _int, _dbl, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dbl,
                             _int, _int, _vp, ctypes.POINTER(ctypes.c_int32)]),
+    "mrs_parareal_pipelined": (_int, [_vp, ctypes.c_int32, _int, _dbl, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, _dbl, _int, _int, ctypes.c_int32, _vp,
+                                      ctypes.POINTER(ctypes.c_int32)]),
     "mrs_profile_enable": (_int, [_vp, _int]),
     "mrs_profile_select": (_int, [_vp, ctypes.c_char_p]),
     "mrs_profile_reset": (_int, [_vp]),
@@ -424,4 +427,15 @@ def mrs_parareal(ctx, ens, n_slices, fine_integ, fine_dt, fine_steps, coarse_ste
     _check(_lib.mrs_parareal(ens, int(n_slices), int(fine_integ), float(fine_dt), int(fine_steps), int(coarse_steps),
                              int(max_iter), float(tol), int(prec), int(bool(include_elastic)), _ptr(hist),
                              ctypes.byref(it)), ctx)
+    return int(it.value), hist[: it.value].copy()
+
+
+def mrs_parareal_pipelined(ctx, ens, n_slices, fine_integ, fine_dt, fine_steps, coarse_steps, max_iter, tol=0.0,
+                           prec=MRS_FP64, include_elastic=True, group=0):
+    """Pipelined schedule; returns (iterations done, relative increment per iteration)."""
+    hist = np.zeros(max(int(max_iter), 1))
+    it = ctypes.c_int32()
+    _check(_lib.mrs_parareal_pipelined(ens, int(n_slices), int(fine_integ), float(fine_dt), int(fine_steps),
+                                       int(coarse_steps), int(max_iter), float(tol), int(prec),
+                                       int(bool(include_elastic)), int(group), _ptr(hist), ctypes.byref(it)), ctx)
     return int(it.value), hist[: it.value].copy()

@@ -489,6 +489,8 @@ void mrs_context_destroy(mrs_context *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipStreamSynchronize(ctx->own_stream);
+    for (auto a : ctx->aux_stream)
+        if (a) (void)hipStreamSynchronize(a);
     auto ens = ctx->ensembles;
     for (auto *e : ens) mrs_ensemble_destroy(e);
     ctx->batch_plans.clear();
@@ -504,6 +506,8 @@ void mrs_context_destroy(mrs_context *ctx) {
     ctx->eval_desc.release();
     ctx->eval_items.release();
     ctx->eval_rod.release();
+    for (auto a : ctx->aux_stream)
+        if (a) (void)hipStreamDestroy(a);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
     delete ctx;
 }
@@ -968,6 +972,42 @@ static mrs_status check_batch(mrs_context *ctx, int32_t n_ens, mrs_ensemble *con
     return MRS_OK;
 }
 
+}  // extern "C"
+
+namespace mrs {
+
+mrs_status ensemble_enqueue(mrs_ensemble *E, int integ, double dt, int nsteps, int prec, int elastic,
+                            hipStream_t s) {
+    mrs_context *ctx = E->ctx;
+    Plan *P;
+    mrs_status st = ensemble_plan(E, prec, &P);
+    if (st != MRS_OK) return st;
+    HIPCHK(ctx, queue_steps(ctx, *P, integ, dt, nsteps, elastic, s));
+    return MRS_OK;
+}
+
+mrs_status batch_enqueue(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *ens, int integ, double dt,
+                         int nsteps, int prec, int elastic, int use_graph, hipStream_t s) {
+    Plan *P;
+    mrs_status st = batch_plan(ctx, n_ens, ens, prec, &P);
+    if (st != MRS_OK) return st;
+    if (use_graph && !ctx->prof_on)
+        HIPCHK(ctx, graph_steps(ctx, *P, integ, dt, nsteps, elastic, s));
+    else
+        HIPCHK(ctx, queue_steps(ctx, *P, integ, dt, nsteps, elastic, s));
+    return MRS_OK;
+}
+
+hipStream_t aux_stream(mrs_context *ctx, int i) {
+    hipStream_t &s = ctx->aux_stream[i];
+    if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    return s;
+}
+
+}  // namespace mrs
+
+extern "C" {
+
 mrs_status mrs_batch_step(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *ens, mrs_integrator integ,
                           double dt, int32_t nsteps, mrs_precision prec, int include_elastic, int use_graph) {
     CHECK_CTX(ctx);
@@ -975,13 +1015,9 @@ mrs_status mrs_batch_step(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *
     if (st != MRS_OK) return st;
     if ((st = check_step_args(ctx, integ, dt, nsteps, prec)) != MRS_OK) return st;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    Plan *P;
-    if ((st = batch_plan(ctx, n_ens, ens, (int)prec, &P)) != MRS_OK) return st;
-    const int el = include_elastic ? 1 : 0;
-    if (use_graph && !ctx->prof_on)
-        HIPCHK(ctx, graph_steps(ctx, *P, (int)integ, dt, nsteps, el, ctx->stream));
-    else
-        HIPCHK(ctx, queue_steps(ctx, *P, (int)integ, dt, nsteps, el, ctx->stream));
+    st = batch_enqueue(ctx, n_ens, ens, (int)integ, dt, nsteps, (int)prec, include_elastic ? 1 : 0, use_graph,
+                       ctx->stream);
+    if (st != MRS_OK) return st;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return MRS_OK;
 }

@@ -80,6 +80,8 @@ struct mrs_context {
     int n_cu = 256;
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
+    // further streams of the pipelined Parareal (created on first use)
+    hipStream_t aux_stream[3] = {nullptr, nullptr, nullptr};
     std::string err;
     // scratch of the one-shot evaluation
     mrs::DevBuf eval_rec, eval_part, eval_desc, eval_items, eval_rod;
@@ -163,5 +165,14 @@ hipError_t run_stage(mrs_context *ctx, Plan &P, int stage_state, int elastic, in
 inline int rk_stages(int integ) { return integ == MRS_RK2 ? 2 : 4; }
 inline int rk_scheme(int integ) { return integ == MRS_RK2 ? RK_SCHEME_RK2 : RK_SCHEME_RK4; }
 hipError_t upload(mrs_context *ctx, void *dst, const void *src, size_t bytes, hipStream_t s);
+// Queue nsteps steps of one ensemble, or of a batch (as mrs_batch_step), on
+// stream s without waiting for them.  The caller holds ctx->mu.
+mrs_status ensemble_enqueue(mrs_ensemble *E, int integ, double dt, int nsteps, int prec, int elastic,
+                            hipStream_t s);
+mrs_status batch_enqueue(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *ens, int integ, double dt,
+                         int nsteps, int prec, int elastic, int use_graph, hipStream_t s);
+// The context's further stream i in [0, 3) (non-blocking, default
+// priority); null if it cannot be created.
+hipStream_t aux_stream(mrs_context *ctx, int i);
 
 }  // namespace mrs

@@ -77,7 +77,7 @@ def test_graph_replays_equal_eager(mrs, ctx, prec):
 
 
 def test_batched_slices_parity_one_step(mrs, ctx):
-    """Config-3 slices: one batched RK4 step of every slice against the oracle."""
+    """The 16 slices of 32 filaments x 100 points: one batched RK4 step of every slice against the oracle."""
     base, slices = synth.slices(n_slices=16)
     hs = [_create(mrs, ctx, e) for e in slices]
     try:

@@ -68,15 +68,16 @@ def test_parareal_matches_oracle(mrs, ctx, integ):
 
 
 def test_parareal_converges_and_stops_at_tolerance(mrs, ctx):
-    """Config-3 geometry with the external torques scaled by 1e-2 (smooth
-    enough for a coarse Euler propagator): the increments fall by orders of
+    """Slice base geometry (32 filaments x 100 points) with the external
+    torques scaled by 1e-2 (smooth enough for a coarse Euler propagator):
+    the increments fall by orders of
     magnitude per iteration and the iteration stops at the tolerance."""
     base, slices = synth.slices(n_slices=1)
     e = slices[0]
     h = mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, 1e-2 * e.n, e.eps, e.mu, rod_of(mrs, e.rod()))
     try:
         it, hist = mrs.mrs_parareal(ctx, h, 8, mrs.MRS_RK4, 1e-5, 20, 2, 8, 1e-11, mrs.MRS_FP64, True)
-        say(f"slices slice (torques x 1e-2), 8 slices: {it} iterations, increments {hist}")
+        say(f"32 x 100 slice base (torques x 1e-2), 8 slices: {it} iterations, increments {hist}")
         assert it < 8 and hist[-1] <= 1e-11
         assert np.all(np.diff(np.log10(hist)) < -1.0)
     finally:
@@ -98,5 +99,72 @@ def test_parareal_invalid_arguments(mrs, ctx):
             mrs.mrs_parareal(ctx, h, 2, mrs.MRS_RK4, 1e-5, 4, 1, 3)  # max_iter > n_slices
         with pytest.raises(mrs.MrsError):
             mrs.mrs_parareal(ctx, h, 2, mrs.MRS_RK4, 1e-5, 0, 1, 2)
+    finally:
+        mrs.mrs_ensemble_destroy(h)
+
+
+def _run_both(mrs, ctx, make, args, group):
+    """The regular and the pipelined schedule on fresh copies of one ensemble."""
+    a, b = make(), make()
+    try:
+        it_r, h_r = mrs.mrs_parareal(ctx, a, *args)
+        it_p, h_p = mrs.mrs_parareal_pipelined(ctx, b, *args, group=group)
+        Xa, Da, _, _ = mrs.mrs_ensemble_get(ctx, a)
+        Xb, Db, _, _ = mrs.mrs_ensemble_get(ctx, b)
+        ta, tb = mrs.mrs_ensemble_get_time(ctx, a), mrs.mrs_ensemble_get_time(ctx, b)
+    finally:
+        mrs.mrs_ensemble_destroy(a)
+        mrs.mrs_ensemble_destroy(b)
+    return (it_r, h_r, Xa, Da, ta), (it_p, h_p, Xb, Db, tb)
+
+
+def _assert_same(r, p):
+    assert r[0] == p[0]
+    np.testing.assert_array_equal(r[1], p[1])
+    np.testing.assert_array_equal(r[2], p[2])
+    np.testing.assert_array_equal(r[3], p[3])
+    assert r[4] == p[4]
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32C"])
+@pytest.mark.parametrize("group", [1, 2, 0, 5])
+def test_pipelined_equals_regular_all_iterations(mrs, ctx, prec, group):
+    """Sec. II.D: the pipelined schedule computes the regular iterates bit for
+    bit, for every group size (1, 2, the default, all slices)."""
+    e = synth.filaments(4, 50, 2.0, 21)
+    ns = 5
+    args = (ns, mrs.MRS_RK4, 1e-5, 8, 1, ns, 0.0, getattr(mrs, "MRS_" + prec), True)
+    r, p = _run_both(mrs, ctx, lambda: _ens(mrs, ctx, e), args, group)
+    say(f"{prec} group {group}: {p[0]} iterations, increments {p[1]}")
+    assert p[0] == ns
+    _assert_same(r, p)
+
+
+@pytest.mark.parametrize("group", [1, 3])
+def test_pipelined_stops_where_regular_stops(mrs, ctx, group):
+    """With a tolerance the pipelined schedule stops at the same iteration
+    with the same increments and state (the fine groups of the next
+    iteration start only once the increment exceeds the tolerance)."""
+    base, slices = synth.slices(n_slices=1)
+    e = slices[0]
+    make = lambda: mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, 1e-2 * e.n, e.eps, e.mu,
+                                           rod_of(mrs, e.rod()))
+    args = (8, mrs.MRS_RK4, 1e-5, 20, 2, 8, 1e-11, mrs.MRS_FP64, True)
+    r, p = _run_both(mrs, ctx, make, args, group)
+    say(f"group {group}: {p[0]} iterations, increments {p[1]}")
+    assert p[0] < 8 and p[1][-1] <= 1e-11
+    _assert_same(r, p)
+
+
+def test_pipelined_invalid_group(mrs, ctx):
+    e = synth.filaments(2, 16, 1.0, 9)
+    h = _ens(mrs, ctx, e)
+    try:
+        with pytest.raises(mrs.MrsError):
+            mrs.mrs_parareal_pipelined(ctx, h, 3, mrs.MRS_RK4, 1e-5, 4, 1, 3, group=4)
+        with pytest.raises(mrs.MrsError):
+            mrs.mrs_parareal_pipelined(ctx, h, 3, mrs.MRS_RK4, 1e-5, 4, 1, 3, group=-1)
+        with pytest.raises(mrs.MrsError):
+            mrs.mrs_parareal_pipelined(ctx, h, 2, mrs.MRS_RK4, 1e-5, 4, 1, 3)  # max_iter > n_slices
     finally:
         mrs.mrs_ensemble_destroy(h)

@@ -62,7 +62,7 @@ def test_ensemble_eval(mrs, ctx, prec, elastic):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_rod64_euler_teacher_forced(mrs, ctx, prec):
-    """Config 1: 64 points, 100 forward-Euler steps at dt = 1e-4."""
+    """One filament of 64 points, 100 forward-Euler steps at dt = 1e-4."""
     e = synth.rod64()
     rod = e.rod()
     dt = 1e-4
@@ -91,7 +91,7 @@ def test_rod64_euler_teacher_forced(mrs, ctx, prec):
 @pytest.mark.parametrize("integ", ["RK4", "RK2"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_rk_teacher_forced(mrs, ctx, prec, integ):
-    """Config-3 geometry (32 filaments x 100 points), RK4 / RK2 at dt = 1e-5."""
+    """Slice base geometry (32 filaments x 100 points), RK4 / RK2 at dt = 1e-5."""
     base, slices = synth.slices(n_slices=1)
     e = slices[0]
     rod = e.rod()

@@ -183,6 +183,29 @@ def test_swim_parareal_full_iterations_equal_serial_fine(mrs, ctx):
         mrs.mrs_ensemble_destroy(ser)
 
 
+def test_swim_parareal_pipelined_equals_regular(mrs, ctx):
+    """The time-dependent problem: the pipelined schedule starts every
+    slice at its boundary time and reproduces the regular iterates."""
+    e, p = _swim(F=4, seed=9)
+    dt, fsteps, ns = 1e-5, 20, 4
+    a = _create(mrs, ctx, e, p, 0.25)
+    b = _create(mrs, ctx, e, p, 0.25)
+    try:
+        it_r, h_r = mrs.mrs_parareal(ctx, a, ns, mrs.MRS_RK2, dt, fsteps, 2, 3, 0.0, mrs.MRS_FP32C, True)
+        it_p, h_p = mrs.mrs_parareal_pipelined(ctx, b, ns, mrs.MRS_RK2, dt, fsteps, 2, 3, 0.0, mrs.MRS_FP32C,
+                                               True, group=1)
+        assert it_r == it_p == 3
+        np.testing.assert_array_equal(h_r, h_p)
+        Xa, Da, _, _ = mrs.mrs_ensemble_get(ctx, a)
+        Xb, Db, _, _ = mrs.mrs_ensemble_get(ctx, b)
+        np.testing.assert_array_equal(Xa, Xb)
+        np.testing.assert_array_equal(Da, Db)
+        assert mrs.mrs_ensemble_get_time(ctx, a) == mrs.mrs_ensemble_get_time(ctx, b)
+    finally:
+        mrs.mrs_ensemble_destroy(a)
+        mrs.mrs_ensemble_destroy(b)
+
+
 def test_invalid_swimming_arguments(mrs, ctx):
     e, p = _swim(F=2, seed=10)
     ens = mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, p.rod))
