@@ -30,27 +30,32 @@ FLOPS_PER_PAIR = 92       # algorithmic flops of one (target, source) evaluation
 
 # HBM bytes per pair-kernel launch from hardware counters (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, the factors a 256 MiB device copy reads), valid only for
-# the kernel source they were taken on: any other source reports null.
-KERNEL_SRC = os.path.join(ROOT, "paper_2604_12083_amd", "csrc", "mrs_pairs.hip")
+# the kernel source and work-list builder (their sha256) and the number of
+# source chunks (partial sums per target) they were taken on: any other
+# source or decomposition reports null.
+KERNEL_SRC = [os.path.join(ROOT, "paper_2604_12083_amd", "csrc", f) for f in ("mrs_pairs.hip", "mrs_runtime.cpp")]
 MEASURED_TRAFFIC = {
-    "0397d2201a897893c80851214f38ac91811750e8221b642e13d82cdf0b244fb6": {
-        ("ens12800", "fp32c"): (2653.83 * 2.0 + 30000.0) * 1024,
-        ("ens12800", "fp64"): (4134.46 * 2.0 + 30000.0) * 1024,
-        ("ens256000", "fp32c"): (271870.97 * 2.0 + 204000.0) * 1024,
-        ("ens256000", "fp64"): (849082.72 * 2.0 + 396000.0) * 1024,
+    "d950d26dfee13bf82e780befd802abb2f4df7786f64db3329b08db16ea26c005": {
+        ("ens12800", "fp32c", 62): (2700.67 * 2.0 + 37200.0) * 1024,
+        ("ens12800", "fp64", 50): (4134.22 * 2.0 + 30000.0) * 1024,
+        ("ens256000", "fp32c", 22): (183679.44 * 2.0 + 264000.0) * 1024,
+        ("ens256000", "fp64", 33): (471081.02 * 2.0 + 396000.0) * 1024,
     },
 }
 
 
-def measured_traffic(workload_name, tag):
+def measured_traffic(workload_name, tag, chunks):
     import hashlib
 
+    h = hashlib.sha256()
     try:
-        with open(KERNEL_SRC, "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
+        for path in KERNEL_SRC:
+            with open(path, "rb") as fh:
+                h.update(fh.read())
     except OSError:
         return None
-    v = MEASURED_TRAFFIC.get(sha, {}).get((workload_name, tag))
+    sha = h.hexdigest()
+    v = MEASURED_TRAFFIC.get(sha, {}).get((workload_name, tag, chunks))
     return None if v is None else round(v)
 
 
@@ -503,6 +508,7 @@ def main():
         for prec, tag in ((mrs.MRS_FP32C, "fp32c"), (mrs.MRS_FP64, "fp64")):
             log(f"measure {tag} N={e.N} steps={args.steps}")
             res[tag] = measure(mrs, ctx, e, prec, args.steps, args.warmup, args.dt, integ, swim)
+            res[tag]["chunks"] = mrs.mrs_tune_get(ctx, e.N, prec)["chunks"]
         cpu, errs = (None, None)
         if not args.no_cpu:
             log("cpu baseline (oracle)")
@@ -517,7 +523,9 @@ def main():
             "ms_per_step": 1e3 * r["wall_s"] / args.steps,
             "ms_per_step_graph": 1e3 * r["wall_graph_s"] / args.steps,
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-            "roofline": roofline(e.N * e.N, r["kernel_avg_s"], peak, measured_traffic(args.workload, tag)),
+            "roofline": roofline(e.N * e.N, r["kernel_avg_s"], peak,
+                                 measured_traffic(args.workload, tag, r["chunks"])),
+            "source_chunks": r["chunks"],
             "kernels_avg_us": {k: round(v["avg_us"], 2) for k, v in r["kernels"].items()},
             "frame_update_GBps": frame_update_gbps(e.N, r["kernels"]),
         }

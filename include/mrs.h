@@ -272,8 +272,11 @@ mrs_status mrs_server_stop(mrs_server *srv);
 /* ---- pair-kernel tuning ------------------------------------------------ */
 
 /* How the pair kernel covers an ensemble of a given size: mode 0 = LDS-tiled
- * (targets_per_lane 1 or 2, `chunks` source chunks, 0 = automatic), mode 1 =
- * wave-split for small ensembles. */
+ * (targets_per_lane 1 or 2, `chunks` source chunks of equal size, 0 =
+ * automatic), mode 1 = wave-split for small ensembles.  An automatic FP32C
+ * configuration of a large grid also splits the last ~8% of every target
+ * tile's sources into shorter chunks dispatched last; mrs_tune_get reports
+ * `chunks` as the total number of chunks (partial sums per target). */
 typedef struct {
     int32_t mode;
     int32_t targets_per_lane;

@@ -46,8 +46,11 @@ struct DevBuf {
 struct PairCfg {
     int mode = PAIR_TILE;  // PAIR_TILE or PAIR_SPLIT
     int tpl = 1;           // targets per lane (tile mode)
-    int K = 1;             // source chunks
+    int K = 1;             // source chunks (partial sums per target)
     int chunk = 0;         // sources per chunk
+    // tail split: sources [tail_start, N) in chunks of tail_chunk sources,
+    // partial slots k_big.. (tail_start = 0: none, every chunk is `chunk`)
+    int tail_start = 0, tail_chunk = 0, k_big = 0;
 };
 
 // Work lists of one launch sequence over a set of ensembles.
@@ -56,6 +59,7 @@ struct Plan {
     int n_ens = 0;
     std::vector<EnsDesc> h_desc;
     std::vector<PairItem> split, tile1, tile2;
+    std::vector<PairItem> tail1, tail2;  // tail-split items, dispatched after tile1 / tile2
     std::vector<RodItem> rods;
     std::vector<PointItem> pts;
     std::vector<PointItem> lj;   // 64-point target blocks of the ensembles with LJ repulsion
@@ -156,6 +160,9 @@ PairCfg choose_cfg(mrs_context *ctx, int64_t N, int prec);
 // Reorders tiled pair blocks so that those with near pairs along a filament
 // (source range overlapping the target range) are dispatched first.
 void near_blocks_first(std::vector<PairItem> &v);
+// Dispatch order of a plan's tiled blocks: near blocks first, the short
+// tail-split blocks last (moved from tail1 / tail2 to the end of tile1 / tile2).
+void order_items(Plan &P);
 // Power-of-two size class of the tuning table.
 int size_bucket(int64_t N);
 size_t ensemble_bytes(int64_t N, int n_fil, bool has_ext, int K64, int K32);

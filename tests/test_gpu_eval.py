@@ -151,6 +151,22 @@ def test_autotune_and_every_config_parity(mrs, prec):
         mrs.mrs_context_destroy(c)
 
 
+def test_fp32c_tail_split_config(mrs):
+    """Automatic FP32C configurations of grids of at least four blocks per
+    compute unit split the last ~8% of every target tile's sources into
+    quarter chunks (here 64 sources) dispatched last; FP64, small grids and
+    explicit chunk counts keep equal chunks."""
+    c = mrs.mrs_context_create(0)
+    try:
+        assert mrs.mrs_tune_get(c, 12800, 1)["chunks"] == 46 + 16
+        assert mrs.mrs_tune_get(c, 12800, 0)["chunks"] == 50
+        assert mrs.mrs_tune_get(c, 3200, 1)["chunks"] == 25
+        mrs.mrs_tune_set(c, 12800, 1, 0, 1, 50)
+        assert mrs.mrs_tune_get(c, 12800, 1)["chunks"] == 50
+    finally:
+        mrs.mrs_context_destroy(c)
+
+
 @pytest.mark.parametrize("tpl", [1, 2])
 def test_fp32c_near_pairs_across_filaments(mrs, tpl):
     """Filaments crossing through one small region: near pairs (r < 4 eps)
