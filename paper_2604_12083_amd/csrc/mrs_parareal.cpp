@@ -261,10 +261,10 @@ extern "C" mrs_status mrs_parareal_pipelined(mrs_ensemble *E, int32_t ns, mrs_in
     if (!E) return MRS_EINVAL;
     mrs_context *ctx = E->ctx;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ns >= 1 && (group < 0 || group > ns)) return fail(ctx, MRS_EINVAL, "group must be in [0, n_slices]");
     Solve S;
     mrs_status st = S.init(E, ns, fi, fdt, fsteps, csteps, max_iter, tol, prec, include_elastic);
     if (st != MRS_OK) return st;
-    if (group < 0 || group > ns) return fail(ctx, MRS_EINVAL, "group must be in [0, n_slices]");
     const int g = group > 0 ? group : std::max(1, (ns + 3) / 4);
     // sweeps (coarse propagation, correction) on the context's stream; the
     // fine groups on up to three more, group j on stream j % n_sf, so that
