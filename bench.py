@@ -333,10 +333,10 @@ def bench_parareal(mrs, ctx, prec, tol, coarse_steps):
             "eta_vs_serial_fine": eta, "error_relative_to_displacement": eta_disp}
 
 
-def bench_schedules(mrs, ctx, prec, iters=4, fine_steps=(5, 20, 50, 200), coarse_steps=10):
+def bench_schedules(mrs, ctx, prec, integ="RK4", iters=4, fine_steps=(5, 20, 50, 200), coarse_steps=10):
     """Regular against pipelined Parareal (Sec. II.D) on one GPU for several
     fine/coarse cost ratios r: 16 slices of the 3,200-point slice ensemble,
-    fine RK4 x fine_steps, coarse Euler x coarse_steps, a fixed number of
+    fine `integ` x fine_steps, coarse Euler x coarse_steps, a fixed number of
     iterations (tol = 0), so both schedules do the same work."""
     import synth
 
@@ -346,14 +346,15 @@ def bench_schedules(mrs, ctx, prec, iters=4, fine_steps=(5, 20, 50, 200), coarse
     mk = lambda: mrs.mrs_ensemble_create(ctx, base.offsets, base.X, base.D, base.f, tq, base.eps, base.mu, rod)
     out = []
     for fs in fine_steps:
-        row = {"fine_steps": fs, "coarse_steps": coarse_steps, "r_evals": 4 * fs / coarse_steps}
+        stages = {"RK2": 2, "RK4": 4}[integ]
+        row = {"fine": integ, "fine_steps": fs, "coarse_steps": coarse_steps, "r_evals": stages * fs / coarse_steps}
         for name, fn, kw in (("regular", mrs.mrs_parareal, {}), ("pipelined", mrs.mrs_parareal_pipelined, {}),
                              ("pipelined_g1", mrs.mrs_parareal_pipelined, {"group": 1})):
-            log(f"parareal schedules: {name} fine_steps={fs}")
+            log(f"parareal schedules: {name} {integ} fine_steps={fs}")
             h = mk()
             try:
                 t0 = time.perf_counter()
-                fn(ctx, h, 16, mrs.MRS_RK4, 1e-5, fs, coarse_steps, iters, 0.0, prec, True, **kw)
+                fn(ctx, h, 16, getattr(mrs, "MRS_" + integ), 1e-5, fs, coarse_steps, iters, 0.0, prec, True, **kw)
                 row[name + "_s"] = time.perf_counter() - t0
             finally:
                 mrs.mrs_ensemble_destroy(h)
@@ -465,6 +466,7 @@ def main():
                 r = {tag: bench_parareal(mrs, ctx, p, tol, 10) for tag, p, tol in
                      (("fp64", mrs.MRS_FP64, 1e-12), ("fp32c", mrs.MRS_FP32C, 1e-6))}
                 r["schedules_fp32c"] = bench_schedules(mrs, ctx, mrs.MRS_FP32C)
+                r["schedules_fp32c_rk2"] = bench_schedules(mrs, ctx, mrs.MRS_FP32C, integ="RK2")
                 line = {"metric": "Parareal wall time on one GPU vs serial fine (32 filaments x 100 points, 16 slices)",
                         "value": r["fp32c"]["speedup_vs_serial"], "unit": "x", "n_gpus": 1, "steps": 3200,
                         "warmup": 1, "ms_per_step": 1e3 * r["fp32c"]["parareal_s"] / 3200,
