@@ -35,11 +35,11 @@ FLOPS_PER_PAIR = 92       # algorithmic flops of one (target, source) evaluation
 # source or decomposition reports null.
 KERNEL_SRC = [os.path.join(ROOT, "paper_2604_12083_amd", "csrc", f) for f in ("mrs_pairs.hip", "mrs_runtime.cpp")]
 MEASURED_TRAFFIC = {
-    "d950d26dfee13bf82e780befd802abb2f4df7786f64db3329b08db16ea26c005": {
-        ("ens12800", "fp32c", 62): (2700.67 * 2.0 + 37200.0) * 1024,
-        ("ens12800", "fp64", 50): (4134.22 * 2.0 + 30000.0) * 1024,
-        ("ens256000", "fp32c", 22): (183679.44 * 2.0 + 264000.0) * 1024,
-        ("ens256000", "fp64", 33): (471081.02 * 2.0 + 396000.0) * 1024,
+    "f67cdb666a1ca33cfb83e645e4c083f76b625226fc97f1728b0f905ba8e35798": {
+        ("ens12800", "fp32c", 62): (2707.30 * 2.0 + 37200.0) * 1024,
+        ("ens12800", "fp64", 50): (4134.20 * 2.0 + 30000.0) * 1024,
+        ("ens256000", "fp32c", 22): (183519.0 * 2.0 + 264000.0) * 1024,
+        ("ens256000", "fp64", 33): (471052.0 * 2.0 + 396000.0) * 1024,
     },
 }
 
