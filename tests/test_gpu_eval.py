@@ -115,6 +115,19 @@ def test_invalid_arguments(mrs, ctx):
 
 
 @pytest.mark.parametrize("prec", [1, 0])
+def test_overflowing_result_is_reported(mrs, ctx, prec):
+    """Finite inputs whose velocities overflow (forces near the largest
+    double) give MRS_ENUMERIC, not a silent inf; the context stays usable."""
+    X, f, n = _cloud(10, 6)
+    with pytest.raises(mrs.MrsError) as ei:
+        mrs.mrs_eval_host(ctx, X, 1e307 * np.sign(f), n, 1e-3, 1.0, prec)
+    assert ei.value.status == mrs.MRS_ENUMERIC
+    U, W = mrs.mrs_eval_host(ctx, X, f, n, 0.03, 0.7, prec)
+    Uo, Wo = oracle.mrs_eval(X, f, n, 0.03, 0.7)
+    assert oracle.rel_err(U, Uo) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [1, 0])
 def test_ens256000_full_size_sampled(mrs, ctx, prec):
     """256,000 points, all targets evaluated on the GPU, 2,048 seeded targets
     checked one by one against the oracle."""
