@@ -33,13 +33,13 @@ FLOPS_PER_PAIR = 92       # algorithmic flops of one (target, source) evaluation
 # the kernel source and work-list builder (their sha256) and the number of
 # source chunks (partial sums per target) they were taken on: any other
 # source or decomposition reports null.
-KERNEL_SRC = [os.path.join(ROOT, "paper_2604_12083_amd", "csrc", f) for f in ("mrs_pairs.hip", "mrs_runtime.cpp")]
+KERNEL_SRC = [os.path.join(ROOT, "paper_2604_12083_amd", "csrc", f) for f in ("mrs_pairs.hip", "mrs_plan.cpp")]
 MEASURED_TRAFFIC = {
-    "f67cdb666a1ca33cfb83e645e4c083f76b625226fc97f1728b0f905ba8e35798": {
+    "bf3678f7ca29082dad20b5baba2dedd2ae5159bc6c1c88a16f6c316aa664a56c": {
         ("ens12800", "fp32c", 62): (2707.30 * 2.0 + 37200.0) * 1024,
-        ("ens12800", "fp64", 50): (4134.20 * 2.0 + 30000.0) * 1024,
-        ("ens256000", "fp32c", 22): (183519.0 * 2.0 + 264000.0) * 1024,
-        ("ens256000", "fp64", 33): (471052.0 * 2.0 + 396000.0) * 1024,
+        ("ens12800", "fp64", 50): (4134.22 * 2.0 + 30000.0) * 1024,
+        ("ens256000", "fp32c", 22): (183519.27 * 2.0 + 264000.0) * 1024,
+        ("ens256000", "fp64", 33): (471073.36 * 2.0 + 396000.0) * 1024,
     },
 }
 

@@ -290,6 +290,20 @@ typedef struct {
  * already created keep the configuration they were planned with. */
 mrs_status mrs_autotune(mrs_context *ctx, int64_t n, mrs_precision prec, int32_t reps,
                         mrs_pair_config *best, double *best_ms);
+/* Host only (no device is touched): the pair-kernel work list that the
+ * automatic configuration builds for one ensemble of n points on a device
+ * with n_cu compute units, in dispatch order.  *mode, *targets_per_lane,
+ * *chunks and *tail_start (each may be NULL) receive the configuration
+ * (chunks = partial sums per target; tail_start = first source of the short
+ * tail chunks, n if there are none); *n_items receives the number of
+ * blocks.  items (may be
+ * NULL to query the count) receives 5 int32 per block: first target,
+ * targets, first source, sources, partial-sum slot.  Errors: MRS_EINVAL for
+ * n < 1 or too large, n_cu < 1, an unknown precision, a null n_items, or
+ * max_items below the block count (n_items is still set). */
+mrs_status mrs_plan_items(int64_t n, mrs_precision prec, int32_t n_cu, int32_t *mode, int32_t *targets_per_lane,
+                          int32_t *chunks, int32_t *tail_start, int32_t *items, int64_t max_items,
+                          int64_t *n_items);
 /* Read / set the configuration used for ensembles of n points. */
 mrs_status mrs_tune_get(mrs_context *ctx, int64_t n, mrs_precision prec, mrs_pair_config *out);
 mrs_status mrs_tune_set(mrs_context *ctx, int64_t n, mrs_precision prec, const mrs_pair_config *cfg);

@@ -122,6 +122,8 @@ _SIGS = {
     "mrs_tune_set": (_int, [_vp, _i64, _int, ctypes.POINTER(mrs_pair_config)]),
     "mrs_parareal": (_int, [_vp, ctypes.c_int32, _int, _dbl, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dbl,
                             _int, _int, _vp, ctypes.POINTER(ctypes.c_int32)]),
+    "mrs_plan_items": (_int, [ctypes.c_int64, _int, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, _vp,
+                              ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "mrs_parareal_pipelined": (_int, [_vp, ctypes.c_int32, _int, _dbl, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_int32, _dbl, _int, _int, ctypes.c_int32, _vp,
                                       ctypes.POINTER(ctypes.c_int32)]),
@@ -409,6 +411,20 @@ def mrs_tune_get(ctx, n, prec=MRS_FP32C):
     c = mrs_pair_config()
     _check(_lib.mrs_tune_get(ctx, int(n), int(prec), ctypes.byref(c)), ctx)
     return {"mode": c.mode, "targets_per_lane": c.targets_per_lane, "chunks": c.chunks}
+
+
+def mrs_plan_items(n, prec, n_cu=256):
+    """Host-only work list of the automatic pair-kernel configuration:
+    (config dict, int32 array of blocks x (tgt0, ntgt, src0, nsrc, slot)) in
+    dispatch order."""
+    m, t, k, ts = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    cnt = ctypes.c_int64()
+    _check(_lib.mrs_plan_items(int(n), int(prec), int(n_cu), ctypes.byref(m), ctypes.byref(t), ctypes.byref(k),
+                               ctypes.byref(ts), None, 0, ctypes.byref(cnt)))
+    items = np.zeros((cnt.value, 5), dtype=np.int32)
+    _check(_lib.mrs_plan_items(int(n), int(prec), int(n_cu), None, None, None, None, items.ctypes.data, cnt.value,
+                               ctypes.byref(cnt)))
+    return {"mode": m.value, "targets_per_lane": t.value, "chunks": k.value, "tail_start": ts.value}, items
 
 
 def mrs_tune_set(ctx, n, prec, mode, targets_per_lane=1, chunks=0) -> None:

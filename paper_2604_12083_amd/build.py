@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrs.so")
-SOURCES = ["mrs_pairs.hip", "mrs_kernels.hip", "mrs_runtime.cpp", "mrs_server.cpp", "mrs_autotune.cpp", "mrs_parareal.cpp"]
+SOURCES = ["mrs_pairs.hip", "mrs_kernels.hip", "mrs_runtime.cpp", "mrs_plan.cpp", "mrs_server.cpp", "mrs_autotune.cpp", "mrs_parareal.cpp"]
 
 # Packed FP32 instructions are kept out of the generated code on purpose.
 HIP_FLAGS = [

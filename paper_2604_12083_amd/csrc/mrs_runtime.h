@@ -157,6 +157,9 @@ inline hipError_t timed(mrs_context *ctx, const char *name, hipStream_t s, F &&l
 
 
 PairCfg choose_cfg(mrs_context *ctx, int64_t N, int prec);
+// The configuration for N points: `tuned` (a tuning-table entry) or, if null,
+// the automatic one for a device with n_cu compute units.  Host only.
+PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu);
 // Reorders tiled pair blocks so that those with near pairs along a filament
 // (source range overlapping the target range) are dispatched first.
 void near_blocks_first(std::vector<PairItem> &v);
