@@ -25,8 +25,9 @@ def mrs():
 
 
 # (filaments, points per filament, kind, integrator) of a mixed request set
+# (the last one, 7,680 points, is large enough for the FP32C tail split)
 SPECS = [(4, 64, 0, "RK4"), (12, 100, 1, "RK4"), (1, 200, 1, "RK2"), (30, 128, 0, "RK4"), (7, 77, 1, "EULER"),
-         (64, 64, 1, "RK4"), (2, 256, 0, "RK4"), (9, 90, 1, "RK2")]
+         (64, 64, 1, "RK4"), (2, 256, 0, "RK4"), (9, 90, 1, "RK2"), (60, 128, 0, "RK4")]
 
 
 def _requests():
