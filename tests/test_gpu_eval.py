@@ -80,6 +80,21 @@ def test_eps_extremes(mrs, ctx, prec, eps):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_coincident_points(mrs, ctx, prec):
+    """Degenerate geometry: pairs at r = 0 between distinct points (every
+    kernel function is finite there, Sec. II.C), a block where every pair
+    coincides, and duplicates scattered through a cloud."""
+    X, f, n = _cloud(300, 12, box=0.6)
+    Xd = np.concatenate([X, X[::3]])
+    rng = np.random.default_rng(13)
+    fd = np.concatenate([f, rng.normal(size=(100, 3))])
+    nd = np.concatenate([n, rng.normal(size=(100, 3))])
+    _check(mrs, ctx, Xd, fd, nd, 0.02, 1.0, prec, "duplicates")
+    Xs = np.tile(np.array([[0.3, -0.2, 0.9]]), (64, 1))
+    _check(mrs, ctx, Xs, f[:64], n[:64], 0.05, 1.0, prec, "all-coincident")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_linearity_and_zero_loads(mrs, ctx, prec):
     X, f, n = _cloud(700, 3)
     U, W = eval_dev(mrs, ctx, X, np.zeros_like(f), np.zeros_like(n), 0.05, 1.0, prec)
