@@ -30,32 +30,30 @@ FLOPS_PER_PAIR = 92       # algorithmic flops of one (target, source) evaluation
 
 # HBM bytes per pair-kernel launch from hardware counters (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, the factors a 256 MiB device copy reads), valid only for
-# the kernel source and work-list builder (their sha256) and the number of
-# source chunks (partial sums per target) they were taken on: any other
-# source or decomposition reports null.
-KERNEL_SRC = [os.path.join(ROOT, "paper_2604_12083_amd", "csrc", f) for f in ("mrs_pairs.hip", "mrs_plan.cpp")]
+# the pair-kernel source (its sha256) and the exact work list (sha256 of the
+# blocks `mrs_plan_items` gives for the workload) they were taken on: any
+# other kernel or decomposition reports null.
+KERNEL_SRC = os.path.join(ROOT, "paper_2604_12083_amd", "csrc", "mrs_pairs.hip")
+KERNEL_SHA = "6dcc14e18a5200f81ed940b25525aa5a073f2f69f155c244ff15fca792d72597"
 MEASURED_TRAFFIC = {
-    "bf3678f7ca29082dad20b5baba2dedd2ae5159bc6c1c88a16f6c316aa664a56c": {
-        ("ens12800", "fp32c", 62): (2707.30 * 2.0 + 37200.0) * 1024,
-        ("ens12800", "fp64", 50): (4134.22 * 2.0 + 30000.0) * 1024,
-        ("ens256000", "fp32c", 22): (183519.27 * 2.0 + 264000.0) * 1024,
-        ("ens256000", "fp64", 33): (471073.36 * 2.0 + 396000.0) * 1024,
-    },
+    ("ens12800", "fp32c", "678ec7c5e5d82ecf"): (2707.30 * 2.0 + 37200.0) * 1024,
+    ("ens12800", "fp64", "adb3c89bda2d142d"): (4134.22 * 2.0 + 30000.0) * 1024,
+    ("ens256000", "fp32c", "4a2b01f9e8a27aa9"): (183519.27 * 2.0 + 264000.0) * 1024,
+    ("ens256000", "fp64", "571ba5e594123b76"): (471073.36 * 2.0 + 396000.0) * 1024,
 }
 
 
-def measured_traffic(workload_name, tag, chunks):
+def measured_traffic(mrs, workload_name, tag, n, prec, n_cu):
     import hashlib
 
-    h = hashlib.sha256()
     try:
-        for path in KERNEL_SRC:
-            with open(path, "rb") as fh:
-                h.update(fh.read())
+        with open(KERNEL_SRC, "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != KERNEL_SHA:
+                return None
     except OSError:
         return None
-    sha = h.hexdigest()
-    v = MEASURED_TRAFFIC.get(sha, {}).get((workload_name, tag, chunks))
+    _, items = mrs.mrs_plan_items(n, prec, n_cu)
+    v = MEASURED_TRAFFIC.get((workload_name, tag, hashlib.sha256(items.tobytes()).hexdigest()[:16]))
     return None if v is None else round(v)
 
 
@@ -77,6 +75,13 @@ def workload(name):
         e = synth.swimmers(1000, box=40.0, seed=12)
         p = synth.swim_params(e)
         return e, ("1,000 straight swimmers x 51 points (51,000 points), length 1, eps = 4 ds, in [0,40]^2 at "
+                   f"z = 1 +- 0.1; waveform A={p.wave[0]}, k=2 pi, f={p.wave[2]:.4g}; Lennard-Jones sigma = 3 eps, "
+                   f"energy {p.lj[1]}"), p
+    if name == "swim25":
+        # the largest configuration of the paper's timing table: 25 swimmers of 51 points
+        e = synth.swimmers(25, box=4.0, seed=25)
+        p = synth.swim_params(e)
+        return e, ("25 straight swimmers x 51 points (1,275 points), length 1, eps = 4 ds, in [0,4]^2 at "
                    f"z = 1 +- 0.1; waveform A={p.wave[0]}, k=2 pi, f={p.wave[2]:.4g}; Lennard-Jones sigma = 3 eps, "
                    f"energy {p.lj[1]}"), p
     raise SystemExit(f"unknown workload {name}")
@@ -418,7 +423,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ens12800",
-                    choices=["rod64", "ens12800", "ens256000", "swim", "slices", "serving", "parareal", "copy"])
+                    choices=["rod64", "ens12800", "ens256000", "swim", "swim25", "slices", "serving", "parareal",
+                             "copy"])
     ap.add_argument("--requests", type=int, default=32, help="serving: prefix of the request sequence")
     ap.add_argument("--rates", default="10,100,1000", help="serving: Poisson arrival rates (req/s)")
     ap.add_argument("--slots", type=int, default=64)
@@ -503,6 +509,9 @@ def main():
     # the swimming workload steps with the paper's fine propagator (RK2, 2 stages)
     integ, stages, step_name = ((mrs.MRS_RK2, 2, "midpoint RK2") if swim is not None else
                                 (mrs.MRS_EULER, 1, "forward-Euler"))
+    import torch
+
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     ctx = mrs.mrs_context_create(0)
     try:
         pairs_step = stages * e.N * e.N
@@ -511,6 +520,7 @@ def main():
             log(f"measure {tag} N={e.N} steps={args.steps}")
             res[tag] = measure(mrs, ctx, e, prec, args.steps, args.warmup, args.dt, integ, swim)
             res[tag]["chunks"] = mrs.mrs_tune_get(ctx, e.N, prec)["chunks"]
+            res[tag]["traffic"] = measured_traffic(mrs, args.workload, tag, e.N, prec, n_cu)
         cpu, errs = (None, None)
         if not args.no_cpu:
             log("cpu baseline (oracle)")
@@ -525,8 +535,7 @@ def main():
             "ms_per_step": 1e3 * r["wall_s"] / args.steps,
             "ms_per_step_graph": 1e3 * r["wall_graph_s"] / args.steps,
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-            "roofline": roofline(e.N * e.N, r["kernel_avg_s"], peak,
-                                 measured_traffic(args.workload, tag, r["chunks"])),
+            "roofline": roofline(e.N * e.N, r["kernel_avg_s"], peak, r["traffic"]),
             "source_chunks": r["chunks"],
             "kernels_avg_us": {k: round(v["avg_us"], 2) for k, v in r["kernels"].items()},
             "frame_update_GBps": frame_update_gbps(e.N, r["kernels"]),
@@ -534,6 +543,8 @@ def main():
 
     s32 = summary(res["fp32c"], PEAK_FP32_TFLOPS, "fp32c")
     s64 = summary(res["fp64"], PEAK_FP64_TFLOPS, "fp64")
+    if cpu:
+        cpu["gpu_over_oracle"] = {"fp32c": s32["value"] / cpu["value"], "fp64": s64["value"] / cpu["value"]}
     line = {
         "metric": METRIC,
         "value": s32["value"],

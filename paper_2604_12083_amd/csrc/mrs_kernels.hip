@@ -317,6 +317,16 @@ __device__ __forceinline__ double wave_max_d(double v) {
     return v;
 }
 
+static_assert(kLjBlockPoints <= 64, "an LJ source block fits one wave, one point per lane");
+
+// Value of v in lane l (l wave-uniform), read into scalar registers.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Box of every LJ source block (at most kLjBlockPoints consecutive points of
 // one filament) of the (stage) positions: one wave per block.
 __global__ __launch_bounds__(kBlock) void k_lj_boxes(int stage_state, const EnsDesc *__restrict__ desc,
@@ -345,18 +355,23 @@ __global__ __launch_bounds__(kBlock) void k_lj_boxes(int stage_state, const EnsD
 
 // Lennard-Jones force on every point (Sec. IV): the sum over points of other
 // filaments closer than r_c of 24 e (2 (sig/r)^12 - (sig/r)^6) (x_i - x_j)/r^2.
-// A block owns 64 points (one per lane); its 4 waves split the LJ source
-// blocks (wave w takes every 4th staged box), visit a block only when one of
-// their lanes lies within r_c of its box, and their partial forces are added
-// in wave order.  The block also writes the LJ mask of its 64 points: the
+// A block owns 64 points (one per lane); its kLjWaves waves split the LJ
+// source blocks (wave w takes every kLjWaves-th staged box), visit a block
+// only when one of their lanes lies within r_c of its box, and their partial
+// forces are added in wave order.  Sixteen waves keep the chain of boxes a
+// wave visits short when there are few target blocks (25 swimmers of 51
+// points: 20 blocks).  The block also writes the LJ mask of its 64 points: the
 // FP32C pair kernels evaluate those sources in FP64, since the equal and
 // opposite contact forces largely cancel at a distance and FP32 terms would
 // leave their rounding behind.
-__global__ __launch_bounds__(kBlock) void k_lj_forces(int stage_state, const EnsDesc *__restrict__ desc,
-                                                      const PointItem *__restrict__ items) {
-    constexpr int kWaves = kBlock / 64;
-    __shared__ double sBox[kBlock][6];
-    __shared__ int sBlk[kBlock][3];
+constexpr int kLjWaves = 16;
+constexpr int kLjStage = 256;  // LJ source-block boxes staged in LDS per pass
+
+__global__ __launch_bounds__(64 * kLjWaves) void k_lj_forces(int stage_state, const EnsDesc *__restrict__ desc,
+                                                             const PointItem *__restrict__ items) {
+    constexpr int kWaves = kLjWaves;
+    __shared__ double sBox[kLjStage][6];
+    __shared__ int sBlk[kLjStage][3];
     __shared__ double sPart[kWaves][3][64];
     const PointItem it = items[blockIdx.x];
     const EnsDesc &E = desc[it.ens];
@@ -371,16 +386,16 @@ __global__ __launch_bounds__(kBlock) void k_lj_forces(int stage_state, const Ens
     const double rc = E.lj_rc, rc2 = rc * rc, sig2 = E.lj_sig * E.lj_sig, c24 = 24.0 * E.lj_e;
     double acc[3] = {0.0, 0.0, 0.0};
     const int nblk = E.n_ljblk;
-    for (int b0 = 0; b0 < nblk; b0 += kBlock) {
+    for (int b0 = 0; b0 < nblk; b0 += kLjStage) {
         __syncthreads();
-        if (b0 + tid < nblk) {
+        if (tid < kLjStage && b0 + tid < nblk) {
 #pragma unroll
             for (int c = 0; c < 6; c++) sBox[tid][c] = E.lj_box[6 * (size_t)(b0 + tid) + c];
 #pragma unroll
             for (int c = 0; c < 3; c++) sBlk[tid][c] = E.lj_blk[3 * (b0 + tid) + c];
         }
         __syncthreads();
-        const int cnt = min(kBlock, nblk - b0);
+        const int cnt = min(kLjStage, nblk - b0);
         for (int bb = w; bb < cnt; bb += kWaves) {
             double gap2 = 0.0;
             const double xs[3] = {x0, x1, x2};
@@ -391,17 +406,34 @@ __global__ __launch_bounds__(kBlock) void k_lj_forces(int stage_state, const Ens
             }
             const bool near = real && gap2 < rc2 && sBlk[bb][2] != fi;
             if (!__any(near ? 1 : 0)) continue;  // wave-uniform
-            if (!near) continue;
-            const int j1 = sBlk[bb][1];
-            for (int j = sBlk[bb][0]; j < j1; j++) {
-                const double r0 = x0 - X[j], r1 = x1 - X[(size_t)N + j], r2 = x2 - X[2 * (size_t)N + j];
-                const double rr2 = r0 * r0 + r1 * r1 + r2 * r2;
-                if (!(sqrt(rr2) < rc)) continue;
-                const double s2 = sig2 / rr2, s6 = s2 * s2 * s2;
-                const double cf = c24 * (2.0 * s6 * s6 - s6) / rr2;
-                acc[0] += cf * r0;
-                acc[1] += cf * r1;
-                acc[2] += cf * r2;
+            // the wave loads the block's points once (lane = point, coalesced)
+            // and broadcasts them from lane registers: no dependent global
+            // load per source point
+            const int j0 = sBlk[bb][0], jn = sBlk[bb][1] - j0;  // jn <= kLjBlockPoints = 64
+            double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+            if (lane < jn) {
+                y0 = X[j0 + lane];
+                y1 = X[(size_t)N + j0 + lane];
+                y2 = X[2 * (size_t)N + j0 + lane];
+            }
+            // r < r_c is tested as r^2 < r_c^2 and 1/r^2 is one reciprocal
+            // refined twice (the force vanishes at r_c = 2^(1/6) sigma, so a
+            // decision that differs from r < r_c by a rounding changes no
+            // force); four sources per iteration keep independent chains in
+            // flight
+#pragma unroll 4
+            for (int jj = 0; jj < jn; jj++) {
+                const double r0 = x0 - readlane_d(y0, jj), r1 = x1 - readlane_d(y1, jj), r2 = x2 - readlane_d(y2, jj);
+                const double rr2 = fma(r2, r2, fma(r1, r1, r0 * r0));
+                if (!near || !(rr2 < rc2)) continue;
+                double inv = __builtin_amdgcn_rcp(rr2);
+                inv = fma(inv, fma(-rr2, inv, 1.0), inv);
+                inv = fma(inv, fma(-rr2, inv, 1.0), inv);
+                const double s2 = sig2 * inv, s6 = s2 * s2 * s2;
+                const double cf = c24 * fma(2.0 * s6, s6, -s6) * inv;
+                acc[0] = fma(cf, r0, acc[0]);
+                acc[1] = fma(cf, r1, acc[1]);
+                acc[2] = fma(cf, r2, acc[2]);
             }
         }
     }
@@ -600,7 +632,7 @@ hipError_t launch_lj(int stage_state, const EnsDesc *d_desc, const PointItem *d_
     hipLaunchKernelGGL(k_lj_boxes, dim3(n_box_items), dim3(kBlock), 0, s, stage_state, d_desc, d_box_items);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lj_forces, dim3(n_items), dim3(kBlock), 0, s, stage_state, d_desc, d_items);
+    hipLaunchKernelGGL(k_lj_forces, dim3(n_items), dim3(64 * kLjWaves), 0, s, stage_state, d_desc, d_items);
     return hipGetLastError();
 }
 

@@ -28,13 +28,29 @@ namespace mrs {
 // 256,000; the FP64 kernel, two targets per lane, gets slower).
 constexpr int kTailPercent = 8, kTailDiv = 4;
 
+// Small grids: when 128-source chunks would give fewer than half as many
+// blocks as there are compute units, chunks shrink to 64 sources and the
+// FP64 kernel takes one target per lane, so that twice to four times as many
+// waves hide the latency of the near-pair and contact work (measured on
+// MI355X at 1,275 points, 25 swimmers: FP32C pair kernel 48 -> 31 us, FP64
+// 23 -> 15 us).
+static bool small_grid(int64_t N, int tpl, int n_cu) {
+    const int64_t tiles = (N + (int64_t)kBlock * tpl - 1) / ((int64_t)kBlock * tpl);
+    return 2 * tiles * ((N + 2 * kKahanBlock - 1) / (2 * kKahanBlock)) < n_cu;
+}
+
 PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
     PairCfg c;
+    bool small = false;
     if (tuned) c = *tuned;
     else {
         c.mode = N <= 1024 ? PAIR_SPLIT : PAIR_TILE;
         c.tpl = (prec == MRS_FP32C) ? 1 : 2;
         c.K = 0;
+        if (c.mode == PAIR_TILE && small_grid(N, c.tpl, n_cu)) {
+            small = true;
+            c.tpl = 1;
+        }
     }
     if (c.mode == PAIR_SPLIT) {
         c.K = 1;
@@ -48,7 +64,7 @@ PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
     if (automatic) {
         const int64_t want_blocks = (int64_t)n_cu * 64;
         const int64_t K = (want_blocks + tiles - 1) / tiles;
-        chunk = std::max<int64_t>({(N + K - 1) / K, (int64_t)2 * kKahanBlock, N / 64});
+        chunk = std::max<int64_t>({(N + K - 1) / K, (int64_t)(small ? 1 : 2) * kKahanBlock, N / 64});
     } else {
         chunk = (N + c.K - 1) / c.K;
     }
