@@ -13,11 +13,12 @@ namespace mrs {
 
 // Default pair-kernel configuration for an ensemble of N points.  Small
 // ensembles use the wave-split kernel; larger ones the LDS-tiled kernel with
-// 1 (FP32C) or 2 (FP64) targets per lane and enough source chunks that the
-// grid holds ~64 blocks per compute unit (short blocks keep the tail of the
-// grid short; measured on MI355X at 12,800 and 256,000 points).  A chunk
-// has at least 128 sources and at least N/64, so the split-K partials stay
-// a small fraction of the pair work.
+// 1 (FP32C) or 2 (FP64; 1 for mid-size grids, below) targets per lane and
+// enough source chunks that the grid holds ~64 blocks per compute unit
+// (short blocks keep the tail of the grid short; measured on MI355X at
+// 12,800 and 256,000 points).  A chunk has at least 128 sources (64 in small
+// grids) and at least N/64, so the split-K partials stay a small fraction of
+// the pair work.
 //
 // Tail split (automatic FP32C tiled configurations of grids of at least four
 // blocks per compute unit): the last ~8% of the sources of every target tile
@@ -28,16 +29,22 @@ namespace mrs {
 // 256,000; the FP64 kernel, two targets per lane, gets slower).
 constexpr int kTailPercent = 8, kTailDiv = 4;
 
-// Small grids: when 128-source chunks would give fewer than half as many
-// blocks as there are compute units, chunks shrink to 64 sources and the
-// FP64 kernel takes one target per lane, so that twice to four times as many
-// waves hide the latency of the near-pair and contact work (measured on
-// MI355X at 1,275 points, 25 swimmers: FP32C pair kernel 48 -> 31 us, FP64
-// 23 -> 15 us).
-static bool small_grid(int64_t N, int tpl, int n_cu) {
+// Blocks of the tiled kernel at `tpl` targets per lane and 128-source chunks.
+static int64_t blocks_at(int64_t N, int tpl) {
     const int64_t tiles = (N + (int64_t)kBlock * tpl - 1) / ((int64_t)kBlock * tpl);
-    return 2 * tiles * ((N + 2 * kKahanBlock - 1) / (2 * kKahanBlock)) < n_cu;
+    return tiles * ((N + 2 * kKahanBlock - 1) / (2 * kKahanBlock));
 }
+
+// Mid-size and small grids (measured on MI355X, interleaved A/B against the
+// previous rule).  The FP64 kernel takes one target per lane when two would
+// give fewer than three blocks per compute unit: twice the waves hide the
+// FP64 latency of the near-pair and contact work (3,200 to 6,400 points:
+// -7% to -17% alone, -1% to -2% in batches of 16; neutral at 7,680).  When
+// 128-source chunks give at most one block per compute unit, chunks shrink
+// to 64 sources (2,048 points FP32C: -26% alone, neutral batched; 1,275
+// points, 25 swimmers: FP32C 48 -> 31 us, FP64 23 -> 15 us).
+static bool fp64_one_target(int64_t N, int n_cu) { return blocks_at(N, 2) < (int64_t)3 * n_cu; }
+static bool small_grid(int64_t N, int tpl, int n_cu) { return blocks_at(N, tpl) <= (int64_t)n_cu; }
 
 PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
     PairCfg c;
@@ -47,9 +54,9 @@ PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
         c.mode = N <= 1024 ? PAIR_SPLIT : PAIR_TILE;
         c.tpl = (prec == MRS_FP32C) ? 1 : 2;
         c.K = 0;
-        if (c.mode == PAIR_TILE && small_grid(N, c.tpl, n_cu)) {
-            small = true;
-            c.tpl = 1;
+        if (c.mode == PAIR_TILE) {
+            if (prec == MRS_FP64 && fp64_one_target(N, n_cu)) c.tpl = 1;
+            small = small_grid(N, c.tpl, n_cu);
         }
     }
     if (c.mode == PAIR_SPLIT) {

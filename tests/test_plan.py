@@ -99,6 +99,17 @@ def test_decomposition_sizes_on_mi355x():
     assert cfg["chunks"] == 33
     cfg, items = mrs.mrs_plan_items(3200, mrs.MRS_FP32C)  # too small a grid for the tail split
     assert cfg["chunks"] == 25 and cfg["tail_start"] == 3200 and items[:, 3].min() == 128
+    # mid-size FP64 grids: one target per lane below three blocks per CU at two
+    cfg, _ = mrs.mrs_plan_items(6400, mrs.MRS_FP64)
+    assert cfg == {"mode": 0, "targets_per_lane": 1, "chunks": 50, "tail_start": 6400}
+    cfg, _ = mrs.mrs_plan_items(7680, mrs.MRS_FP64)
+    assert cfg["targets_per_lane"] == 2 and cfg["chunks"] == 60
+    # at most one block per CU with 128-source chunks: 64-source chunks
+    for prec in (mrs.MRS_FP32C, mrs.MRS_FP64):
+        cfg, items = mrs.mrs_plan_items(2048, prec)
+        assert cfg["targets_per_lane"] == 1 and cfg["chunks"] == 32 and items[:, 3].max() == 64
+        cfg, items = mrs.mrs_plan_items(1275, prec)  # 25 swimmers of 51 points
+        assert cfg["targets_per_lane"] == 1 and cfg["chunks"] == 20
     cfg, _ = mrs.mrs_plan_items(1000, mrs.MRS_FP32C)
     assert cfg["mode"] == 1
 
