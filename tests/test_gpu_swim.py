@@ -52,9 +52,10 @@ def _frame_err(Da, Db):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("F,box", [(8, 2.0), (40, 4.0)])
-def test_swim_eval_matches_oracle(mrs, ctx, prec, F, box):
-    e, p = _swim(F=F, box=box)
+@pytest.mark.parametrize("F,box,seed", [(8, 2.0, 3), (40, 4.0, 3), (25, 4.0, 25)])
+def test_swim_eval_matches_oracle(mrs, ctx, prec, F, box, seed):
+    """(25, 4.0, 25) is the benchmarked 25-swimmer ensemble (1,275 points)."""
+    e, p = _swim(F=F, box=box, seed=seed)
     F = oracle.lj_forces(e.offsets, e.X, p.lj)
     assert np.count_nonzero(np.abs(F).sum(axis=1)) >= 4, "the geometry must bring filaments within r_c"
     t = 0.0371
@@ -72,6 +73,30 @@ def test_swim_eval_matches_oracle(mrs, ctx, prec, F, box):
     Ut, _ = oracle.velocities(e.offsets, e.X, e.D, p.rod, e.f, e.n, e.eps, e.mu, True, wave=p.wave,
                               t=t + 0.5 * math.pi / p.wave[2], lj=p.lj)
     assert oracle.rel_err(Ut, Uo) > 1e-3
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_swim25_rk2_steps_match_oracle(mrs, ctx, prec):
+    """The benchmarked 25-swimmer ensemble (box 4, seed 25) stepped with the
+    timed propagator, midpoint RK2 at dt = 1e-6, teacher-forced per step."""
+    e, p = _swim(F=25, box=4.0, seed=25)
+    dt = 1e-6
+    ens = _create(mrs, ctx, e, p)
+    try:
+        X, D, _, _ = mrs.mrs_ensemble_get(ctx, ens)
+        t = 0.0
+        for step in range(2):
+            Xo, Do, _, _, to = oracle.step_ex(e.offsets, X, D, p.rod, e.f, e.n, e.eps, e.mu, oracle.RK2, dt, 1,
+                                              wave=p.wave, t=t, lj=p.lj)
+            mrs.mrs_ensemble_step(ctx, ens, mrs.MRS_RK2, dt, 1, prec, True)
+            X1, D1, _, _ = mrs.mrs_ensemble_get(ctx, ens)
+            ex, ed = step_err(X1, Xo, X), _frame_err(D1, Do)
+            say(f"swim25 RK2 prec={prec} step {step}: dX {ex:.3e} D {ed:.3e}")
+            assert ex <= TOL[prec] and ed <= TOL[prec]
+            assert mrs.mrs_ensemble_get_time(ctx, ens) == to
+            X, D, t = X1, D1, to
+    finally:
+        mrs.mrs_ensemble_destroy(ens)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
