@@ -114,6 +114,17 @@ def test_decomposition_sizes_on_mi355x():
     assert cfg["mode"] == 1
 
 
+def test_size_rules_follow_the_cu_count():
+    """The one-target and 64-source-chunk rules are stated in blocks per
+    compute unit, so a device with fewer CUs switches at smaller sizes."""
+    for n_cu, n, prec, tpl, K in [(80, 1275, mrs.MRS_FP32C, 1, 20), (80, 2048, mrs.MRS_FP32C, 1, 16),
+                                  (256, 2048, mrs.MRS_FP32C, 1, 32), (80, 3200, mrs.MRS_FP64, 1, 25),
+                                  (80, 6400, mrs.MRS_FP64, 2, 50), (256, 6400, mrs.MRS_FP64, 1, 50)]:
+        cfg, items = mrs.mrs_plan_items(n, prec, n_cu)
+        assert (cfg["targets_per_lane"], cfg["chunks"]) == (tpl, K), (n_cu, n, prec, cfg)
+        _cover_check(n, items)
+
+
 def test_plan_items_invalid_arguments():
     for args in [(0, mrs.MRS_FP32C, 256), (10, 7, 256), (10, mrs.MRS_FP64, 0), (2**31, mrs.MRS_FP64, 256)]:
         with pytest.raises(mrs.MrsError) as ei:
