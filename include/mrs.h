@@ -141,7 +141,12 @@ mrs_status mrs_rotsqrt_device(mrs_context *ctx, int64_t count, const double *dR,
 
 /* Copy a filament ensemble to the device: offsets (n_fil + 1), X (n x 3),
  * D (n x 9), external point loads f_ext, n_ext (n x 3, NULL = zero; held
- * constant during steps), eps, mu and the rod moduli. */
+ * constant during steps), eps, mu and the rod moduli.  The device copy keeps
+ * the filaments in a spatial order of the library's choosing (by the Morton
+ * key of their centroids at creation, filaments whole), so that the pair
+ * kernels' blocks of consecutive points stay compact; every array passed to
+ * or returned by the ensemble calls uses the caller's order, and the order
+ * in which the caller lists the filaments does not change any result. */
 mrs_status mrs_ensemble_create(mrs_context *ctx, int32_t n_fil, const int32_t *offsets,
                                const double *X, const double *D, const double *f_ext,
                                const double *n_ext, double eps, double mu,

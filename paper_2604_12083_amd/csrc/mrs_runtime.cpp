@@ -359,6 +359,7 @@ mrs_status ensemble_clone(mrs_ensemble *S, mrs_ensemble **out) {
     if (st != MRS_OK) return st;
     const size_t v3 = (size_t)S->N * 3 * sizeof(double), v9 = 3 * v3;
     hipStream_t s = ctx->stream;
+    E->perm = S->perm;
     E->has_wave = S->has_wave;
     E->has_lj = S->has_lj;
     for (int i = 0; i < 3; i++) E->wave[i] = S->wave[i];
@@ -674,21 +675,79 @@ mrs_status mrs_rotsqrt_device(mrs_context *ctx, int64_t count, const double *dR,
 
 // ---- ensembles
 
-static void aos_to_soa(const double *src, double *dst, int64_t n, int w) {
+// Row-major caller arrays (n x w) to and from the stored SoA layout; stored
+// point k is caller point perm[k].
+static void aos_to_soa(const double *src, double *dst, int64_t n, int w, const std::vector<int64_t> &perm) {
     for (int64_t k = 0; k < n; k++)
-        for (int c = 0; c < w; c++) dst[(size_t)c * n + k] = src[(size_t)w * k + c];
+        for (int c = 0; c < w; c++) dst[(size_t)c * n + k] = src[(size_t)w * perm[k] + c];
 }
 
-static void soa_to_aos(const double *src, double *dst, int64_t n, int w) {
+static void soa_to_aos(const double *src, double *dst, int64_t n, int w, const std::vector<int64_t> &perm) {
     for (int64_t k = 0; k < n; k++)
-        for (int c = 0; c < w; c++) dst[(size_t)w * k + c] = src[(size_t)c * n + k];
+        for (int c = 0; c < w; c++) dst[(size_t)w * perm[k] + c] = src[(size_t)c * n + k];
 }
 
-static mrs_status put_soa(mrs_context *ctx, DevBuf &d, const double *src, int64_t n, int w) {
+static mrs_status put_soa(mrs_context *ctx, DevBuf &d, const double *src, int64_t n, int w,
+                          const std::vector<int64_t> &perm) {
     std::vector<double> tmp((size_t)n * w);
-    aos_to_soa(src, tmp.data(), n, w);
+    aos_to_soa(src, tmp.data(), n, w, perm);
     HIPCHK(ctx, hipMemcpy(d.p, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice));
     return MRS_OK;
+}
+
+// 21-bit spread for a 63-bit Morton key.
+static uint64_t spread3(uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
+// Stored order of an ensemble's filaments: by the Morton key of their
+// centroids (ties by caller index), whole filaments kept together.  The pair
+// kernels cut the points into blocks of consecutive indices; filaments that
+// are neighbours in space then share blocks, so a block's box stays small and
+// far blocks take the anchored path (filaments shorter than a block, placed
+// in random order, otherwise give boxes spanning the domain and every block
+// the masked path).  Results are returned in the caller's order; only the
+// order of floating-point sums changes.  Writes the stored offsets and the
+// point permutation (stored point k = caller point perm[k]).
+static void spatial_order(int32_t n_fil, const int32_t *off, const double *X, std::vector<int32_t> &soff,
+                          std::vector<int64_t> &perm) {
+    const int64_t n = off[n_fil];
+    std::vector<double> cen((size_t)n_fil * 3, 0.0);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t f = 0; f < n_fil; f++) {
+        for (int c = 0; c < 3; c++) {
+            double s = 0.0;
+            for (int32_t k = off[f]; k < off[f + 1]; k++) s += X[3 * (size_t)k + c];
+            cen[3 * (size_t)f + c] = s / (off[f + 1] - off[f]);
+            lo[c] = std::min(lo[c], cen[3 * (size_t)f + c]);
+            hi[c] = std::max(hi[c], cen[3 * (size_t)f + c]);
+        }
+    }
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)n_fil);
+    for (int32_t f = 0; f < n_fil; f++) {
+        uint64_t m = 0;
+        for (int c = 0; c < 3; c++) {
+            const double span = hi[c] - lo[c];
+            const double u = span > 0.0 ? (cen[3 * (size_t)f + c] - lo[c]) / span : 0.0;
+            m |= spread3((uint64_t)std::min(2097151.0, std::max(0.0, u * 2097151.0))) << c;
+        }
+        key[f] = {m, f};
+    }
+    std::sort(key.begin(), key.end());
+    soff.assign((size_t)n_fil + 1, 0);
+    perm.resize((size_t)n);
+    int64_t pos = 0;
+    for (int32_t i = 0; i < n_fil; i++) {
+        const int32_t f = key[i].second;
+        for (int32_t k = off[f]; k < off[f + 1]; k++) perm[pos++] = k;
+        soff[i + 1] = (int32_t)pos;
+    }
 }
 
 static bool all_finite(const double *p, size_t n) {
@@ -713,15 +772,19 @@ mrs_status mrs_ensemble_create(mrs_context *ctx, int32_t n_fil, const int32_t *o
         (n_ext && !all_finite(n_ext, 3 * n)))
         return fail(ctx, MRS_EINVAL, "non-finite input");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    std::vector<int32_t> soff;
+    std::vector<int64_t> perm;
+    spatial_order(n_fil, offsets, X, soff, perm);
     std::unique_ptr<mrs_ensemble> E;
-    mrs_status st = ensemble_alloc(ctx, n_fil, offsets, eps, mu, rod, f_ext || n_ext, E);
+    mrs_status st = ensemble_alloc(ctx, n_fil, soff.data(), eps, mu, rod, f_ext || n_ext, E);
     if (st != MRS_OK) return st;
-    if ((st = put_soa(ctx, E->X, X, n, 3)) != MRS_OK) return st;
-    if ((st = put_soa(ctx, E->D, D, n, 9)) != MRS_OK) return st;
+    E->perm = std::move(perm);
+    if ((st = put_soa(ctx, E->X, X, n, 3, E->perm)) != MRS_OK) return st;
+    if ((st = put_soa(ctx, E->D, D, n, 9, E->perm)) != MRS_OK) return st;
     if (E->has_ext) {
         std::vector<double> z((size_t)3 * n, 0.0);
-        if ((st = put_soa(ctx, E->fext, f_ext ? f_ext : z.data(), n, 3)) != MRS_OK) return st;
-        if ((st = put_soa(ctx, E->next, n_ext ? n_ext : z.data(), n, 3)) != MRS_OK) return st;
+        if ((st = put_soa(ctx, E->fext, f_ext ? f_ext : z.data(), n, 3, E->perm)) != MRS_OK) return st;
+        if ((st = put_soa(ctx, E->next, n_ext ? n_ext : z.data(), n, 3, E->perm)) != MRS_OK) return st;
     }
     ctx->ensembles.push_back(E.get());
     *out = E.release();
@@ -736,8 +799,8 @@ mrs_status mrs_ensemble_set_state(mrs_ensemble *E, const double *X, const double
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     mrs_status st;
-    if (X && (st = put_soa(ctx, E->X, X, E->N, 3)) != MRS_OK) return st;
-    if (D && (st = put_soa(ctx, E->D, D, E->N, 9)) != MRS_OK) return st;
+    if (X && (st = put_soa(ctx, E->X, X, E->N, 3, E->perm)) != MRS_OK) return st;
+    if (D && (st = put_soa(ctx, E->D, D, E->N, 9, E->perm)) != MRS_OK) return st;
     return MRS_OK;
 }
 
@@ -851,7 +914,7 @@ mrs_status mrs_ensemble_get(mrs_ensemble *E, double *X, double *D, double *U, do
     for (auto &o : outs) {
         if (!o.dst) continue;
         HIPCHK(ctx, hipMemcpy(tmp.data(), o.src->p, (size_t)n * o.w * sizeof(double), hipMemcpyDeviceToHost));
-        soa_to_aos(tmp.data(), o.dst, n, o.w);
+        soa_to_aos(tmp.data(), o.dst, n, o.w, E->perm);
     }
     return MRS_OK;
 }

@@ -112,7 +112,10 @@ struct mrs_ensemble {
     uint64_t uid = 0;  // unique per process; plan caches key on it, never on addresses
     int32_t n_fil = 0;
     int64_t N = 0;
-    std::vector<int32_t> offsets;
+    std::vector<int32_t> offsets;  // CSR over the filaments in the stored (spatial) order
+    // Point k of the stored order is point perm[k] of the caller's order
+    // (filaments kept whole; see spatial_order in mrs_runtime.cpp).
+    std::vector<int64_t> perm;
     double eps = 0, mu = 0;
     mrs_rod_params rod{};
     bool has_ext = false;
