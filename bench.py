@@ -40,6 +40,8 @@ MEASURED_TRAFFIC = {
     ("ens12800", "fp64", "adb3c89bda2d142d"): (4134.22 * 2.0 + 30000.0) * 1024,
     ("ens256000", "fp32c", "4a2b01f9e8a27aa9"): (183519.27 * 2.0 + 264000.0) * 1024,
     ("ens256000", "fp64", "571ba5e594123b76"): (471073.36 * 2.0 + 396000.0) * 1024,
+    ("swim", "fp32c", "72ec18efbf0e53ad"): (34175.97 * 2.0 + 176908.13) * 1024,
+    ("swim", "fp64", "df10004c75444124"): (90326.99 * 2.0 + 148220.98) * 1024,
 }
 
 
