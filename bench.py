@@ -110,8 +110,9 @@ def measure(mrs, ctx, e, prec, steps, warmup, dt, integ=None, swim=None):
             lat.append((time.perf_counter() - t0) * 1e3)
         # throughput: K steps queued back to back; HIP events bracket the
         # dominant pair kernel only, on the stream it is launched on
-        kname = ("pairs_tile_f32c" if prec == mrs.MRS_FP32C else "pairs_tile_f64") if e.N > 1024 else \
-            ("pairs_split_f32c" if prec == mrs.MRS_FP32C else "pairs_split_f64")
+        split = mrs.mrs_tune_get(ctx, e.N, prec)["mode"] == 1
+        kname = ("pairs_split_f32c" if prec == mrs.MRS_FP32C else "pairs_split_f64") if split else \
+            ("pairs_tile_f32c" if prec == mrs.MRS_FP32C else "pairs_tile_f64")
         mrs.mrs_profile_reset(ctx)
         mrs.mrs_profile_select(ctx, kname)
         mrs.mrs_profile_enable(ctx, True)

@@ -13,7 +13,11 @@ constexpr int kSrcTile = 256;
 // Sources summed in plain FP32 before one compensated (Kahan) update.
 constexpr int kKahanBlock = 64;
 // Targets per wave in the small-N pair kernel (lanes split the sources).
-constexpr int kSplitTargetsPerWave = 4;
+// One: the kernel is latency-bound, and four times the waves shorten each
+// wave's chain (MI355X: 64 points 10.2 -> 6.6 us FP32C, 8.2 -> 6.3 us FP64;
+// 960 points 27.7 -> 15.0 us and 19.1 -> 11.8 us; same results, since each
+// target's sum is formed the same way).
+constexpr int kSplitTargetsPerWave = 1;
 constexpr int kSplitTargetsPerBlock = kSplitTargetsPerWave * (kBlock / 64);
 
 // Source record of the FP32C pair kernel, 48 bytes, read as three float4:

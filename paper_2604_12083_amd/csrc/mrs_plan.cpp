@@ -12,7 +12,7 @@
 namespace mrs {
 
 // Default pair-kernel configuration for an ensemble of N points.  Small
-// ensembles use the wave-split kernel; larger ones the LDS-tiled kernel with
+// ensembles (split_mode) use the wave-split kernel; larger ones the LDS-tiled kernel with
 // 1 (FP32C) or 2 (FP64; 1 for mid-size grids, below) targets per lane and
 // enough source chunks that the grid holds ~64 blocks per compute unit
 // (short blocks keep the tail of the grid short; measured on MI355X at
@@ -44,6 +44,14 @@ static int64_t blocks_at(int64_t N, int tpl) {
 // to 64 sources (2,048 points FP32C: -26% alone, neutral batched; 1,275
 // points, 25 swimmers: FP32C 48 -> 31 us, FP64 23 -> 15 us).
 static bool fp64_one_target(int64_t N, int n_cu) { return blocks_at(N, 2) < (int64_t)3 * n_cu; }
+
+// Ensembles up to this size use the wave-split kernel (one target per wave,
+// lanes split the sources).  FP32C keeps it up to 1,536 points, where it beat
+// the tiled kernel on MI355X (pair + reduction kernels: 1,152 points 22.6 vs
+// 25.8 us, 1,275 points (25 swimmers) 32.8 vs 37.0, 1,536 points 25.1 vs
+// 26.6; 2,048 points 29.9 vs 27.6); FP64 was even up to 1,536 and slower at
+// 2,048, so it switches at 1,024.
+static bool split_mode(int64_t N, int prec) { return N <= (prec == MRS_FP32C ? 1536 : 1024); }
 static bool small_grid(int64_t N, int tpl, int n_cu) { return blocks_at(N, tpl) <= (int64_t)n_cu; }
 
 PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
@@ -51,7 +59,7 @@ PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
     bool small = false;
     if (tuned) c = *tuned;
     else {
-        c.mode = N <= 1024 ? PAIR_SPLIT : PAIR_TILE;
+        c.mode = split_mode(N, prec) ? PAIR_SPLIT : PAIR_TILE;
         c.tpl = (prec == MRS_FP32C) ? 1 : 2;
         c.K = 0;
         if (c.mode == PAIR_TILE) {
