@@ -554,7 +554,11 @@ mrs_status mrs_eval_host(mrs_context *ctx, int64_t n, const double *X, const dou
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     hipStream_t s = ctx->stream;
     const size_t b = (size_t)n * 3 * sizeof(double);
-    DevBuf io;
+    // kept by the context: no device allocation (and no freeing, which waits
+    // for the device) per call; growing it frees the old one, so first wait
+    // for anything still queued that could use it
+    DevBuf &io = ctx->eval_io;
+    if (io.bytes < 5 * b) HIPCHK(ctx, hipStreamSynchronize(s));
     HIPCHK(ctx, io.reserve(5 * b));
     double *dX = io.as<double>(), *df = dX + 3 * n, *dn = df + 3 * n, *dU = dn + 3 * n, *dW = dU + 3 * n;
     HIPCHK(ctx, hipMemcpyAsync(dX, X, b, hipMemcpyHostToDevice, s));

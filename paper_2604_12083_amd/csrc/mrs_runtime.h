@@ -89,6 +89,7 @@ struct mrs_context {
     std::string err;
     // scratch of the one-shot evaluation
     mrs::DevBuf eval_rec, eval_part, eval_desc, eval_items, eval_rod;
+    mrs::DevBuf eval_io;  // mrs_eval_host's device copies of X, f, n, U, Omega (grow-only)
     // pinned staging for small uploads, reused after its event completes
     void *stage_host = nullptr;
     size_t stage_bytes = 0;
