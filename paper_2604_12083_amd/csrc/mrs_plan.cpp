@@ -12,8 +12,9 @@
 namespace mrs {
 
 // Default pair-kernel configuration for an ensemble of N points.  Small
-// ensembles (split_mode) use the wave-split kernel; larger ones the LDS-tiled kernel with
-// 1 (FP32C) or 2 (FP64; 1 for mid-size grids, below) targets per lane and
+// ensembles (split_mode) use the wave-split kernel; larger ones the
+// LDS-tiled kernel with 1 (FP32C) or 2 (FP64; 1 for mid-size grids, below)
+// targets per lane and
 // enough source chunks that the grid holds ~64 blocks per compute unit
 // (short blocks keep the tail of the grid short; measured on MI355X at
 // 12,800 and 256,000 points).  A chunk has at least 128 sources (64 in small
@@ -42,8 +43,10 @@ static int64_t blocks_at(int64_t N, int tpl) {
 // -7% to -17% alone, -1% to -2% in batches of 16; neutral at 7,680).  When
 // 128-source chunks give at most one block per compute unit, chunks shrink
 // to 64 sources (2,048 points FP32C: -26% alone, neutral batched; 1,275
-// points, 25 swimmers: FP32C 48 -> 31 us, FP64 23 -> 15 us).
+// points, 25 swimmers: FP64 23 -> 15 us, and FP32C 48 -> 31 us before that
+// size moved to the wave-split kernel).
 static bool fp64_one_target(int64_t N, int n_cu) { return blocks_at(N, 2) < (int64_t)3 * n_cu; }
+static bool small_grid(int64_t N, int tpl, int n_cu) { return blocks_at(N, tpl) <= (int64_t)n_cu; }
 
 // Ensembles up to this size use the wave-split kernel (one target per wave,
 // lanes split the sources).  FP32C keeps it up to 1,536 points, where it beat
@@ -52,7 +55,6 @@ static bool fp64_one_target(int64_t N, int n_cu) { return blocks_at(N, 2) < (int
 // 26.6; 2,048 points 29.9 vs 27.6); FP64 was even up to 1,536 and slower at
 // 2,048, so it switches at 1,024.
 static bool split_mode(int64_t N, int prec) { return N <= (prec == MRS_FP32C ? 1536 : 1024); }
-static bool small_grid(int64_t N, int tpl, int n_cu) { return blocks_at(N, tpl) <= (int64_t)n_cu; }
 
 PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
     PairCfg c;
