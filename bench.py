@@ -34,14 +34,14 @@ FLOPS_PER_PAIR = 92       # algorithmic flops of one (target, source) evaluation
 # blocks `mrs_plan_items` gives for the workload) they were taken on: any
 # other kernel or decomposition reports null.
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_12083_amd", "csrc", "mrs_pairs.hip")
-KERNEL_SHA = "6dcc14e18a5200f81ed940b25525aa5a073f2f69f155c244ff15fca792d72597"
+KERNEL_SHA = "30ba426091534d1ca9c03f292a90ea92b429d48142b109c54bc52ebb22006047"
 MEASURED_TRAFFIC = {
-    ("ens12800", "fp32c", "678ec7c5e5d82ecf"): (2707.30 * 2.0 + 37200.0) * 1024,
-    ("ens12800", "fp64", "adb3c89bda2d142d"): (4134.22 * 2.0 + 30000.0) * 1024,
-    ("ens256000", "fp32c", "4a2b01f9e8a27aa9"): (183519.27 * 2.0 + 264000.0) * 1024,
-    ("ens256000", "fp64", "571ba5e594123b76"): (471073.36 * 2.0 + 396000.0) * 1024,
-    ("swim", "fp32c", "72ec18efbf0e53ad"): (34175.97 * 2.0 + 176908.13) * 1024,
-    ("swim", "fp64", "df10004c75444124"): (90326.99 * 2.0 + 148220.98) * 1024,
+    ("ens12800", "fp32c", "678ec7c5e5d82ecf"): (2706.80 * 2.0 + 37200.0) * 1024,
+    ("ens12800", "fp64", "adb3c89bda2d142d"): (4134.21 * 2.0 + 30000.0) * 1024,
+    ("ens256000", "fp32c", "4a2b01f9e8a27aa9"): (183528.43 * 2.0 + 264000.0) * 1024,
+    ("ens256000", "fp64", "571ba5e594123b76"): (471076.54 * 2.0 + 396000.0) * 1024,
+    ("swim", "fp32c", "72ec18efbf0e53ad"): (34185.52 * 2.0 + 176908.05) * 1024,
+    ("swim", "fp64", "df10004c75444124"): (90377.61 * 2.0 + 148221.08) * 1024,
 }
 
 

@@ -428,18 +428,31 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Small-ensemble pair kernel: each wave owns kSplitTargetsPerWave targets and
 // its 64 lanes stride over the item's sources; per-lane sums are combined in
 // FP64 with a butterfly of wave shuffles in a fixed order.
+// Sources staged through LDS per round by the whole block (its waves share
+// them): FP32C rounds are the 1,024-source compensated chunks of the loop
+// below (48 KB), FP64 rounds 256 sources (20 KB).  A lane reads its sources
+// in the same order as straight from the records, so the staging changes no
+// result; it replaces one dependent global load per lane and 64 sources by
+// one per round.
+constexpr int kSplitPerLane = 16;  // FP32C: sources per lane between compensated updates
+constexpr int kSplitRoundF32 = 64 * kSplitPerLane, kSplitRoundF64 = kBlock;
+
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restrict__ desc,
                                                         const PairItem *__restrict__ items) {
     constexpr int TW = kSplitTargetsPerWave;
+    static_assert(sizeof(RecF32) == 48 && sizeof(RecF64) == 80, "record layouts");
+    __shared__ float4 sBuf[PREC == 1 ? 3 * kSplitRoundF32 : 5 * kSplitRoundF64];
     const PairItem it = items[blockIdx.x];
     const EnsDesc &E = desc[it.ens];
-    const int lane = threadIdx.x & 63;
-    const int tb = (threadIdx.x >> 6) * TW;
-    if (tb >= it.ntgt) return;  // whole wave idle (wave-uniform)
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int tb = (tid >> 6) * TW;
+    // a wave without targets still stages sources and meets every barrier
+    const bool active = tb < it.ntgt;  // wave-uniform
     double out[TW][6];
     if (PREC == 1) {
         const RecF32 *__restrict__ rec = reinterpret_cast<const RecF32 *>(E.rec);
+        RecF32 *sRec = reinterpret_cast<RecF32 *>(sBuf);
         float thx[TW], thy[TW], thz[TW], tlx[TW], tly[TW], tlz[TW], s[TW][6], c[TW][6];
         double pn[TW][6];
 #pragma unroll
@@ -450,22 +463,25 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
 #pragma unroll
             for (int k = 0; k < 6; k++) { s[t][k] = 0.f; c[t][k] = 0.f; pn[t][k] = 0.0; }
         }
-        constexpr int kPerLane = 16;  // sources per lane between compensated updates
-        for (int j0 = 0; j0 < it.nsrc; j0 += 64 * kPerLane) {
+        for (int j0 = 0; j0 < it.nsrc; j0 += kSplitRoundF32) {
+            const int cnt = min(kSplitRoundF32, it.nsrc - j0);
+            __syncthreads();
+            for (int q = tid; q < cnt; q += kBlock) sRec[q] = rec[it.src0 + j0 + q];
+            __syncthreads();
+            if (!active) continue;
             float p[TW][6];
             float rmin = kNearR2;
 #pragma unroll
             for (int t = 0; t < TW; t++)
 #pragma unroll
                 for (int k = 0; k < 6; k++) p[t][k] = 0.f;
-            const int jend = min(j0 + 64 * kPerLane, it.nsrc);
-            for (int j = j0 + lane; j < jend; j += 64) {
-                const int jg = it.src0 + j;
+            for (int j = lane; j < cnt; j += 64) {
+                const int jg = it.src0 + j0 + j;
                 if (E.lj_mask && ((E.lj_mask[jg / kLjMaskPoints] >> (jg % kLjMaskPoints)) & 1)) {
                     rmin = 0.0f;  // a source with contact forces: FP64 below
                     continue;
                 }
-                const RecF32 r = rec[it.src0 + j];
+                const RecF32 r = sRec[j];
 #pragma unroll
                 for (int t = 0; t < TW; t++)
                     rmin = fminf(rmin, pair_f32<true>(thx[t], thy[t], thz[t], tlx[t], tly[t], tlz[t], r.a, r.b, r.c, p[t]));
@@ -475,9 +491,9 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
 #pragma unroll
                 for (int k = 0; k < 6; k++) kahan_add(s[t][k], c[t][k], p[t][k]);
             if (rmin < kNearR2) {  // near pairs and contact-force blocks of this lane's sources: FP64
-                for (int j = j0 + lane; j < jend; j += 64) {
-                    const RecF32 r = rec[it.src0 + j];
-                    const int jg = it.src0 + j;
+                for (int j = lane; j < cnt; j += 64) {
+                    const RecF32 r = sRec[j];
+                    const int jg = it.src0 + j0 + j;
                     const bool strong = E.lj_mask && ((E.lj_mask[jg / kLjMaskPoints] >> (jg % kLjMaskPoints)) & 1);
 #pragma unroll
                     for (int t = 0; t < TW; t++) {
@@ -490,12 +506,14 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
                 }
             }
         }
+        if (!active) return;  // no barrier follows
 #pragma unroll
         for (int t = 0; t < TW; t++)
 #pragma unroll
             for (int k = 0; k < 6; k++) out[t][k] = wave_sum(((double)s[t][k] - (double)c[t][k]) + pn[t][k]);
     } else {
         const RecF64 *__restrict__ rec = reinterpret_cast<const RecF64 *>(E.rec);
+        RecF64 *sRec = reinterpret_cast<RecF64 *>(sBuf);
         const double e2 = E.eps * E.eps, c375e2 = 3.75 * e2;
         double tx[TW], ty[TW], tz[TW], acc[TW][6];
 #pragma unroll
@@ -505,13 +523,20 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
 #pragma unroll
             for (int k = 0; k < 6; k++) acc[t][k] = 0.0;
         }
-        for (int j = lane; j < it.nsrc; j += 64) {
-            const RecF64 &r = rec[it.src0 + j];
-            const double x = r.x, y = r.y, z = r.z, fx = r.fx, fy = r.fy, fz = r.fz, nx = r.nx,
-                         ny = r.ny, nz = r.nz;
+        for (int j0 = 0; j0 < it.nsrc; j0 += kSplitRoundF64) {
+            const int cnt = min(kSplitRoundF64, it.nsrc - j0);
+            __syncthreads();
+            for (int q = tid; q < cnt; q += kBlock) sRec[q] = rec[it.src0 + j0 + q];
+            __syncthreads();
+            if (!active) continue;
+            for (int j = lane; j < cnt; j += 64) {
+                const RecF64 r = sRec[j];
 #pragma unroll
-            for (int t = 0; t < TW; t++) pair_f64(tx[t], ty[t], tz[t], x, y, z, fx, fy, fz, nx, ny, nz, e2, c375e2, acc[t]);
+                for (int t = 0; t < TW; t++)
+                    pair_f64(tx[t], ty[t], tz[t], r.x, r.y, r.z, r.fx, r.fy, r.fz, r.nx, r.ny, r.nz, e2, c375e2, acc[t]);
+            }
         }
+        if (!active) return;  // no barrier follows
 #pragma unroll
         for (int t = 0; t < TW; t++)
 #pragma unroll
