@@ -280,8 +280,8 @@ mrs_status mrs_server_stop(mrs_server *srv);
  * (targets_per_lane 1 or 2, `chunks` source chunks of equal size, 0 =
  * automatic), mode 1 = wave-split for small ensembles.  Without a stored
  * configuration the library picks one from n and the compute-unit count:
- * wave-split up to 1,536 points (FP32C) or 1,024 (FP64), else one target
- * per lane (FP32C, and FP64 when two would give fewer than three blocks per
+ * wave-split up to 1,024 points, else one target per lane (FP32C, and
+ * FP64 when two would give fewer than three blocks per
  * compute unit) or two, and source chunks of 128 sources or more (64 when
  * 128 would give at most one block per compute unit).  An automatic FP32C
  * configuration of a large grid

@@ -48,13 +48,14 @@ static int64_t blocks_at(int64_t N, int tpl) {
 static bool fp64_one_target(int64_t N, int n_cu) { return blocks_at(N, 2) < (int64_t)3 * n_cu; }
 static bool small_grid(int64_t N, int tpl, int n_cu) { return blocks_at(N, tpl) <= (int64_t)n_cu; }
 
-// Ensembles up to this size use the wave-split kernel (one target per wave,
-// lanes split the sources).  FP32C keeps it up to 1,536 points, where it beat
-// the tiled kernel on MI355X (pair + reduction kernels: 1,152 points 22.6 vs
-// 25.8 us, 1,275 points (25 swimmers) 32.8 vs 37.0, 1,536 points 25.1 vs
-// 26.6; 2,048 points 29.9 vs 27.6); FP64 was even up to 1,536 and slower at
-// 2,048, so it switches at 1,024.
-static bool split_mode(int64_t N, int prec) { return N <= (prec == MRS_FP32C ? 1536 : 1024); }
+// Ensembles up to 1,024 points use the wave-split kernel (one target per
+// wave, lanes split the sources), in both precisions.  Alone it is faster
+// than the tiled kernel up to ~1,500 points (MI355X, pair + reduction
+// kernels, FP32C: 1,024 points 18.8 vs 25.8 us, 1,280 points 20.4 vs 26.1),
+// but in batches of 16 ensembles it loses from ~1,000 points on (1,024
+// points 67 vs 44 us, 1,280 points 90 vs 58; 512 points even), so the limit
+// stays where the batched cost is still moderate.
+static bool split_mode(int64_t N, int) { return N <= 1024; }
 
 PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
     PairCfg c;

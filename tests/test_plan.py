@@ -47,7 +47,7 @@ def test_every_pair_covered_once_with_own_slot(n, prec):
     tiles = _cover_check(n, items)
     K = cfg["chunks"]
     assert items[:, 4].min() >= 0 and items[:, 4].max() < K
-    split_max = 1536 if prec == mrs.MRS_FP32C else 1024
+    split_max = 1024
     if cfg["mode"] == 1:  # wave-split kernel for small ensembles: one chunk
         assert n <= split_max and K == 1
         return
@@ -109,12 +109,11 @@ def test_decomposition_sizes_on_mi355x():
     for prec in (mrs.MRS_FP32C, mrs.MRS_FP64):
         cfg, items = mrs.mrs_plan_items(2048, prec)
         assert cfg["targets_per_lane"] == 1 and cfg["chunks"] == 32 and items[:, 3].max() == 64
-    cfg, _ = mrs.mrs_plan_items(1275, mrs.MRS_FP64)  # 25 swimmers of 51 points
-    assert cfg["targets_per_lane"] == 1 and cfg["chunks"] == 20
-    # the wave-split kernel: up to 1,536 points in FP32C, 1,024 in FP64
-    for n, prec, mode in [(1536, mrs.MRS_FP32C, 1), (1537, mrs.MRS_FP32C, 0), (1275, mrs.MRS_FP32C, 1),
-                          (1024, mrs.MRS_FP64, 1), (1025, mrs.MRS_FP64, 0)]:
-        assert mrs.mrs_plan_items(n, prec)[0]["mode"] == mode, (n, prec)
+    for prec in (mrs.MRS_FP32C, mrs.MRS_FP64):
+        cfg, _ = mrs.mrs_plan_items(1275, prec)  # 25 swimmers of 51 points
+        assert cfg["targets_per_lane"] == 1 and cfg["chunks"] == 20
+        # the wave-split kernel up to 1,024 points
+        assert mrs.mrs_plan_items(1024, prec)[0]["mode"] == 1 and mrs.mrs_plan_items(1025, prec)[0]["mode"] == 0
     cfg, _ = mrs.mrs_plan_items(1000, mrs.MRS_FP32C)
     assert cfg["mode"] == 1
 
@@ -122,7 +121,7 @@ def test_decomposition_sizes_on_mi355x():
 def test_size_rules_follow_the_cu_count():
     """The one-target and 64-source-chunk rules are stated in blocks per
     compute unit, so a device with fewer CUs switches at smaller sizes."""
-    for n_cu, n, prec, tpl, K in [(80, 1275, mrs.MRS_FP64, 1, 20), (80, 2048, mrs.MRS_FP32C, 1, 16),
+    for n_cu, n, prec, tpl, K in [(80, 1275, mrs.MRS_FP32C, 1, 20), (80, 2048, mrs.MRS_FP32C, 1, 16),
                                   (256, 2048, mrs.MRS_FP32C, 1, 32), (80, 3200, mrs.MRS_FP64, 1, 25),
                                   (80, 6400, mrs.MRS_FP64, 2, 50), (256, 6400, mrs.MRS_FP64, 1, 50)]:
         cfg, items = mrs.mrs_plan_items(n, prec, n_cu)
