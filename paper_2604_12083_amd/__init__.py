@@ -8,7 +8,8 @@ call takes device pointers (their data_ptr is used) and the current torch
 stream may be passed as `stream`.
 
 The library must be built (``python -m paper_2604_12083_amd.build`` or
-``__graft_entry__.build()``); importing this package without it raises.
+``__graft_entry__.build()``); without it the package imports (so that the
+build module can run) but every entry point raises ImportError.
 """
 from __future__ import annotations
 
@@ -27,10 +28,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmrs.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "mrs.h")
 
-if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_12083_amd.build`")
 
-_lib = ctypes.CDLL(LIB_PATH)
+
+class _MissingLibrary:
+    """Stands in for libmrs.so until it is built: every call raises, so
+    nothing runs without the HIP library (there is no other code path)."""
+
+    def __getattr__(self, name):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_12083_amd.build` "
+                          f"(needed for {name})")
+
+
+_lib = _MissingLibrary()
 
 MRS_OK, MRS_EINVAL, MRS_ENOMEM, MRS_EDEVICE, MRS_ENOTREADY, MRS_EBUSY, MRS_ENUMERIC = 0, -1, -2, -3, -4, -5, -6
 MRS_FP64, MRS_FP32C = 0, 1
@@ -133,11 +142,29 @@ _SIGS = {
     "mrs_profile_query": (_int, [_vp, ctypes.c_char_p, ctypes.POINTER(_i64), ctypes.POINTER(_dbl)]),
 }
 
-for _name, (_res, _args) in _SIGS.items():
-    if hasattr(_lib, _name):
-        _f = getattr(_lib, _name)
-        _f.restype = _res
-        _f.argtypes = _args
+
+
+def _load_library():
+    """Load libmrs.so and declare the C signatures."""
+    global _lib
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        if hasattr(lib, name):
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+    _lib = lib
+
+
+def library_loaded() -> bool:
+    return not isinstance(_lib, _MissingLibrary)
+
+
+# The build step (paper_2604_12083_amd.build) imports this package before the
+# library exists; every entry point raises ImportError until it is built and
+# the package is reloaded.
+if os.path.exists(LIB_PATH):
+    _load_library()
 
 
 def declared_functions(header: str = HEADER):
