@@ -38,8 +38,15 @@
  *   non-finite scalar, a bad offsets array or an unknown enum value.
  *   MRS_ENOMEM: a device or host allocation failed.  MRS_EDEVICE: a HIP
  *   call failed (the context should then be destroyed).  MRS_ENUMERIC: a
- *   result that was checked came out non-finite.  mrs_last_error gives a
- *   message for the last failing call on the context.
+ *   result came out non-finite (an overflow, e.g. of the single-precision
+ *   source records of MRS_FP32C, or of a step): the reduction kernels raise
+ *   a flag when a velocity or updated position they write is not finite,
+ *   and calls that copy results to the host scan them.  It is returned by
+ *   mrs_eval_host, mrs_ensemble_eval/_step/_get, mrs_batch_step/_eval,
+ *   mrs_parareal(_pipelined) and by the server (result status); the
+ *   results are still written.  The asynchronous *_device calls cannot
+ *   report it.  mrs_last_error gives a message for the last failing call
+ *   on the context.
  * Threads and streams.  A context is not thread-safe.  Calls taking a
  *   `stream` (a hipStream_t passed as void*, NULL = the context stream)
  *   are asynchronous with respect to the host; all other calls return after
@@ -111,7 +118,13 @@ mrs_status mrs_eval_host(mrs_context *ctx, int64_t n, const double *X, const dou
                          const double *torque, double eps, double mu, mrs_precision prec,
                          double *U, double *Omega);
 
-/* Same on caller-owned device arrays (n x 3 each), queued on `stream`. */
+/* Same on caller-owned device arrays (n x 3 each), queued on `stream`.
+ * The evaluation scratch (source records, split-K partial sums, work list)
+ * belongs to the context: each call makes its stream wait for the end of
+ * the previous call's kernels (an event), so calls queued on different
+ * streams without a host synchronisation between them run one after the
+ * other on the device and each gives its own result.  The outputs are not
+ * checked for finiteness (the call returns before they exist). */
 mrs_status mrs_eval_device(mrs_context *ctx, int64_t n, const double *dX, const double *df,
                            const double *dtorque, double eps, double mu, mrs_precision prec,
                            double *dU, double *dOmega, void *stream);
@@ -153,6 +166,15 @@ mrs_status mrs_ensemble_create(mrs_context *ctx, int32_t n_fil, const int32_t *o
                                const mrs_rod_params *rod, mrs_ensemble **out);
 /* Replace the state (host arrays; either may be NULL to keep it). */
 mrs_status mrs_ensemble_set_state(mrs_ensemble *ens, const double *X, const double *D);
+/* Replace the external point force f_ext and torque n_ext exerted on the
+ * fluid at every point (Sec. II.C, Eq. superposition: the loads the MRS sum
+ * takes besides the rod's own forces), n x 3 host arrays in the caller's
+ * order, copied; NULL = zero.  They stay constant during later steps and
+ * are added to the elastic loads (or used alone with include_elastic = 0).
+ * Errors: MRS_EINVAL for a null ensemble or a non-finite value;
+ * MRS_ENOMEM if an ensemble created without loads cannot get their
+ * buffers. */
+mrs_status mrs_ensemble_set_external(mrs_ensemble *ens, const double *f_ext, const double *n_ext);
 /* Number of points. */
 mrs_status mrs_ensemble_size(const mrs_ensemble *ens, int64_t *n);
 /* Swimming (Sec. IV).  wave = (A, k, f), or NULL to switch it off: the

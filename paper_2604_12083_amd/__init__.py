@@ -110,6 +110,7 @@ _SIGS = {
     "mrs_ensemble_set_state": (_int, [_vp, _vp, _vp]),
     "mrs_ensemble_size": (_int, [_vp, ctypes.POINTER(_i64)]),
     "mrs_ensemble_set_swimming": (_int, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
+    "mrs_ensemble_set_external": (_int, [_vp, _vp, _vp]),
     "mrs_ensemble_set_time": (_int, [_vp, _dbl]),
     "mrs_ensemble_get_time": (_int, [_vp, ctypes.POINTER(_dbl)]),
     "mrs_ensemble_eval": (_int, [_vp, _int, _int]),
@@ -288,6 +289,13 @@ def mrs_ensemble_set_state(ctx, ens, X=None, D=None) -> None:
     _check(_lib.mrs_ensemble_set_state(ens, _ptr(X), _ptr(D)), ctx)
 
 
+def mrs_ensemble_set_external(ctx, ens, f_ext=None, n_ext=None) -> None:
+    """Replace the external point loads (n x 3 host arrays; None = zero)."""
+    fe = None if f_ext is None else _f64(f_ext, 3)
+    ne = None if n_ext is None else _f64(n_ext, 3)
+    _check(_lib.mrs_ensemble_set_external(ens, _ptr(fe), _ptr(ne)), ctx)
+
+
 def mrs_ensemble_size(ens) -> int:
     n = _i64()
     _check(_lib.mrs_ensemble_size(ens, ctypes.byref(n)))
@@ -394,11 +402,12 @@ def _server_out(n):
 
 
 def mrs_server_poll(srv, ticket, n):
-    """(status, info, (X, D, U, Omega)); outputs are None unless done with MRS_OK."""
+    """(status, info, (X, D, U, Omega)); outputs are None unless done with
+    MRS_OK or MRS_ENUMERIC (a result with non-finite values)."""
     info = mrs_result_info()
     X, D, U, W = _server_out(n)
     st = _lib.mrs_server_poll(srv, ctypes.c_uint64(ticket), ctypes.byref(info), _ptr(X), _ptr(D), _ptr(U), _ptr(W))
-    return st, info, ((X, D, U, W) if st == MRS_OK else None)
+    return st, info, ((X, D, U, W) if st in (MRS_OK, MRS_ENUMERIC) else None)
 
 
 def mrs_server_wait(srv, ticket, n, timeout_s=60.0):
@@ -406,7 +415,7 @@ def mrs_server_wait(srv, ticket, n, timeout_s=60.0):
     X, D, U, W = _server_out(n)
     st = _lib.mrs_server_wait(srv, ctypes.c_uint64(ticket), float(timeout_s), ctypes.byref(info), _ptr(X), _ptr(D),
                               _ptr(U), _ptr(W))
-    return st, info, ((X, D, U, W) if st == MRS_OK else None)
+    return st, info, ((X, D, U, W) if st in (MRS_OK, MRS_ENUMERIC) else None)
 
 
 def mrs_server_stats_get(srv):

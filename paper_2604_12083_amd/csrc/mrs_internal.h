@@ -69,6 +69,8 @@ struct EnsDesc {
     double *lj_box;         // per LJ source block: lo[3], hi[3] of its positions (with LJ)
     uint64_t *lj_mask;      // per aligned 64-point block: bit j set when point 64 b + j
                             // feels a LJ force (with LJ)
+    int32_t *nonfinite;     // set to 1 (plain vector store) by the reduction when a
+                            // result it writes is not finite; may be null
 };
 
 // Source blocks of the Lennard-Jones pass hold at most this many consecutive

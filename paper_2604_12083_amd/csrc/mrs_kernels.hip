@@ -470,6 +470,14 @@ __device__ __forceinline__ void rotate_frame(const double *din, double *__restri
     for (int k = 0; k < 9; k++) Dout[(size_t)k * N + i] = d[k];
 }
 
+// Raises the ensemble's non-finite flag when any of v[0..n) is not finite
+// (an ordinary vector store from the lanes that see one).
+__device__ __forceinline__ void check_finite(const EnsDesc &E, const double *v, int n) {
+    bool ok = true;
+    for (int k = 0; k < n; k++) ok = ok && isfinite(v[k]);
+    if (!ok && E.nonfinite) *E.nonfinite = 1;
+}
+
 // One block per kReducePoints points: the waves each sum a fixed share of
 // the split-K chunks for the block's points (lane = point), the parts are
 // combined through LDS in wave order, and wave 0 runs the epilogue.
@@ -529,6 +537,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(int stage, int scheme
     if ((EPI == EPI_EULER || EPI == EPI_RK_FINAL) && i == 0 && E.clock) *E.clock += dt;
     const double U[3] = {acc[0] * E.cU, acc[1] * E.cU, acc[2] * E.cU};
     const double W[3] = {acc[3] * E.cW, acc[4] * E.cW, acc[5] * E.cW};
+    const double UW[6] = {U[0], U[1], U[2], W[0], W[1], W[2]};
+    check_finite(E, UW, 6);
     if (EPI == EPI_WRITE) {
         if (E.aos_io) {
 #pragma unroll
@@ -540,12 +550,15 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(int stage, int scheme
         return;
     }
     if (EPI == EPI_EULER) {
+        double xn[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) {
+            xn[c] = xv[c] + dt * U[c];
             E.U[(size_t)c * N + i] = U[c];
             E.W[(size_t)c * N + i] = W[c];
-            E.X[(size_t)c * N + i] = xv[c] + dt * U[c];
+            E.X[(size_t)c * N + i] = xn[c];
         }
+        check_finite(E, xn, 3);
         rotate_frame(dv, E.D, N, i, dt * W[0], dt * W[1], dt * W[2], true);
         return;
     }
@@ -574,8 +587,13 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(int stage, int scheme
         }
         rotate_frame(dv, E.Ds, N, i, h * W[0], h * W[1], h * W[2], false);
     } else {
+        double xn[3];
 #pragma unroll
-        for (int c = 0; c < 3; c++) E.X[(size_t)c * N + i] = xv[c] + dt * ua[c];
+        for (int c = 0; c < 3; c++) {
+            xn[c] = xv[c] + dt * ua[c];
+            E.X[(size_t)c * N + i] = xn[c];
+        }
+        check_finite(E, xn, 3);
         rotate_frame(dv, E.D, N, i, dt * wa[0], dt * wa[1], dt * wa[2], true);
     }
 }

@@ -110,6 +110,7 @@ struct Solve {
         prec = p;
         el = include_elastic ? 1 : 0;
         N = E->N;
+        numeric_reset(ctx);
         W.assign(ns + 1, nullptr);
         for (int n = 0; n <= ns; n++) {
             mrs_status st = ensemble_clone(E, &W[n]);
@@ -176,11 +177,15 @@ struct Solve {
     }
 
     // The result: the last boundary state and its time into the ensemble.
-    mrs_status finish(const States &U, hipStream_t s) {
+    // MRS_ENUMERIC when a propagation produced a non-finite value (flag of
+    // the reduction kernels, cleared by init) or an increment was not finite.
+    mrs_status finish(const States &U, hipStream_t s, bool finite_increments) {
         if (copy_state(E->X.as<double>(), E->D.as<double>(), U.X(ns), U.D(ns), N, s) != hipSuccess ||
             set_clock(E, ns, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             return fail(ctx, MRS_EDEVICE, "parareal result copy");
-        return MRS_OK;
+        mrs_status st = numeric_check(ctx);
+        if (st == MRS_OK && !finite_increments) st = fail(ctx, MRS_ENUMERIC, "non-finite Parareal increment");
+        return st;
     }
 };
 
@@ -211,6 +216,7 @@ extern "C" mrs_status mrs_parareal(mrs_ensemble *E, int32_t ns, mrs_integrator f
     }
     std::vector<double> ha((size_t)3 * N), hb((size_t)3 * N);
     int done = 0;
+    bool finite_inc = true;
     for (int k = 1; k <= max_iter; k++) {
         // fine propagations of slices k..ns from the previous iterate, batched (Eq. intermediate)
         std::vector<mrs_ensemble *> batch;
@@ -247,11 +253,11 @@ extern "C" mrs_status mrs_parareal(mrs_ensemble *E, int32_t ns, mrs_integrator f
         std::swap(Go.buf.bytes, Gn.buf.bytes);
         if (history) history[k - 1] = inc;
         done = k;
+        finite_inc = finite_inc && std::isfinite(inc);
         if (!(inc > tol)) break;
     }
-    if ((st = S.finish(U, s)) != MRS_OK) return st;
     if (iters) *iters = done;
-    return MRS_OK;
+    return S.finish(U, s, finite_inc);
 }
 
 extern "C" mrs_status mrs_parareal_pipelined(mrs_ensemble *E, int32_t ns, mrs_integrator fi, double fdt,
@@ -340,6 +346,7 @@ extern "C" mrs_status mrs_parareal_pipelined(mrs_ensemble *E, int32_t ns, mrs_in
     }
     std::vector<double> ha((size_t)3 * N), hb((size_t)3 * N);
     int done = 0;
+    bool finite_inc = true;
     for (int k = 1; k <= max_iter; k++) {
         States &V = It[k & 1];
         const States &U = It[(k - 1) & 1];
@@ -373,11 +380,11 @@ extern "C" mrs_status mrs_parareal_pipelined(mrs_ensemble *E, int32_t ns, mrs_in
         }
         if (history) history[k - 1] = inc;
         done = k;
+        finite_inc = finite_inc && std::isfinite(inc);
         if (!(inc > tol)) break;
     }
     for (int i = 0; i < n_sf; i++)
         if (hipStreamSynchronize(sf[i]) != hipSuccess) return fail(ctx, MRS_EDEVICE, "parareal fine stream");
-    if ((st = S.finish(It[done & 1], sc)) != MRS_OK) return st;
     if (iters) *iters = done;
-    return MRS_OK;
+    return S.finish(It[done & 1], sc, finite_inc);
 }

@@ -26,6 +26,24 @@ mrs_status fail(mrs_context *ctx, mrs_status st, const char *fmt, ...) {
     return st;
 }
 
+void numeric_reset(mrs_context *ctx) {
+    if (ctx->flag_host) *reinterpret_cast<volatile int32_t *>(ctx->flag_host) = 0;
+}
+
+mrs_status numeric_check(mrs_context *ctx) {
+    if (ctx->flag_host && *reinterpret_cast<volatile int32_t *>(ctx->flag_host) != 0) {
+        numeric_reset(ctx);
+        return fail(ctx, MRS_ENUMERIC, "a result came out non-finite");
+    }
+    return MRS_OK;
+}
+
+mrs_status check_host_finite(mrs_context *ctx, const double *p, size_t n, const char *what) {
+    for (size_t i = 0; i < n; i++)
+        if (!std::isfinite(p[i])) return fail(ctx, MRS_ENUMERIC, "non-finite %s at %zu", what, i);
+    return MRS_OK;
+}
+
 Plan::~Plan() {
     for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
 }
@@ -117,6 +135,7 @@ static EnsDesc ensemble_desc(mrs_ensemble *E, int prec, const PairCfg &c) {
     d.lj_blk = E->has_lj ? E->lj_blk.as<int32_t>() : nullptr;
     d.lj_box = E->has_lj ? E->lj_box.as<double>() : nullptr;
     d.lj_mask = E->has_lj ? E->lj_mask.as<uint64_t>() : nullptr;
+    d.nonfinite = E->ctx->flag_dev;
     return d;
 }
 
@@ -413,11 +432,21 @@ mrs_status mrs_context_create(int device, mrs_context **out) {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         ctx->n_cu = ncu;
+    void *flag = nullptr;
     if (hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->stage_event, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ctx->stage_event, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->eval_done, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc(&flag, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer(reinterpret_cast<void **>(&ctx->flag_dev), flag, 0) != hipSuccess) {
+        if (flag) (void)hipHostFree(flag);
+        if (ctx->eval_done) (void)hipEventDestroy(ctx->eval_done);
+        if (ctx->stage_event) (void)hipEventDestroy(ctx->stage_event);
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
         delete ctx;
         return MRS_EDEVICE;
     }
+    ctx->flag_host = static_cast<int32_t *>(flag);
+    *ctx->flag_host = 0;
     ctx->stream = ctx->own_stream;
     *out = ctx;
     return MRS_OK;
@@ -440,6 +469,8 @@ void mrs_context_destroy(mrs_context *ctx) {
     for (auto ev : ctx->event_pool) (void)hipEventDestroy(ev);
     if (ctx->stage_host) (void)hipHostFree(ctx->stage_host);
     if (ctx->stage_event) (void)hipEventDestroy(ctx->stage_event);
+    if (ctx->eval_done) (void)hipEventDestroy(ctx->eval_done);
+    if (ctx->flag_host) (void)hipHostFree(ctx->flag_host);
     ctx->eval_rec.release();
     ctx->eval_part.release();
     ctx->eval_desc.release();
@@ -466,23 +497,39 @@ mrs_status mrs_context_synchronize(mrs_context *ctx) {
     return MRS_OK;
 }
 
-// One-shot evaluation on caller device arrays (AoS n x 3).
-mrs_status mrs_eval_device(mrs_context *ctx, int64_t n, const double *dX, const double *df,
-                           const double *dt, double eps, double mu, mrs_precision prec, double *dU,
-                           double *dW, void *stream) {
-    CHECK_CTX(ctx);
+}  // extern "C"
+
+namespace mrs {
+
+// Device memory of one one-shot evaluation besides its inputs and outputs:
+// source records, split-K partial sums, and the descriptor + work lists.
+struct EvalScratch {
+    void *rec = nullptr;
+    double *part = nullptr;
+    char *items = nullptr;
+};
+
+// Work lists and descriptor of one evaluation, laid out for one upload:
+// [desc][split][tile1][tile2][pts], each part 256-byte aligned.
+struct EvalLayout {
+    Plan P;
+    EnsDesc d{};
+    std::vector<char> blob;
+    size_t o_desc = 0, o_split = 0, o_t1 = 0, o_t2 = 0, o_pts = 0;
+};
+
+static mrs_status eval_args(mrs_context *ctx, int64_t n, const double *dX, const double *df, const double *dt,
+                            double eps, double mu, mrs_precision prec, const double *dU, const double *dW) {
     if (n < 0 || n > INT32_MAX / 8) return fail(ctx, MRS_EINVAL, "n out of range (%lld)", (long long)n);
     if (!finite_pos(eps) || !finite_pos(mu)) return fail(ctx, MRS_EINVAL, "eps and mu must be finite and > 0");
     if (prec != MRS_FP64 && prec != MRS_FP32C) return fail(ctx, MRS_EINVAL, "unknown precision %d", (int)prec);
-    if (n == 0) return MRS_OK;
-    if (!dX || !df || !dt || !dU || !dW) return fail(ctx, MRS_EINVAL, "null array");
-    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    hipStream_t s = pick_stream(ctx, stream);
-    const int p = (int)prec;
-    PairCfg c = choose_cfg(ctx, n, p);
-    HIPCHK(ctx, ctx->eval_rec.reserve((size_t)n * sizeof(RecF64)));
-    HIPCHK(ctx, ctx->eval_part.reserve((size_t)c.K * 6 * (size_t)n * sizeof(double)));
-    EnsDesc d{};
+    if (n > 0 && (!dX || !df || !dt || !dU || !dW)) return fail(ctx, MRS_EINVAL, "null array");
+    return MRS_OK;
+}
+
+static void eval_layout(EvalLayout &L, int64_t n, const double *dX, const double *df, const double *dt, double eps,
+                        double mu, int p, double *dU, double *dW, const PairCfg &c, const EvalScratch &sc) {
+    EnsDesc &d = L.d;
     d.N = (int32_t)n;
     d.K = c.K;
     d.aos_io = 1;
@@ -491,54 +538,95 @@ mrs_status mrs_eval_device(mrs_context *ctx, int64_t n, const double *dX, const 
     d.next = dt;
     d.U = dU;
     d.W = dW;
-    d.rec = ctx->eval_rec.p;
-    d.part = ctx->eval_part.as<double>();
+    d.rec = sc.rec;
+    d.part = sc.part;
     d.eps = eps;
     d.inv_eps = 1.0 / eps;
     d.mu = mu;
     d.cU = 1.0 / (8.0 * kPi * mu);
     d.cW = p == MRS_FP32C ? 1.0 / (8.0 * kPi * mu * eps) : d.cU;
-    Plan P;
-    P.prec = p;
-    add_items(P, 0, n, 0, c);
-    order_items(P);
-    // desc + items in one upload: [desc][split][tile1][tile2][pts]
-    std::vector<char> blob;
+    L.P.prec = p;
+    add_items(L.P, 0, n, 0, c);
+    order_items(L.P);
     auto put = [&](const void *src, size_t bytes) {
-        size_t off = (blob.size() + 255) & ~size_t(255);
-        blob.resize(off + bytes);
-        if (bytes) std::memcpy(blob.data() + off, src, bytes);
+        size_t off = (L.blob.size() + 255) & ~size_t(255);
+        L.blob.resize(off + bytes);
+        if (bytes) std::memcpy(L.blob.data() + off, src, bytes);
         return off;
     };
-    size_t o_desc = put(&d, sizeof d);
-    size_t o_split = put(P.split.data(), P.split.size() * sizeof(PairItem));
-    size_t o_t1 = put(P.tile1.data(), P.tile1.size() * sizeof(PairItem));
-    size_t o_t2 = put(P.tile2.data(), P.tile2.size() * sizeof(PairItem));
-    size_t o_pts = put(P.pts.data(), P.pts.size() * sizeof(PointItem));
-    HIPCHK(ctx, ctx->eval_items.reserve(blob.size()));
-    HIPCHK(ctx, upload(ctx, ctx->eval_items.p, blob.data(), blob.size(), s));
-    char *base = ctx->eval_items.as<char>();
-    const EnsDesc *dd = reinterpret_cast<const EnsDesc *>(base + o_desc);
-    HIPCHK(ctx, timed(ctx, "pack_aos", s, [&] { return launch_pack_aos(p, dd, d, s); }));
-    if (!P.split.empty())
-        HIPCHK(ctx, timed(ctx, pair_name(p, PAIR_SPLIT), s, [&] {
-            return launch_pairs(p, PAIR_SPLIT, 1, dd, reinterpret_cast<const PairItem *>(base + o_split),
+    L.o_desc = put(&d, sizeof d);
+    L.o_split = put(L.P.split.data(), L.P.split.size() * sizeof(PairItem));
+    L.o_t1 = put(L.P.tile1.data(), L.P.tile1.size() * sizeof(PairItem));
+    L.o_t2 = put(L.P.tile2.data(), L.P.tile2.size() * sizeof(PairItem));
+    L.o_pts = put(L.P.pts.data(), L.P.pts.size() * sizeof(PointItem));
+}
+
+// Queue the kernels of an evaluation whose blob is on the device at `base`.
+static hipError_t eval_launch(mrs_context *ctx, const EvalLayout &L, int p, const char *base, hipStream_t s) {
+    const Plan &P = L.P;
+    const EnsDesc *dd = reinterpret_cast<const EnsDesc *>(base + L.o_desc);
+    hipError_t e = timed(ctx, "pack_aos", s, [&] { return launch_pack_aos(p, dd, L.d, s); });
+    if (e == hipSuccess && !P.split.empty())
+        e = timed(ctx, pair_name(p, PAIR_SPLIT), s, [&] {
+            return launch_pairs(p, PAIR_SPLIT, 1, dd, reinterpret_cast<const PairItem *>(base + L.o_split),
                                 (int)P.split.size(), s);
-        }));
-    if (!P.tile1.empty())
-        HIPCHK(ctx, timed(ctx, pair_name(p, PAIR_TILE), s, [&] {
-            return launch_pairs(p, PAIR_TILE, 1, dd, reinterpret_cast<const PairItem *>(base + o_t1),
+        });
+    if (e == hipSuccess && !P.tile1.empty())
+        e = timed(ctx, pair_name(p, PAIR_TILE), s, [&] {
+            return launch_pairs(p, PAIR_TILE, 1, dd, reinterpret_cast<const PairItem *>(base + L.o_t1),
                                 (int)P.tile1.size(), s);
-        }));
-    if (!P.tile2.empty())
-        HIPCHK(ctx, timed(ctx, pair_name(p, PAIR_TILE), s, [&] {
-            return launch_pairs(p, PAIR_TILE, 2, dd, reinterpret_cast<const PairItem *>(base + o_t2),
+        });
+    if (e == hipSuccess && !P.tile2.empty())
+        e = timed(ctx, pair_name(p, PAIR_TILE), s, [&] {
+            return launch_pairs(p, PAIR_TILE, 2, dd, reinterpret_cast<const PairItem *>(base + L.o_t2),
                                 (int)P.tile2.size(), s);
-        }));
-    HIPCHK(ctx, timed(ctx, "reduce_write", s, [&] {
-        return launch_reduce(EPI_WRITE, 0, 0, 0.0, dd, reinterpret_cast<const PointItem *>(base + o_pts),
-                             (int)P.pts.size(), s);
-    }));
+        });
+    if (e == hipSuccess)
+        e = timed(ctx, "reduce_write", s, [&] {
+            return launch_reduce(EPI_WRITE, 0, 0, 0.0, dd, reinterpret_cast<const PointItem *>(base + L.o_pts),
+                                 (int)P.pts.size(), s);
+        });
+    return e;
+}
+
+}  // namespace mrs
+
+extern "C" {
+
+// One-shot evaluation on caller device arrays (AoS n x 3).
+mrs_status mrs_eval_device(mrs_context *ctx, int64_t n, const double *dX, const double *df,
+                           const double *dt, double eps, double mu, mrs_precision prec, double *dU,
+                           double *dW, void *stream) {
+    CHECK_CTX(ctx);
+    mrs_status st = eval_args(ctx, n, dX, df, dt, eps, mu, prec, dU, dW);
+    if (st != MRS_OK || n == 0) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    hipStream_t s = pick_stream(ctx, stream);
+    const int p = (int)prec;
+    PairCfg c = choose_cfg(ctx, n, p);
+    // the scratch below is shared by every evaluation of the context: this
+    // one waits on its stream for the previous one (any stream) to finish,
+    // and growing a buffer (which frees the old one) first waits on the host
+    const size_t rec_bytes = (size_t)n * sizeof(RecF64);
+    const size_t part_bytes = (size_t)c.K * 6 * (size_t)n * sizeof(double);
+    if (ctx->eval_pending) {
+        if (rec_bytes > ctx->eval_rec.bytes || part_bytes > ctx->eval_part.bytes)
+            HIPCHK(ctx, hipEventSynchronize(ctx->eval_done));
+        HIPCHK(ctx, hipStreamWaitEvent(s, ctx->eval_done, 0));
+    }
+    HIPCHK(ctx, ctx->eval_rec.reserve(rec_bytes));
+    HIPCHK(ctx, ctx->eval_part.reserve(part_bytes));
+    EvalScratch sc;
+    sc.rec = ctx->eval_rec.p;
+    sc.part = ctx->eval_part.as<double>();
+    EvalLayout L;
+    eval_layout(L, n, dX, df, dt, eps, mu, p, dU, dW, c, sc);
+    if (ctx->eval_pending && L.blob.size() > ctx->eval_items.bytes) HIPCHK(ctx, hipEventSynchronize(ctx->eval_done));
+    HIPCHK(ctx, ctx->eval_items.reserve(L.blob.size()));
+    HIPCHK(ctx, upload(ctx, ctx->eval_items.p, L.blob.data(), L.blob.size(), s));
+    HIPCHK(ctx, eval_launch(ctx, L, p, ctx->eval_items.as<char>(), s));
+    HIPCHK(ctx, hipEventRecord(ctx->eval_done, s));
+    ctx->eval_pending = true;
     return MRS_OK;
 }
 
@@ -851,6 +939,28 @@ mrs_status mrs_ensemble_set_swimming(mrs_ensemble *E, const double *wave, const 
     return MRS_OK;
 }
 
+mrs_status mrs_ensemble_set_external(mrs_ensemble *E, const double *f_ext, const double *n_ext) {
+    if (!E) return MRS_EINVAL;
+    mrs_context *ctx = E->ctx;
+    const int64_t n = E->N;
+    if ((f_ext && !all_finite(f_ext, 3 * n)) || (n_ext && !all_finite(n_ext, 3 * n)))
+        return fail(ctx, MRS_EINVAL, "non-finite external load");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (!E->has_ext) {
+        if (!f_ext && !n_ext) return MRS_OK;  // the loads stay zero
+        const size_t v3 = (size_t)n * 3 * sizeof(double);
+        if (E->fext.reserve(v3) != hipSuccess || E->next.reserve(v3) != hipSuccess)
+            return fail(ctx, MRS_ENOMEM, "external load buffers (%lld points)", (long long)n);
+        E->has_ext = true;
+        invalidate_plans(E);  // the descriptors gain the load arrays
+    }
+    std::vector<double> z(f_ext && n_ext ? 0 : (size_t)3 * n, 0.0);
+    mrs_status st;
+    if ((st = put_soa(ctx, E->fext, f_ext ? f_ext : z.data(), n, 3, E->perm)) != MRS_OK) return st;
+    return put_soa(ctx, E->next, n_ext ? n_ext : z.data(), n, 3, E->perm);
+}
+
 mrs_status mrs_ensemble_set_time(mrs_ensemble *E, double t) {
     if (!E) return MRS_EINVAL;
     mrs_context *ctx = E->ctx;
@@ -878,9 +988,10 @@ mrs_status mrs_ensemble_eval(mrs_ensemble *E, mrs_precision prec, int include_el
     Plan *P;
     mrs_status st = ensemble_plan(E, (int)prec, &P);
     if (st != MRS_OK) return st;
+    numeric_reset(ctx);
     HIPCHK(ctx, run_stage(ctx, *P, 0, include_elastic ? 1 : 0, EPI_WRITE, 0, 0, 0.0, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    return MRS_OK;
+    return numeric_check(ctx);
 }
 
 static mrs_status check_step_args(mrs_context *ctx, mrs_integrator integ, double dt, int32_t nsteps,
@@ -902,9 +1013,10 @@ mrs_status mrs_ensemble_step(mrs_ensemble *E, mrs_integrator integ, double dt, i
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     Plan *P;
     if ((st = ensemble_plan(E, (int)prec, &P)) != MRS_OK) return st;
+    numeric_reset(ctx);
     HIPCHK(ctx, queue_steps(ctx, *P, (int)integ, dt, nsteps, include_elastic ? 1 : 0, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    return MRS_OK;
+    return numeric_check(ctx);
 }
 
 mrs_status mrs_ensemble_get(mrs_ensemble *E, double *X, double *D, double *U, double *W) {
@@ -915,12 +1027,14 @@ mrs_status mrs_ensemble_get(mrs_ensemble *E, double *X, double *D, double *U, do
     const int64_t n = E->N;
     std::vector<double> tmp((size_t)n * 9);
     struct { double *dst; DevBuf *src; int w; } outs[4] = {{X, &E->X, 3}, {D, &E->D, 9}, {U, &E->U, 3}, {W, &E->W, 3}};
+    mrs_status st = MRS_OK;
     for (auto &o : outs) {
         if (!o.dst) continue;
         HIPCHK(ctx, hipMemcpy(tmp.data(), o.src->p, (size_t)n * o.w * sizeof(double), hipMemcpyDeviceToHost));
         soa_to_aos(tmp.data(), o.dst, n, o.w, E->perm);
+        if (st == MRS_OK) st = check_host_finite(ctx, tmp.data(), (size_t)n * o.w, "state or velocity");
     }
-    return MRS_OK;
+    return st;
 }
 
 void mrs_ensemble_destroy(mrs_ensemble *E) {
@@ -1020,11 +1134,12 @@ mrs_status mrs_batch_step(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *
     if (st != MRS_OK) return st;
     if ((st = check_step_args(ctx, integ, dt, nsteps, prec)) != MRS_OK) return st;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    numeric_reset(ctx);
     st = batch_enqueue(ctx, n_ens, ens, (int)integ, dt, nsteps, (int)prec, include_elastic ? 1 : 0, use_graph,
                        ctx->stream);
     if (st != MRS_OK) return st;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    return MRS_OK;
+    return numeric_check(ctx);
 }
 
 mrs_status mrs_batch_eval(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *ens, mrs_precision prec,
@@ -1036,9 +1151,10 @@ mrs_status mrs_batch_eval(mrs_context *ctx, int32_t n_ens, mrs_ensemble *const *
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     Plan *P;
     if ((st = batch_plan(ctx, n_ens, ens, (int)prec, &P)) != MRS_OK) return st;
+    numeric_reset(ctx);
     HIPCHK(ctx, run_stage(ctx, *P, 0, include_elastic ? 1 : 0, EPI_WRITE, 0, 0, 0.0, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    return MRS_OK;
+    return numeric_check(ctx);
 }
 
 // ---- profiling

@@ -90,6 +90,16 @@ struct mrs_context {
     // scratch of the one-shot evaluation
     mrs::DevBuf eval_rec, eval_part, eval_desc, eval_items, eval_rod;
     mrs::DevBuf eval_io;  // mrs_eval_host's device copies of X, f, n, U, Omega (grow-only)
+    // non-finite flag raised by the reduction kernels of every ensemble of the
+    // context: one int32 in pinned, device-mapped host memory (flag_host is its
+    // host address, flag_dev the address the kernels write)
+    int32_t *flag_host = nullptr;
+    int32_t *flag_dev = nullptr;
+    // end of the last one-shot evaluation (mrs_eval_device / mrs_eval_host),
+    // recorded on its stream: the next one waits for it before it reuses the
+    // evaluation scratch, whatever stream it is queued on
+    hipEvent_t eval_done = nullptr;
+    bool eval_pending = false;
     // pinned staging for small uploads, reused after its event completes
     void *stage_host = nullptr;
     size_t stage_bytes = 0;
@@ -135,6 +145,13 @@ namespace mrs {
 
 // Error helpers
 mrs_status fail(mrs_context *ctx, mrs_status st, const char *fmt, ...);
+// Clear the context's non-finite flag before queuing work whose results are
+// checked; after that work has finished, numeric_check returns MRS_ENUMERIC
+// (and clears the flag) if a reduction kernel raised it.
+void numeric_reset(mrs_context *ctx);
+mrs_status numeric_check(mrs_context *ctx);
+// MRS_ENUMERIC if any of p[0..n) is not finite.
+mrs_status check_host_finite(mrs_context *ctx, const double *p, size_t n, const char *what);
 mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out);
 void add_items(Plan &P, int e, int64_t N, int n_fil, const PairCfg &c);
 // Lennard-Jones blocks of ensemble e of plan P when it has the repulsion on.

@@ -266,8 +266,9 @@ void create_ensembles(mrs_server *S, std::vector<Request *> &pick) {
     }
 }
 
-// Copy results of a finished request to host and free its device state.
-// Caller holds the context lock only.
+// Copy results of a finished request to host and free its device state;
+// a result with a non-finite value completes with MRS_ENUMERIC.  Caller
+// holds the context lock only.
 void collect(Request *r, mrs_status status) {
     if (status == MRS_OK && r->ens) {
         r->Xo.resize((size_t)r->N * 3);
@@ -375,7 +376,8 @@ void loop(mrs_server *S) {
 mrs_status copy_out(Request *r, mrs_result_info *info, double *X, double *D, double *U, double *W) {
     if (info) *info = r->info;
     const size_t n = (size_t)r->N;
-    if (r->info.status == MRS_OK) {
+    // a non-finite result is still returned, with status MRS_ENUMERIC
+    if (r->info.status == MRS_OK || r->info.status == MRS_ENUMERIC) {
         if (X) std::memcpy(X, r->Xo.data(), n * 3 * sizeof(double));
         if (D) std::memcpy(D, r->Do.data(), n * 9 * sizeof(double));
         if (U) std::memcpy(U, r->Uo.data(), n * 3 * sizeof(double));
