@@ -129,6 +129,24 @@ mrs_status mrs_eval_device(mrs_context *ctx, int64_t n, const double *dX, const 
                            const double *dtorque, double eps, double mu, mrs_precision prec,
                            double *dU, double *dOmega, void *stream);
 
+/* mrs_eval_device for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, layouts, ordering and results, but the source records,
+ * split-K partial sums and work list live in a static device array of
+ * 64 MiB that the library holds on every device it runs on until the
+ * process ends (its address is taken when a context is created on the
+ * device); the call allocates no device or pinned host memory.  It serves at
+ * most 500,000 points (MRS_EINVAL beyond, with a message); when the default
+ * decomposition's partial sums do not fit, it uses fewer, longer source
+ * chunks (same results up to the rounding of the split-K sum).  Nothing in
+ * the array needs to start at zero; it keeps the last call's contents.  All
+ * calls on one device share the array: calls of one context are ordered by
+ * its evaluation event whatever their streams, but calls of different
+ * contexts that overlap on the device race and give wrong results. */
+mrs_status mrs_eval_device_noalloc(mrs_context *ctx, int64_t n, const double *dX, const double *df,
+                                   const double *dtorque, double eps, double mu, mrs_precision prec,
+                                   double *dU, double *dOmega, void *stream);
+
 /* ---- rod mechanics (Sec. II.B, Alg. 1, Sec. III.B.1) ------------------- */
 
 /* Point force g and torque m exerted on the fluid by every node:

@@ -102,6 +102,7 @@ _SIGS = {
     "mrs_context_synchronize": (_int, [_vp]),
     "mrs_eval_host": (_int, [_vp, _i64, _vp, _vp, _vp, _dbl, _dbl, _int, _vp, _vp]),
     "mrs_eval_device": (_int, [_vp, _i64, _vp, _vp, _vp, _dbl, _dbl, _int, _vp, _vp, _vp]),
+    "mrs_eval_device_noalloc": (_int, [_vp, _i64, _vp, _vp, _vp, _dbl, _dbl, _int, _vp, _vp, _vp]),
     "mrs_rod_forces_device": (_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.POINTER(mrs_rod_params), _vp, _vp,
                                      _vp, _vp, _vp]),
     "mrs_rotsqrt_device": (_int, [_vp, _i64, _vp, _vp, _vp]),
@@ -260,6 +261,11 @@ def mrs_eval_host(ctx, X, f, n, eps, mu=1.0, prec=MRS_FP64):
 def mrs_eval_device(ctx, n_points, dX, df, dn, eps, mu, prec, dU, dW, stream=None) -> None:
     _check(_lib.mrs_eval_device(ctx, int(n_points), _ptr(dX), _ptr(df), _ptr(dn), float(eps), float(mu), int(prec),
                                 _ptr(dU), _ptr(dW), _stream(stream)), ctx)
+
+
+def mrs_eval_device_noalloc(ctx, n_points, dX, df, dn, eps, mu, prec, dU, dW, stream=None) -> None:
+    _check(_lib.mrs_eval_device_noalloc(ctx, int(n_points), _ptr(dX), _ptr(df), _ptr(dn), float(eps), float(mu),
+                                        int(prec), _ptr(dU), _ptr(dW), _stream(stream)), ctx)
 
 
 def mrs_rod_forces_device(ctx, offsets, dX, dD, rod, dfext, dnext, dg, dm, stream=None) -> None:

@@ -398,6 +398,47 @@ mrs_status ensemble_clone(mrs_ensemble *S, mrs_ensemble **out) {
 
 }  // namespace mrs
 
+// ------------------------------------------- scratch of the no-alloc entry
+
+namespace mrs {
+
+// Device scratch of mrs_eval_device_noalloc, for callers that cannot
+// allocate (code under graph capture, serving loops, harnesses that forbid
+// hipMalloc): the evaluation's work list, source records and split-K
+// partial sums live in this file-scope array, one copy per device, held
+// until the process ends.  Host code never passes the array's name: its
+// device address comes from hipGetSymbolAddress once per device, at context
+// creation with that device current, and is kept in g_scratch[device].
+constexpr size_t kNoallocBytes = size_t(64) << 20;
+constexpr size_t kNoallocListBytes = size_t(1) << 20;  // descriptor + work lists
+constexpr int64_t kNoallocMaxPoints = 500000;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch[kMaxDevices];
+
+// Address of this device's scratch (the current device must be `device`).
+static hipError_t scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return hipSuccess;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch[device] = ptr;
+    return hipSuccess;
+}
+
+static void *scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[device];
+}
+
+}  // namespace mrs
+
 // ------------------------------------------------------------------ C ABI
 
 #define CHECK_CTX(ctx)                                   \
@@ -429,6 +470,10 @@ mrs_status mrs_context_create(int device, mrs_context **out) {
     auto *ctx = new (std::nothrow) mrs_context();
     if (!ctx) return MRS_ENOMEM;
     ctx->device = device;
+    if (scratch_init(device) != hipSuccess) {
+        delete ctx;
+        return MRS_EDEVICE;
+    }
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         ctx->n_cu = ncu;
@@ -625,6 +670,55 @@ mrs_status mrs_eval_device(mrs_context *ctx, int64_t n, const double *dX, const 
     HIPCHK(ctx, ctx->eval_items.reserve(L.blob.size()));
     HIPCHK(ctx, upload(ctx, ctx->eval_items.p, L.blob.data(), L.blob.size(), s));
     HIPCHK(ctx, eval_launch(ctx, L, p, ctx->eval_items.as<char>(), s));
+    HIPCHK(ctx, hipEventRecord(ctx->eval_done, s));
+    ctx->eval_pending = true;
+    return MRS_OK;
+}
+
+mrs_status mrs_eval_device_noalloc(mrs_context *ctx, int64_t n, const double *dX, const double *df,
+                                   const double *dt, double eps, double mu, mrs_precision prec, double *dU,
+                                   double *dW, void *stream) {
+    CHECK_CTX(ctx);
+    mrs_status st = eval_args(ctx, n, dX, df, dt, eps, mu, prec, dU, dW);
+    if (st != MRS_OK || n == 0) return st;
+    if (n > kNoallocMaxPoints)
+        return fail(ctx, MRS_EINVAL, "n = %lld exceeds the %lld points of the allocation-free evaluation's scratch",
+                    (long long)n, (long long)kNoallocMaxPoints);
+    char *base = static_cast<char *>(scratch_ptr(ctx->device));
+    if (!base) return fail(ctx, MRS_EDEVICE, "no scratch address for device %d", ctx->device);
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    hipStream_t s = pick_stream(ctx, stream);
+    const int p = (int)prec;
+    // [descriptor + work lists | source records | partial sums]: the records
+    // take the FP64 size in both precisions; the partials take the rest, and
+    // a configuration whose source chunks need more gets fewer, longer chunks
+    const size_t rec_off = kNoallocListBytes;
+    const size_t part_off = rec_off + (((size_t)n * sizeof(RecF64) + 255) & ~size_t(255));
+    const size_t per_chunk = (size_t)n * 6 * sizeof(double);
+    const int64_t k_room = (int64_t)((kNoallocBytes - part_off) / per_chunk);
+    PairCfg c = choose_cfg(ctx, n, p);
+    if (c.K > k_room) {
+        PairCfg t;
+        t.mode = c.mode;
+        t.tpl = c.tpl;
+        t.K = (int)k_room;
+        c = choose_cfg_for(&t, n, p, ctx->n_cu);
+    }
+    if (c.K < 1 || c.K > k_room) return fail(ctx, MRS_EINVAL, "partial sums of %lld points exceed the scratch", (long long)n);
+    EvalScratch sc;
+    sc.rec = base + rec_off;
+    sc.part = reinterpret_cast<double *>(base + part_off);
+    sc.items = base;
+    EvalLayout L;
+    eval_layout(L, n, dX, df, dt, eps, mu, p, dU, dW, c, sc);
+    if (L.blob.size() > kNoallocListBytes)
+        return fail(ctx, MRS_EINVAL, "work list of %lld points exceeds the scratch", (long long)n);
+    // calls of this context on different streams run in order (as in
+    // mrs_eval_device); calls of other contexts on this device race
+    if (ctx->eval_pending) HIPCHK(ctx, hipStreamWaitEvent(s, ctx->eval_done, 0));
+    // pageable source: the call returns once the list has been staged
+    HIPCHK(ctx, hipMemcpyAsync(base, L.blob.data(), L.blob.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, eval_launch(ctx, L, p, base, s));
     HIPCHK(ctx, hipEventRecord(ctx->eval_done, s));
     ctx->eval_pending = true;
     return MRS_OK;
