@@ -6,6 +6,12 @@ all-pairs MRS sum of U and Omega, and the fixed-order FP64 reduction fused
 with the position/frame update.  The headline workload is 100 filaments x
 128 points (12,800 points); its value is pair interactions per second of the
 FP32-compensated path, with the FP64 path measured the same way beside it.
+The default run adds two legs to the same line: one-shot evaluations of the
+1,000-filament, 256,000-point ensemble in both precisions (pair-kernel
+roofline from its own events; max relative error on its 2,048-target check
+subset from the CPU leg) and 16 fine-propagator slices of 3,200 points
+advanced by RK4 steps as one batched graph launch against one launch per
+kernel per slice.
 
 Prints ONE JSON line.  --gpus N > 1 is not supported (one GPU per run).
 """
@@ -89,9 +95,14 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+SETTLE_S = 0.5  # untimed steps before the warm-up, so that the shader clock has settled
+
+
 def measure(mrs, ctx, e, prec, steps, warmup, dt, integ=None, swim=None):
     """Timed eager steps; HIP events on the launch stream bracket the
-    dominant pair kernel inside the timed region."""
+    dominant pair kernel inside the timed region.  Before the warm-up, untimed
+    steps run for SETTLE_S seconds (the clock of a fresh process ramps up
+    over the first launches)."""
     import torch
 
     integ = mrs.MRS_EULER if integ is None else integ
@@ -101,6 +112,14 @@ def measure(mrs, ctx, e, prec, steps, warmup, dt, integ=None, swim=None):
     if swim is not None:
         mrs.mrs_ensemble_set_swimming(ctx, ens, swim.wave, swim.lj)
     try:
+        t_settle = time.perf_counter()
+        settle_steps = 0
+        while time.perf_counter() - t_settle < SETTLE_S:
+            mrs.mrs_ensemble_step(ctx, ens, integ, dt, 5, prec, True)
+            settle_steps += 5
+        settle_s = time.perf_counter() - t_settle
+        mrs.mrs_ensemble_set_state(ctx, ens, e.X, e.D)
+        mrs.mrs_ensemble_set_time(ctx, ens, 0.0)
         mrs.mrs_ensemble_step(ctx, ens, integ, dt, warmup, prec, True)
         # latency of single synchronous steps
         lat = []
@@ -116,6 +135,7 @@ def measure(mrs, ctx, e, prec, steps, warmup, dt, integ=None, swim=None):
         mrs.mrs_profile_reset(ctx)
         mrs.mrs_profile_select(ctx, kname)
         mrs.mrs_profile_enable(ctx, True)
+        clock_before = mrs.mrs_profile_clock(ctx)
         torch.cuda.synchronize()
         mrs.mrs_context_synchronize(ctx)
         t0 = time.perf_counter()
@@ -123,6 +143,7 @@ def measure(mrs, ctx, e, prec, steps, warmup, dt, integ=None, swim=None):
         mrs.mrs_context_synchronize(ctx)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        clock_after = mrs.mrs_profile_clock(ctx)
         mrs.mrs_profile_enable(ctx, False)
         n_k, ms_k = mrs.mrs_profile_query(ctx, kname)
         # every kernel of the step, from a short untimed pass
@@ -145,6 +166,9 @@ def measure(mrs, ctx, e, prec, steps, warmup, dt, integ=None, swim=None):
         wall_graph = time.perf_counter() - t0
         Xg, Dg, _, _ = mrs.mrs_ensemble_get(ctx, ens)
         return {
+            "settle_s": settle_s,
+            "settle_steps": settle_steps,
+            "clock_mhz": {"before": round(clock_before, 1), "after": round(clock_after, 1)},
             "wall_s": wall,
             "wall_graph_s": wall_graph,
             "lat_ms": lat,
@@ -252,6 +276,63 @@ def roofline(pairs_per_launch, avg_s, peak_tflops, traffic=None):
     ach = FLOPS_PER_PAIR * pairs_per_launch / avg_s / 1e12
     return {"bound": "alu", "achieved": round(ach, 3), "peak": peak_tflops, "unit": "TFLOP/s",
             "frac": round(ach / peak_tflops, 4), "traffic": traffic}
+
+
+def bench_large(mrs, ctx, reps32=3, reps64=2):
+    """One-shot U, Omega evaluations (rod forces + MRS sum + reduction) of the
+    256,000-point ensemble, FP32C then FP64, with HIP events around the pair
+    kernel; returns the leg's summary and the GPU results on the seeded
+    2,048-target check subset (compared with the oracle in the CPU leg)."""
+    import synth
+
+    e = synth.ens256000()
+    idx = synth.ens256000_subset(e.N)
+    rod = mrs.rod_params(*(getattr(e.rod(), k) for k in ("a", "b", "omega0", "ds")))
+    ens = mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod)
+    out, subset = {"n_points": e.N, "pairs_per_eval": e.N * e.N}, {}
+    try:
+        for prec, tag, reps, peak in ((mrs.MRS_FP32C, "fp32c", reps32, PEAK_FP32_TFLOPS),
+                                      (mrs.MRS_FP64, "fp64", reps64, PEAK_FP64_TFLOPS)):
+            log(f"large ensemble {tag}: {reps} evaluations of {e.N} points")
+            mrs.mrs_ensemble_eval(ctx, ens, prec, True)  # plan and warm-up
+            kname = "pairs_tile_f32c" if prec == mrs.MRS_FP32C else "pairs_tile_f64"
+            mrs.mrs_profile_reset(ctx)
+            mrs.mrs_profile_select(ctx, kname)
+            mrs.mrs_profile_enable(ctx, True)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                mrs.mrs_ensemble_eval(ctx, ens, prec, True)
+            wall = (time.perf_counter() - t0) / reps
+            mrs.mrs_profile_enable(ctx, False)
+            n_k, ms_k = mrs.mrs_profile_query(ctx, kname)
+            mrs.mrs_profile_reset(ctx)
+            _, _, U, W = mrs.mrs_ensemble_get(ctx, ens)
+            subset[tag] = (U[idx], W[idx])
+            out[tag] = {"evals": reps, "ms_per_eval": 1e3 * wall, "pairs_per_s": e.N * e.N / wall,
+                        "pair_kernel_us": 1e3 * ms_k / n_k,
+                        "roofline": roofline(e.N * e.N, 1e-3 * ms_k / n_k, peak)}
+    finally:
+        mrs.mrs_ensemble_destroy(ens)
+    return out, subset
+
+
+def oracle_large_subset(subset):
+    """The oracle on the 256,000-point ensemble's 2,048-target check subset
+    (rod forces of every point, then the MRS sum for the subset): its time and
+    the GPU's max relative error there."""
+    import oracle
+    import synth
+
+    e = synth.ens256000()
+    idx = synth.ens256000_subset(e.N)
+    t0 = time.perf_counter()
+    g, m = oracle.rod_forces(e.offsets, e.X, e.D, e.rod(), e.f, e.n)
+    Uo, Wo = oracle.mrs_field(e.X[idx], e.X, g, m, e.eps, e.mu)
+    dt = time.perf_counter() - t0
+    errs = {tag: {"U": oracle.rel_err(U, Uo), "Omega": oracle.rel_err(W, Wo)} for tag, (U, W) in subset.items()}
+    return {"value": len(idx) * e.N / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"rod forces of all {e.N} points + MRS sum for the {len(idx)}-target check subset, once "
+                      f"({dt:.1f} s)"}, errs
 
 
 def bench_slices(mrs, ctx, steps, args):
@@ -435,6 +516,8 @@ def main():
     ap.add_argument("--tick-pairs", type=float, default=2e10, help="serving: pair budget of one serving tick")
     ap.add_argument("--dt", type=float, default=None, help="time step (default 1e-4 for rod64, else 1e-6)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default workload only: skip the 256,000-point and the 16-slice legs")
     args = ap.parse_args()
     if args.dt is None:
         args.dt = 1e-4 if args.workload == "rod64" else 1e-6
@@ -524,10 +607,19 @@ def main():
             res[tag] = measure(mrs, ctx, e, prec, args.steps, args.warmup, args.dt, integ, swim)
             res[tag]["chunks"] = mrs.mrs_tune_get(ctx, e.N, prec)["chunks"]
             res[tag]["traffic"] = measured_traffic(mrs, args.workload, tag, e.N, prec, n_cu)
+        extra = args.workload == "ens12800" and not args.no_extra
+        large = slices_leg = large_subset = None
+        if extra:
+            large, large_subset = bench_large(mrs, ctx)
+            log(f"16 slices x 3,200 points, {args.steps} RK4 steps: batched graph vs plain")
+            slices_leg = bench_slices(mrs, ctx, args.steps, args)
         cpu, errs = (None, None)
         if not args.no_cpu:
             log("cpu baseline (oracle)")
             cpu, errs = cpu_baseline(mrs, ctx, e, [mrs.MRS_FP32C, mrs.MRS_FP64], swim, args.workload)
+            if large_subset is not None:
+                log("oracle on the 256,000-point check subset")
+                cpu["large_subset"], large["max_rel_err_vs_oracle"] = oracle_large_subset(large_subset)
     finally:
         mrs.mrs_context_destroy(ctx)
 
@@ -540,6 +632,8 @@ def main():
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
             "roofline": roofline(e.N * e.N, r["kernel_avg_s"], peak, r["traffic"]),
             "source_chunks": r["chunks"],
+            "settle_s": round(r["settle_s"], 3),
+            "clock_mhz": r["clock_mhz"],
             "kernels_avg_us": {k: round(v["avg_us"], 2) for k, v in r["kernels"].items()},
             "frame_update_GBps": frame_update_gbps(e.N, r["kernels"]),
         }
@@ -573,7 +667,13 @@ def main():
         "cpu_baseline": cpu,
         "max_rel_err_vs_oracle": errs,
         "finite": res["fp32c"]["finite"] and res["fp64"]["finite"],
+        "settle_s": s32["settle_s"],
+        "clock_mhz": s32["clock_mhz"],
     }
+    if large is not None:
+        line["large_256000"] = large
+    if slices_leg is not None:
+        line["slices_16x3200"] = slices_leg
     print(json.dumps(line), flush=True)
 
 

@@ -332,6 +332,12 @@ typedef struct {
     int32_t mode;
     int32_t targets_per_lane;
     int32_t chunks;
+    int32_t schedule;  /* tiled mode: 0 = one block per (target tile, source
+                          chunk); 1 = persistent: a grid of the blocks the
+                          device keeps resident, each claiming the next block
+                          of the work list from a counter until none is left
+                          (same results: every block of work writes its own
+                          partial sums) */
 } mrs_pair_config;
 
 /* Time candidate configurations on a seeded synthetic ensemble of n points
@@ -415,6 +421,11 @@ mrs_status mrs_profile_enable(mrs_context *ctx, int on);
  * context. */
 mrs_status mrs_profile_select(mrs_context *ctx, const char *kernel);
 mrs_status mrs_profile_reset(mrs_context *ctx);
+/* Shader clock of the device now, in MHz: one wave spins for 200,000
+ * shader-clock ticks (s_memtime) and the elapsed ticks of the constant
+ * 100 MHz reference clock (s_memrealtime) give the rate.  Synchronous on the
+ * context stream; meant for reporting the clock beside kernel timings. */
+mrs_status mrs_profile_clock(mrs_context *ctx, double *mhz);
 mrs_status mrs_profile_query(mrs_context *ctx, const char *kernel, int64_t *launches,
                              double *total_ms);
 

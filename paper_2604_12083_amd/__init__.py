@@ -78,7 +78,8 @@ MRS_REQ_EVAL, MRS_REQ_STEPS = 0, 1
 
 
 class mrs_pair_config(ctypes.Structure):
-    _fields_ = [("mode", ctypes.c_int32), ("targets_per_lane", ctypes.c_int32), ("chunks", ctypes.c_int32)]
+    _fields_ = [("mode", ctypes.c_int32), ("targets_per_lane", ctypes.c_int32), ("chunks", ctypes.c_int32),
+                ("schedule", ctypes.c_int32)]
 
 
 class MrsError(RuntimeError):
@@ -141,6 +142,7 @@ _SIGS = {
     "mrs_profile_enable": (_int, [_vp, _int]),
     "mrs_profile_select": (_int, [_vp, ctypes.c_char_p]),
     "mrs_profile_reset": (_int, [_vp]),
+    "mrs_profile_clock": (_int, [_vp, ctypes.POINTER(_dbl)]),
     "mrs_profile_query": (_int, [_vp, ctypes.c_char_p, ctypes.POINTER(_i64), ctypes.POINTER(_dbl)]),
 }
 
@@ -373,6 +375,13 @@ def mrs_profile_reset(ctx) -> None:
     _check(_lib.mrs_profile_reset(ctx), ctx)
 
 
+def mrs_profile_clock(ctx) -> float:
+    """Shader clock (MHz) measured by a short spin on the device."""
+    v = _dbl()
+    _check(_lib.mrs_profile_clock(ctx, ctypes.byref(v)), ctx)
+    return float(v.value)
+
+
 def mrs_profile_query(ctx, kernel=""):
     n = _i64()
     ms = _dbl()
@@ -446,13 +455,14 @@ def mrs_autotune(ctx, n, prec=MRS_FP32C, reps=3):
     c = mrs_pair_config()
     ms = _dbl()
     _check(_lib.mrs_autotune(ctx, int(n), int(prec), int(reps), ctypes.byref(c), ctypes.byref(ms)), ctx)
-    return {"mode": c.mode, "targets_per_lane": c.targets_per_lane, "chunks": c.chunks}, float(ms.value)
+    return {"mode": c.mode, "targets_per_lane": c.targets_per_lane, "chunks": c.chunks,
+            "schedule": c.schedule}, float(ms.value)
 
 
 def mrs_tune_get(ctx, n, prec=MRS_FP32C):
     c = mrs_pair_config()
     _check(_lib.mrs_tune_get(ctx, int(n), int(prec), ctypes.byref(c)), ctx)
-    return {"mode": c.mode, "targets_per_lane": c.targets_per_lane, "chunks": c.chunks}
+    return {"mode": c.mode, "targets_per_lane": c.targets_per_lane, "chunks": c.chunks, "schedule": c.schedule}
 
 
 def mrs_plan_items(n, prec, n_cu=256):
@@ -469,8 +479,8 @@ def mrs_plan_items(n, prec, n_cu=256):
     return {"mode": m.value, "targets_per_lane": t.value, "chunks": k.value, "tail_start": ts.value}, items
 
 
-def mrs_tune_set(ctx, n, prec, mode, targets_per_lane=1, chunks=0) -> None:
-    c = mrs_pair_config(int(mode), int(targets_per_lane), int(chunks))
+def mrs_tune_set(ctx, n, prec, mode, targets_per_lane=1, chunks=0, schedule=0) -> None:
+    c = mrs_pair_config(int(mode), int(targets_per_lane), int(chunks), int(schedule))
     _check(_lib.mrs_tune_set(ctx, int(n), int(prec), ctypes.byref(c)), ctx)
 
 

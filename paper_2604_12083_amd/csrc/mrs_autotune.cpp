@@ -51,8 +51,9 @@ void synth_cloud(int64_t n, std::vector<double> &X, std::vector<double> &f, std:
 }
 
 bool valid_cfg(const mrs_pair_config *c) {
-    return c && (c->mode == PAIR_TILE || c->mode == PAIR_SPLIT) && (c->targets_per_lane == 1 || c->targets_per_lane == 2) &&
-           c->chunks >= 0;
+    return c && (c->mode == PAIR_TILE || c->mode == PAIR_SPLIT || c->mode == PAIR_QUAD) &&
+           (c->targets_per_lane == 1 || c->targets_per_lane == 2) &&
+           c->chunks >= 0 && (c->schedule == SCHED_GRID || c->schedule == SCHED_PERSISTENT);
 }
 
 }  // namespace
@@ -65,6 +66,7 @@ mrs_status mrs_tune_get(mrs_context *ctx, int64_t n, mrs_precision prec, mrs_pai
     out->mode = c.mode;
     out->targets_per_lane = c.tpl;
     out->chunks = c.K;
+    out->schedule = c.sched;
     return MRS_OK;
 }
 
@@ -74,6 +76,7 @@ mrs_status mrs_tune_set(mrs_context *ctx, int64_t n, mrs_precision prec, const m
     c.mode = cfg->mode;
     c.tpl = cfg->targets_per_lane;
     c.K = cfg->chunks;
+    c.sched = cfg->schedule;
     ctx->tune[{(int)prec, size_bucket(n)}] = c;
     return MRS_OK;
 }
@@ -166,6 +169,7 @@ mrs_status mrs_autotune(mrs_context *ctx, int64_t n, mrs_precision prec, int32_t
         best->mode = best_c.mode;
         best->targets_per_lane = best_c.tpl;
         best->chunks = best_c.K;
+        best->schedule = best_c.sched;
     }
     if (best_ms) *best_ms = best_t;
     return MRS_OK;

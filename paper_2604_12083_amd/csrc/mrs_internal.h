@@ -123,17 +123,31 @@ hipError_t launch_rod_forces(int prec, int stage_state, int elastic, int scheme,
 // kLjMaskPoints consecutive points)).
 hipError_t launch_lj(int stage_state, const EnsDesc *d_desc, const PointItem *d_box_items, int n_box_items,
                      const PointItem *d_items, int n_items, hipStream_t s);
+// queue (two uint32 that are zero before the launch and zero again after
+// it) and resident > 0: tiled kernels run the persistent schedule with
+// min(n_items, resident) blocks; otherwise one block per item.
 hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, const PairItem *d_items,
-                        int n_items, hipStream_t s);
+                        int n_items, hipStream_t s, uint32_t *queue = nullptr, int resident = 0);
+// Resident blocks per CU of the persistent tiled pair kernel.
+int pairs_resident_blocks(int prec, int tpl);
 // dt = NaN: every ensemble uses its own EnsDesc::dt.
 hipError_t launch_reduce(int epi, int stage, int scheme, double dt, const EnsDesc *d_desc,
                          const PointItem *d_items, int n_items, hipStream_t s);
 hipError_t launch_rotsqrt(int64_t count, const double *R, double *S, hipStream_t s);
+// out[0] = shader-clock ticks, out[1] = reference-clock ticks of a spin of `cycles` ticks.
+hipError_t launch_clock_probe(int64_t cycles, uint64_t *out, hipStream_t s);
 // Parareal correction (SoA states of N points): X = Xf + Xg - Xo, D = reorth(Df + Dg - Do).
 hipError_t launch_parareal_correct(int N, const double *Xf, const double *Df, const double *Xg, const double *Dg,
                                   const double *Xo, const double *Do, double *X, double *D, hipStream_t s);
 
 // Pair-kernel modes.
-enum PairMode : int { PAIR_TILE = 0, PAIR_SPLIT = 1 };
+// PAIR_QUAD (FP32C): tiles of 64 targets whose four waves split the sources.
+enum PairMode : int { PAIR_TILE = 0, PAIR_SPLIT = 1, PAIR_QUAD = 2 };
+// Schedules of the tiled pair kernels: one block per item, or a resident
+// grid whose blocks claim items from a queue.
+enum PairSched : int { SCHED_GRID = 0, SCHED_PERSISTENT = 1 };
+// Work-queue counters per plan: one pair of uint32 per pair-kernel launch
+// of a stage (split, tile1, tile2), padded.
+constexpr int kQueueWords = 16;
 
 }  // namespace mrs

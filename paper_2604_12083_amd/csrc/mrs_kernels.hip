@@ -626,6 +626,28 @@ __global__ __launch_bounds__(kBlock) void k_parareal_correct(int N, const double
     for (int c = 0; c < 9; c++) D[(size_t)c * N + i] = d[c];
 }
 
+// ------------------------------------------------------------ clock probe
+
+// One wave spins until `cycles` shader-clock ticks (s_memtime) have passed,
+// or `max_iter` reads, and writes the shader ticks and the constant
+// reference-clock ticks (s_memrealtime) that elapsed.
+__global__ __launch_bounds__(64) void k_clock_probe(int64_t cycles, int64_t max_iter, uint64_t *out) {
+    const uint64_t r0 = __builtin_amdgcn_s_memrealtime();
+    const uint64_t t0 = __builtin_amdgcn_s_memtime();
+    uint64_t t = t0;
+    for (int64_t i = 0; i < max_iter && t - t0 < (uint64_t)cycles; i++) t = __builtin_amdgcn_s_memtime();
+    const uint64_t r1 = __builtin_amdgcn_s_memrealtime();
+    if (threadIdx.x == 0) {
+        out[0] = t - t0;
+        out[1] = r1 - r0;
+    }
+}
+
+hipError_t launch_clock_probe(int64_t cycles, uint64_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_clock_probe, dim3(1), dim3(64), 0, s, cycles, (int64_t)1 << 26, out);
+    return hipGetLastError();
+}
+
 // --------------------------------------------------------- launch wrappers
 
 static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }

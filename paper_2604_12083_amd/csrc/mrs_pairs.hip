@@ -20,6 +20,8 @@
 // scale per target.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "mrs_internal.h"
 
 namespace mrs {
@@ -187,11 +189,54 @@ constexpr float kFarBoxGap2 = 17.0f;
 // hi/lo difference of the other paths.
 constexpr float kAnchorGapRatio2 = 16.0f;
 
+// Persistent schedule.  The grid holds as many blocks as the device keeps
+// resident; each block claims the next item of the work list from a counter
+// (queue[0], an ordinary vector atomic from one lane) until the list is
+// exhausted, so blocks that run ahead take more items and the device stays
+// full until the last items, which the work list makes the shortest.  Every
+// item still writes its own partial slot: results do not depend on which
+// block ran which item.  The last block to leave (queue[1] counts them)
+// resets both counters, so the next launch (or graph replay) starts at zero.
+__device__ __forceinline__ int claim_item(uint32_t *queue, int *sNext) {
+    __syncthreads();  // the previous item is finished and sNext has been read
+    if (threadIdx.x == 0) *sNext = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    return *sNext;
+}
+
+__device__ __forceinline__ void leave_queue(uint32_t *queue) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(queue + 1, 1u) == gridDim.x - 1) {
+            atomicExch(queue, 0u);
+            atomicExch(queue + 1, 0u);
+        }
+    }
+}
+
+// Orders a wave's own LDS writes before its later reads (and its reads
+// before later writes) without waiting for the other waves of the block.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Blocks per CU the register budget must allow: 5 with one target per lane
-// (<= 102 VGPRs), 3 with two (<= 170).
-template <int T>
+// (<= 102 VGPRs), 3 with two (<= 170).  PERSIST: items claimed from the queue;
+// otherwise block b runs item b.
+//
+// QUAD (one target per lane): the block's four waves share the item's 64
+// targets and split its sources, wave w taking the 64-source blocks w, w + 4,
+// ... of the item; each wave stages and uses only its own blocks (no block
+// barrier in the loop), and the four waves' sums are added in wave order at
+// the end of the item.  A wave's share of an item is a quarter of the
+// item's pairs, so the waves that run last on a SIMD hold short work.
+template <int T, bool PERSIST, bool QUAD>
 __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const EnsDesc *__restrict__ desc,
-                                                           const PairItem *__restrict__ items) {
+                                                           const PairItem *__restrict__ items, int n_items,
+                                                           uint32_t *queue) {
+    static_assert(!QUAD || T == 1, "four-wave source split: one target per lane");
     // staged sources: sW = (w, fx) with w the anchored position, sF = (fy, fz,
     // nx, ny), sN = (nz, lo), sH = (hi, 0)
     __shared__ float4 sW[kSrcTile], sF[kSrcTile], sN[kSrcTile], sH[kSrcTile];
@@ -199,16 +244,21 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
     // per 64-source block: hi-part box lo, hi, anchor c, squared half-diagonal
     __shared__ float sBox[kSrcTile / kKahanBlock][10];
     static_assert(kSrcTile / kKahanBlock == kBlock / 64, "one source block per wave");
-    const PairItem it = items[blockIdx.x];
+    __shared__ int sNext;
+    int idx = PERSIST ? claim_item(queue, &sNext) : (int)blockIdx.x;
+    while (idx < n_items) {
+    const PairItem it = items[idx];
     const EnsDesc &E = desc[it.ens];
     const RecF32 *__restrict__ rec = reinterpret_cast<const RecF32 *>(E.rec);
     const int tid = threadIdx.x;
+    // target slot of this lane: the block's lanes (tiled) or the wave's (QUAD)
+    const int tl = QUAD ? (tid & 63) : tid;
     float thx[T], thy[T], thz[T], tlx[T], tly[T], tlz[T];
     float s[T][6], c[T][6];
     float tlo[3] = {INFINITY, INFINITY, INFINITY}, thi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
     for (int t = 0; t < T; t++) {
-        const int li = min(tid + t * kBlock, it.ntgt - 1);
+        const int li = min(tl + t * kBlock, it.ntgt - 1);
         const RecF32 r = rec[it.tgt0 + li];
         thx[t] = r.a.x; thy[t] = r.a.y; thz[t] = r.a.z;
         tlx[t] = r.b.x; tly[t] = r.b.y; tlz[t] = r.b.z;
@@ -220,7 +270,12 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
 #pragma unroll
     for (int k = 0; k < 3; k++) { tlo[k] = wave_min(tlo[k]); thi[k] = wave_max(thi[k]); }
     for (int base = 0; base < it.nsrc; base += kSrcTile) {
-        __syncthreads();
+        if (QUAD) {
+            if (base + (tid & ~63) >= it.nsrc) break;  // wave-uniform: this wave has no block left
+            wave_sync();
+        } else {
+            __syncthreads();
+        }
         const int j = base + tid;
         const bool real = j < it.nsrc;
         float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, cc = a;
@@ -258,9 +313,13 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
             for (int k = 0; k < 3; k++) { bx[k] = lo[k]; bx[3 + k] = hi[k]; bx[6 + k] = ctr[k]; }
             bx[9] = hd2;
         }
-        __syncthreads();
+        if (QUAD) wave_sync();
+        else __syncthreads();
         const int cnt = min(kSrcTile, it.nsrc - base);
-        for (int sb = 0; sb < cnt; sb += kKahanBlock) {
+        // QUAD: only the block this wave staged
+        const int sb0 = QUAD ? (tid & ~63) : 0;
+        const int sb1 = QUAD ? sb0 + kKahanBlock : cnt;
+        for (int sb = sb0; sb < sb1; sb += kKahanBlock) {
             float p[T][6];
             // bit j of near[t]: source sb + j is near target t (masked path only)
             uint64_t near[T];
@@ -358,23 +417,47 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
         }
     }
     const int N = E.N;
+    if (QUAD) {
+        // the four waves' sums for the same targets, added in wave order
 #pragma unroll
-    for (int t = 0; t < T; t++) {
-        const int li = tid + t * kBlock;
-        if (li < it.ntgt) {
+        for (int k = 0; k < 6; k++) sNear[k][0][tid] += (double)s[0][k] - (double)c[0][k];
+        __syncthreads();
+        if (tid < 64 && tid < it.ntgt) {
 #pragma unroll
-            for (int k = 0; k < 6; k++)
-                E.part[((size_t)it.chunk * 6 + k) * N + it.tgt0 + li] =
-                    ((double)s[t][k] - (double)c[t][k]) + sNear[k][t][tid];
+            for (int k = 0; k < 6; k++) {
+                double v = sNear[k][0][tid];
+#pragma unroll
+                for (int w = 1; w < kBlock / 64; w++) v += sNear[k][0][w * 64 + tid];
+                E.part[((size_t)it.chunk * 6 + k) * N + it.tgt0 + tid] = v;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < T; t++) {
+            const int li = tid + t * kBlock;
+            if (li < it.ntgt) {
+#pragma unroll
+                for (int k = 0; k < 6; k++)
+                    E.part[((size_t)it.chunk * 6 + k) * N + it.tgt0 + li] =
+                        ((double)s[t][k] - (double)c[t][k]) + sNear[k][t][tid];
+            }
         }
     }
+    if (!PERSIST) break;
+    idx = claim_item(queue, &sNext);
+    }
+    if (PERSIST) leave_queue(queue);
 }
 
-template <int T>
+template <int T, bool PERSIST>
 __global__ __launch_bounds__(kBlock) void k_pairs_tile_f64(const EnsDesc *__restrict__ desc,
-                                                           const PairItem *__restrict__ items) {
+                                                           const PairItem *__restrict__ items, int n_items,
+                                                           uint32_t *queue) {
     __shared__ double2 s0[kSrcTile], s1[kSrcTile], s2[kSrcTile], s3[kSrcTile], s4[kSrcTile];
-    const PairItem it = items[blockIdx.x];
+    __shared__ int sNext;
+    int idx = PERSIST ? claim_item(queue, &sNext) : (int)blockIdx.x;
+    while (idx < n_items) {
+    const PairItem it = items[idx];
     const EnsDesc &E = desc[it.ens];
     const RecF64 *__restrict__ rec = reinterpret_cast<const RecF64 *>(E.rec);
     const int tid = threadIdx.x;
@@ -417,6 +500,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs_tile_f64(const EnsDesc *__rest
             for (int k = 0; k < 6; k++) E.part[((size_t)it.chunk * 6 + k) * N + it.tgt0 + li] = acc[t][k];
         }
     }
+    if (!PERSIST) break;
+    idx = claim_item(queue, &sNext);
+    }
+    if (PERSIST) leave_queue(queue);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -557,19 +644,55 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
 }
 
 // --------------------------------------------------------- launch wrapper
+
+template <int T, bool PERSIST>
+static void launch_tile(int prec, dim3 g, dim3 b, hipStream_t s, const EnsDesc *d_desc, const PairItem *d_items,
+                        int n_items, uint32_t *queue) {
+    if (prec == 1)
+        hipLaunchKernelGGL((k_pairs_tile_f32<T, PERSIST, false>), g, b, 0, s, d_desc, d_items, n_items, queue);
+    else hipLaunchKernelGGL((k_pairs_tile_f64<T, PERSIST>), g, b, 0, s, d_desc, d_items, n_items, queue);
+}
+
+// Resident blocks per CU of a tiled pair kernel (persistent schedule).
+int pairs_resident_blocks(int prec, int tpl) {
+    static int cache[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    int &c = cache[prec == 1][tpl == 2 ? 2 : 1];
+    if (c > 0) return c;
+    int nb = 0;
+    hipError_t e;
+    if (prec == 1)
+        e = tpl == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs_tile_f32<2, true, false>, kBlock, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs_tile_f32<1, true, false>, kBlock, 0);
+    else
+        e = tpl == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs_tile_f64<2, true>, kBlock, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pairs_tile_f64<1, true>, kBlock, 0);
+    c = (e == hipSuccess && nb > 0) ? nb : 1;
+    return c;
+}
+
 hipError_t launch_pairs(int prec, int mode, int tpl, const EnsDesc *d_desc, const PairItem *d_items,
-                        int n_items, hipStream_t s) {
+                        int n_items, hipStream_t s, uint32_t *queue, int resident) {
     if (n_items == 0) return hipSuccess;
-    const dim3 g(n_items), b(kBlock);  // the pair kernels index LDS by threadIdx.x < kBlock
+    const dim3 b(kBlock);  // the pair kernels index LDS by threadIdx.x < kBlock
     if (mode == PAIR_SPLIT) {
+        const dim3 g(n_items);
         if (prec == 1) hipLaunchKernelGGL(k_pairs_split<1>, g, b, 0, s, d_desc, d_items);
         else hipLaunchKernelGGL(k_pairs_split<0>, g, b, 0, s, d_desc, d_items);
-    } else if (prec == 1) {
-        if (tpl == 2) hipLaunchKernelGGL(k_pairs_tile_f32<2>, g, b, 0, s, d_desc, d_items);
-        else hipLaunchKernelGGL(k_pairs_tile_f32<1>, g, b, 0, s, d_desc, d_items);
+    } else if (mode == PAIR_QUAD) {  // FP32C only (the plan never makes FP64 QUAD items)
+        if (queue && resident > 0)
+            hipLaunchKernelGGL((k_pairs_tile_f32<1, true, true>), dim3((unsigned)std::min(n_items, resident)), b, 0, s,
+                               d_desc, d_items, n_items, queue);
+        else
+            hipLaunchKernelGGL((k_pairs_tile_f32<1, false, true>), dim3(n_items), b, 0, s, d_desc, d_items, n_items,
+                               nullptr);
+    } else if (queue && resident > 0) {
+        const dim3 g((unsigned)std::min(n_items, resident));
+        if (tpl == 2) launch_tile<2, true>(prec, g, b, s, d_desc, d_items, n_items, queue);
+        else launch_tile<1, true>(prec, g, b, s, d_desc, d_items, n_items, queue);
     } else {
-        if (tpl == 2) hipLaunchKernelGGL(k_pairs_tile_f64<2>, g, b, 0, s, d_desc, d_items);
-        else hipLaunchKernelGGL(k_pairs_tile_f64<1>, g, b, 0, s, d_desc, d_items);
+        const dim3 g(n_items);
+        if (tpl == 2) launch_tile<2, false>(prec, g, b, s, d_desc, d_items, n_items, nullptr);
+        else launch_tile<1, false>(prec, g, b, s, d_desc, d_items, n_items, nullptr);
     }
     return hipGetLastError();
 }

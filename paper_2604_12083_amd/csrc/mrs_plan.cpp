@@ -60,8 +60,11 @@ static bool split_mode(int64_t N, int) { return N <= 1024; }
 PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
     PairCfg c;
     bool small = false;
-    if (tuned) c = *tuned;
-    else {
+    if (tuned) {
+        c = *tuned;
+        if (c.mode == PAIR_QUAD && prec != MRS_FP32C) c.mode = PAIR_TILE;  // the four-wave split is FP32C only
+        if (c.mode == PAIR_QUAD) c.tpl = 1;
+    } else {
         c.mode = split_mode(N, prec) ? PAIR_SPLIT : PAIR_TILE;
         c.tpl = (prec == MRS_FP32C) ? 1 : 2;
         c.K = 0;
@@ -75,7 +78,7 @@ PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
         c.chunk = (int)N;
         return c;
     }
-    const int64_t tile = (int64_t)kBlock * c.tpl;
+    const int64_t tile = c.mode == PAIR_QUAD ? 64 : (int64_t)kBlock * c.tpl;
     const int64_t tiles = (N + tile - 1) / tile;
     int64_t chunk;
     const bool automatic = c.K <= 0;
@@ -106,13 +109,15 @@ PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
 }
 
 void add_items(Plan &P, int e, int64_t N, int n_fil, const PairCfg &c) {
+    if (c.mode != PAIR_SPLIT && c.sched == SCHED_PERSISTENT) P.sched = SCHED_PERSISTENT;
     if (c.mode == PAIR_SPLIT) {
         for (int64_t t0 = 0; t0 < N; t0 += kSplitTargetsPerBlock)
             P.split.push_back({e, (int)t0, (int)std::min<int64_t>(kSplitTargetsPerBlock, N - t0), 0, (int)N, 0});
     } else {
-        const int64_t tile = (int64_t)kBlock * c.tpl;
-        auto &dst = c.tpl == 2 ? P.tile2 : P.tile1;
-        auto &tail = c.tpl == 2 ? P.tail2 : P.tail1;
+        const bool quad = c.mode == PAIR_QUAD;
+        const int64_t tile = quad ? 64 : (int64_t)kBlock * c.tpl;
+        auto &dst = quad ? P.quad : (c.tpl == 2 ? P.tile2 : P.tile1);
+        auto &tail = quad ? P.tailq : (c.tpl == 2 ? P.tail2 : P.tail1);
         // chunk-major: consecutive blocks share a source chunk, so every XCD
         // (blocks go to the 8 XCDs in turn) reads each chunk once into its L2
         const int64_t B = c.tail_start > 0 ? c.tail_start : N;  // end of the regular chunks
@@ -146,10 +151,13 @@ void near_blocks_first(std::vector<PairItem> &v) {
 void order_items(Plan &P) {
     near_blocks_first(P.tile1);
     near_blocks_first(P.tile2);
+    near_blocks_first(P.quad);
     P.tile1.insert(P.tile1.end(), P.tail1.begin(), P.tail1.end());
     P.tile2.insert(P.tile2.end(), P.tail2.begin(), P.tail2.end());
+    P.quad.insert(P.quad.end(), P.tailq.begin(), P.tailq.end());
     P.tail1.clear();
     P.tail2.clear();
+    P.tailq.clear();
 }
 
 }  // namespace mrs
@@ -167,7 +175,8 @@ extern "C" mrs_status mrs_plan_items(int64_t n, mrs_precision prec, int32_t n_cu
     P.prec = (int)prec;
     add_items(P, 0, n, 0, c);
     order_items(P);
-    const std::vector<PairItem> &v = c.mode == PAIR_SPLIT ? P.split : (c.tpl == 2 ? P.tile2 : P.tile1);
+    const std::vector<PairItem> &v =
+        c.mode == PAIR_SPLIT ? P.split : (c.mode == PAIR_QUAD ? P.quad : (c.tpl == 2 ? P.tile2 : P.tile1));
     *n_items = (int64_t)v.size();
     if (mode) *mode = c.mode;
     if (targets_per_lane) *targets_per_lane = c.tpl;

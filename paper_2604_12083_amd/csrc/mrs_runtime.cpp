@@ -78,10 +78,13 @@ void add_lj_items(Plan &P, int e, const mrs_ensemble *E) {
 hipError_t finalize_plan(Plan &P) {
     order_items(P);
     hipError_t e;
+    if ((e = P.d_queue.reserve(kQueueWords * sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = hipMemset(P.d_queue.p, 0, kQueueWords * sizeof(uint32_t))) != hipSuccess) return e;
     if ((e = upload_vec(P.d_desc, P.h_desc)) != hipSuccess) return e;
     if ((e = upload_vec(P.d_split, P.split)) != hipSuccess) return e;
     if ((e = upload_vec(P.d_tile1, P.tile1)) != hipSuccess) return e;
     if ((e = upload_vec(P.d_tile2, P.tile2)) != hipSuccess) return e;
+    if ((e = upload_vec(P.d_quad, P.quad)) != hipSuccess) return e;
     if ((e = upload_vec(P.d_rods, P.rods)) != hipSuccess) return e;
     if ((e = upload_vec(P.d_lj, P.lj)) != hipSuccess) return e;
     if ((e = upload_vec(P.d_ljb, P.ljb)) != hipSuccess) return e;
@@ -174,27 +177,44 @@ hipEvent_t take_event(mrs_context *ctx) {
 
 static const char *pair_name(int prec, int mode) {
     if (mode == PAIR_SPLIT) return prec == MRS_FP32C ? "pairs_split_f32c" : "pairs_split_f64";
+    if (mode == PAIR_QUAD) return "pairs_tile_f32c_quad";
     return prec == MRS_FP32C ? "pairs_tile_f32c" : "pairs_tile_f64";
 }
 
-hipError_t run_pairs(mrs_context *ctx, Plan &P, hipStream_t s) {
+// Pair-kernel launches of one stage: the small-ensemble kernel, then the
+// tiled kernel at one and at two targets per lane, each on its own queue
+// counters when the plan runs the persistent schedule.
+static hipError_t pair_launches(mrs_context *ctx, int prec, int sched, const EnsDesc *dd, const PairItem *split,
+                                int n_split, const PairItem *t1, int n_t1, const PairItem *t2, int n_t2,
+                                const PairItem *tq, int n_tq, uint32_t *queue, hipStream_t s) {
     hipError_t e = hipSuccess;
-    if (!P.split.empty())
-        e = timed(ctx, pair_name(P.prec, PAIR_SPLIT), s, [&] {
-            return launch_pairs(P.prec, PAIR_SPLIT, 1, P.d_desc.as<EnsDesc>(), P.d_split.as<PairItem>(),
-                                (int)P.split.size(), s);
+    const bool pers = sched == SCHED_PERSISTENT && queue;
+    if (n_split)
+        e = timed(ctx, pair_name(prec, PAIR_SPLIT), s,
+                  [&] { return launch_pairs(prec, PAIR_SPLIT, 1, dd, split, n_split, s); });
+    if (e == hipSuccess && n_t1)
+        e = timed(ctx, pair_name(prec, PAIR_TILE), s, [&] {
+            return launch_pairs(prec, PAIR_TILE, 1, dd, t1, n_t1, s, pers ? queue : nullptr,
+                                pers ? pairs_resident_blocks(prec, 1) * ctx->n_cu : 0);
         });
-    if (e == hipSuccess && !P.tile1.empty())
-        e = timed(ctx, pair_name(P.prec, PAIR_TILE), s, [&] {
-            return launch_pairs(P.prec, PAIR_TILE, 1, P.d_desc.as<EnsDesc>(), P.d_tile1.as<PairItem>(),
-                                (int)P.tile1.size(), s);
+    if (e == hipSuccess && n_t2)
+        e = timed(ctx, pair_name(prec, PAIR_TILE), s, [&] {
+            return launch_pairs(prec, PAIR_TILE, 2, dd, t2, n_t2, s, pers ? queue + 2 : nullptr,
+                                pers ? pairs_resident_blocks(prec, 2) * ctx->n_cu : 0);
         });
-    if (e == hipSuccess && !P.tile2.empty())
-        e = timed(ctx, pair_name(P.prec, PAIR_TILE), s, [&] {
-            return launch_pairs(P.prec, PAIR_TILE, 2, P.d_desc.as<EnsDesc>(), P.d_tile2.as<PairItem>(),
-                                (int)P.tile2.size(), s);
+    if (e == hipSuccess && n_tq)
+        e = timed(ctx, pair_name(prec, PAIR_QUAD), s, [&] {
+            return launch_pairs(prec, PAIR_QUAD, 1, dd, tq, n_tq, s, pers ? queue + 4 : nullptr,
+                                pers ? pairs_resident_blocks(prec, 1) * ctx->n_cu : 0);
         });
     return e;
+}
+
+hipError_t run_pairs(mrs_context *ctx, Plan &P, hipStream_t s) {
+    return pair_launches(ctx, P.prec, P.sched, P.d_desc.as<EnsDesc>(), P.d_split.as<PairItem>(), (int)P.split.size(),
+                         P.d_tile1.as<PairItem>(), (int)P.tile1.size(), P.d_tile2.as<PairItem>(),
+                         (int)P.tile2.size(), P.d_quad.as<PairItem>(), (int)P.quad.size(), P.d_queue.as<uint32_t>(),
+                         s);
 }
 
 const char *epi_name(int epi) {
@@ -560,7 +580,7 @@ struct EvalLayout {
     Plan P;
     EnsDesc d{};
     std::vector<char> blob;
-    size_t o_desc = 0, o_split = 0, o_t1 = 0, o_t2 = 0, o_pts = 0;
+    size_t o_desc = 0, o_split = 0, o_t1 = 0, o_t2 = 0, o_tq = 0, o_pts = 0, o_queue = 0;
 };
 
 static mrs_status eval_args(mrs_context *ctx, int64_t n, const double *dX, const double *df, const double *dt,
@@ -603,7 +623,10 @@ static void eval_layout(EvalLayout &L, int64_t n, const double *dX, const double
     L.o_split = put(L.P.split.data(), L.P.split.size() * sizeof(PairItem));
     L.o_t1 = put(L.P.tile1.data(), L.P.tile1.size() * sizeof(PairItem));
     L.o_t2 = put(L.P.tile2.data(), L.P.tile2.size() * sizeof(PairItem));
+    L.o_tq = put(L.P.quad.data(), L.P.quad.size() * sizeof(PairItem));
     L.o_pts = put(L.P.pts.data(), L.P.pts.size() * sizeof(PointItem));
+    const uint32_t zero[kQueueWords] = {};
+    L.o_queue = put(zero, sizeof zero);  // work-queue counters start at zero
 }
 
 // Queue the kernels of an evaluation whose blob is on the device at `base`.
@@ -611,21 +634,12 @@ static hipError_t eval_launch(mrs_context *ctx, const EvalLayout &L, int p, cons
     const Plan &P = L.P;
     const EnsDesc *dd = reinterpret_cast<const EnsDesc *>(base + L.o_desc);
     hipError_t e = timed(ctx, "pack_aos", s, [&] { return launch_pack_aos(p, dd, L.d, s); });
-    if (e == hipSuccess && !P.split.empty())
-        e = timed(ctx, pair_name(p, PAIR_SPLIT), s, [&] {
-            return launch_pairs(p, PAIR_SPLIT, 1, dd, reinterpret_cast<const PairItem *>(base + L.o_split),
-                                (int)P.split.size(), s);
-        });
-    if (e == hipSuccess && !P.tile1.empty())
-        e = timed(ctx, pair_name(p, PAIR_TILE), s, [&] {
-            return launch_pairs(p, PAIR_TILE, 1, dd, reinterpret_cast<const PairItem *>(base + L.o_t1),
-                                (int)P.tile1.size(), s);
-        });
-    if (e == hipSuccess && !P.tile2.empty())
-        e = timed(ctx, pair_name(p, PAIR_TILE), s, [&] {
-            return launch_pairs(p, PAIR_TILE, 2, dd, reinterpret_cast<const PairItem *>(base + L.o_t2),
-                                (int)P.tile2.size(), s);
-        });
+    if (e == hipSuccess)
+        e = pair_launches(ctx, p, P.sched, dd, reinterpret_cast<const PairItem *>(base + L.o_split),
+                          (int)P.split.size(), reinterpret_cast<const PairItem *>(base + L.o_t1), (int)P.tile1.size(),
+                          reinterpret_cast<const PairItem *>(base + L.o_t2), (int)P.tile2.size(),
+                          reinterpret_cast<const PairItem *>(base + L.o_tq), (int)P.quad.size(),
+                          reinterpret_cast<uint32_t *>(const_cast<char *>(base) + L.o_queue), s);
     if (e == hipSuccess)
         e = timed(ctx, "reduce_write", s, [&] {
             return launch_reduce(EPI_WRITE, 0, 0, 0.0, dd, reinterpret_cast<const PointItem *>(base + L.o_pts),
@@ -1273,6 +1287,24 @@ mrs_status mrs_profile_reset(mrs_context *ctx) {
         ctx->event_pool.push_back(r.stop);
     }
     ctx->prof.clear();
+    return MRS_OK;
+}
+
+mrs_status mrs_profile_clock(mrs_context *ctx, double *mhz) {
+    CHECK_CTX(ctx);
+    if (!mhz) return fail(ctx, MRS_EINVAL, "null output");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    hipStream_t s = ctx->stream;
+    uint64_t *buf = nullptr;
+    HIPCHK(ctx, hipHostMalloc(reinterpret_cast<void **>(&buf), 2 * sizeof(uint64_t), hipHostMallocMapped));
+    uint64_t *dbuf = nullptr;
+    hipError_t e = hipHostGetDevicePointer(reinterpret_cast<void **>(&dbuf), buf, 0);
+    if (e == hipSuccess) e = launch_clock_probe(200000, dbuf, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    const uint64_t tick = buf[0], ref = buf[1];
+    (void)hipHostFree(buf);
+    if (e != hipSuccess) return fail(ctx, MRS_EDEVICE, "clock probe: %s", hipGetErrorString(e));
+    *mhz = ref > 0 ? 100.0 * (double)tick / (double)ref : 0.0;  // reference clock: 100 MHz
     return MRS_OK;
 }
 

@@ -44,13 +44,14 @@ struct DevBuf {
 
 // How the pair kernel covers one ensemble.
 struct PairCfg {
-    int mode = PAIR_TILE;  // PAIR_TILE or PAIR_SPLIT
-    int tpl = 1;           // targets per lane (tile mode)
+    int mode = PAIR_TILE;  // PAIR_TILE, PAIR_SPLIT or PAIR_QUAD
+    int tpl = 1;           // targets per lane (tile mode; 1 in QUAD mode)
     int K = 1;             // source chunks (partial sums per target)
     int chunk = 0;         // sources per chunk
     // tail split: sources [tail_start, N) in chunks of tail_chunk sources,
     // partial slots k_big.. (tail_start = 0: none, every chunk is `chunk`)
     int tail_start = 0, tail_chunk = 0, k_big = 0;
+    int sched = SCHED_GRID;  // schedule of the tiled kernel (PairSched)
 };
 
 // Work lists of one launch sequence over a set of ensembles.
@@ -58,13 +59,15 @@ struct Plan {
     int prec = 0;
     int n_ens = 0;
     std::vector<EnsDesc> h_desc;
-    std::vector<PairItem> split, tile1, tile2;
-    std::vector<PairItem> tail1, tail2;  // tail-split items, dispatched after tile1 / tile2
+    std::vector<PairItem> split, tile1, tile2, quad;
+    std::vector<PairItem> tail1, tail2, tailq;  // tail-split items, dispatched after tile1 / tile2 / quad
     std::vector<RodItem> rods;
     std::vector<PointItem> pts;
     std::vector<PointItem> lj;   // 64-point target blocks of the ensembles with LJ repulsion
     std::vector<PointItem> ljb;  // their LJ source blocks, kBlock / 64 per item
-    DevBuf d_desc, d_split, d_tile1, d_tile2, d_rods, d_pts, d_lj, d_ljb;
+    DevBuf d_desc, d_split, d_tile1, d_tile2, d_quad, d_rods, d_pts, d_lj, d_ljb;
+    int sched = SCHED_GRID;  // persistent if any ensemble of the plan asks for it
+    DevBuf d_queue;          // kQueueWords uint32, zero between launches
     // cached graphs: key = (integrator, dt bits, steps, elastic)
     std::map<std::tuple<int, uint64_t, int, int>, hipGraphExec_t> graphs;
     int64_t pairs_per_eval = 0;
