@@ -22,147 +22,12 @@
 
 #include <algorithm>
 
+#include "mrs_device_pairs.h"
 #include "mrs_internal.h"
 
 namespace mrs {
 
-// ---------------------------------------------------------------- helpers
-
-__device__ __forceinline__ float rsq_f32(float x) { return __builtin_amdgcn_rsqf(x); }
-
-// Hardware reciprocal square root refined by one third-order step
-// q <- q (1 + e/2 + 3 e^2/8), e = 1 - x q^2, which takes the hardware
-// estimate to double precision.
-__device__ __forceinline__ double rsq_f64(double x) {
-    double q = __builtin_amdgcn_rsq(x);
-    double e = fma(-x, q * q, 1.0);
-    double p = fma(0.375, e, 0.5);
-    return fma(q * e, p, q);
-}
-
-__device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
-    float y = x - c;
-    float t = s + y;
-    c = (t - s) - y;
-    s = t;
-}
-
-// Pairs closer than rho = r/eps < 4 (R^2 = rho^2 + 1 < 17) carry the largest
-// terms of every sum; the FP32C kernels evaluate them in FP64 (on the exact
-// hi/lo difference) and every other pair in FP32.
-constexpr float kNearR2 = 17.0f;
-
-// R^2 = rho^2 + 1 of a target (th + tl) and a source (sh + sl), in FP32.
-// Both the hot loop and the near-pair rescan use this one function, so they
-// take the same near/far decision bit for bit.
-__device__ __forceinline__ float sep_f32(float thx, float thy, float thz, float tlx, float tly,
-                                         float tlz, float shx, float shy, float shz, float slx,
-                                         float sly, float slz, float &rx, float &ry, float &rz) {
-    rx = (thx - shx) + (tlx - slx);
-    ry = (thy - shy) + (tly - sly);
-    rz = (thz - shz) + (tlz - slz);
-    return fmaf(rz, rz, fmaf(ry, ry, fmaf(rx, rx, 1.0f)));
-}
-
-// Contribution of one source at separation r (R2 = |r|^2 + 1) to p[0..5] =
-// (8 pi mu U, 8 pi mu eps Omega) of one target, in units of eps.  With MASK a
-// near pair adds exactly zero; without it the caller guarantees that no pair
-// is near.
-template <bool MASK>
-__device__ __forceinline__ void pair_core_f32(float rx, float ry, float rz, float R2, float fx,
-                                              float fy, float fz, float nx, float ny, float nz,
-                                              float *p) {
-    const float q = (MASK && R2 < kNearR2) ? 0.0f : rsq_f32(R2);
-    const float q2 = q * q, q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
-    const float h1 = q + q3;
-    const float t = 1.5f * q5;
-    const float h3 = q3 + t;
-    const float u = 3.75f * q7;
-    const float h5 = u + t;
-    const float h4 = fmaf(-0.5f, h3, u);
-    const float fr = fmaf(fz, rz, fmaf(fy, ry, fx * rx));
-    const float nr = fmaf(nz, rz, fmaf(ny, ry, nx * rx));
-    const float a = q3 * fr, b = h5 * nr;
-    // H3 (n x r) = n x g and H3 (f x r) = f x g with g = H3 r
-    const float gx = h3 * rx, gy = h3 * ry, gz = h3 * rz;
-    p[0] = fmaf(-nz, gy, fmaf(ny, gz, fmaf(a, rx, fmaf(h1, fx, p[0]))));
-    p[1] = fmaf(-nx, gz, fmaf(nz, gx, fmaf(a, ry, fmaf(h1, fy, p[1]))));
-    p[2] = fmaf(-ny, gx, fmaf(nx, gy, fmaf(a, rz, fmaf(h1, fz, p[2]))));
-    p[3] = fmaf(-fz, gy, fmaf(fy, gz, fmaf(b, rx, fmaf(h4, nx, p[3]))));
-    p[4] = fmaf(-fx, gz, fmaf(fz, gx, fmaf(b, ry, fmaf(h4, ny, p[4]))));
-    p[5] = fmaf(-fy, gx, fmaf(fx, gy, fmaf(b, rz, fmaf(h4, nz, p[5]))));
-}
-
-// The same for a source record (a = hi + fx, b = lo + fy, c = fz, n); returns R^2.
-template <bool MASK>
-__device__ __forceinline__ float pair_f32(float thx, float thy, float thz, float tlx, float tly,
-                                          float tlz, const float4 A, const float4 B,
-                                          const float4 C, float *p) {
-    float rx, ry, rz;
-    const float R2 = sep_f32(thx, thy, thz, tlx, tly, tlz, A.x, A.y, A.z, B.x, B.y, B.z, rx, ry, rz);
-    pair_core_f32<MASK>(rx, ry, rz, R2, A.w, B.w, C.x, C.y, C.z, C.w, p);
-    return R2;
-}
-
-// Same in FP64 for the separation r = x_target - X_source:
-// p += (8 pi mu U, 8 pi mu Omega) in unscaled units (e2 = eps^2, c375e2 =
-// 3.75 eps^2), or the eps-unit form with e2 = 1, c375e2 = 3.75.
-__device__ __forceinline__ void pair_f64_r(double rx, double ry, double rz, double fx, double fy,
-                                           double fz, double nx, double ny, double nz, double e2,
-                                           double c375e2, double *p) {
-    const double R2 = fma(rz, rz, fma(ry, ry, fma(rx, rx, e2)));
-    const double q = rsq_f64(R2);
-    const double q2 = q * q, q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
-    const double h1 = fma(e2, q3, q);
-    const double t = 1.5 * q5;
-    const double h3 = fma(e2, t, q3);
-    const double u = c375e2 * q7;
-    const double h5 = t + u;
-    const double h4 = fma(-0.5, h3, e2 * u);
-    const double fr = fma(fz, rz, fma(fy, ry, fx * rx));
-    const double nr = fma(nz, rz, fma(ny, ry, nx * rx));
-    const double a = q3 * fr, b = h5 * nr;
-    const double gx = h3 * rx, gy = h3 * ry, gz = h3 * rz;  // see pair_f32
-    p[0] = fma(-nz, gy, fma(ny, gz, fma(a, rx, fma(h1, fx, p[0]))));
-    p[1] = fma(-nx, gz, fma(nz, gx, fma(a, ry, fma(h1, fy, p[1]))));
-    p[2] = fma(-ny, gx, fma(nx, gy, fma(a, rz, fma(h1, fz, p[2]))));
-    p[3] = fma(-fz, gy, fma(fy, gz, fma(b, rx, fma(h4, nx, p[3]))));
-    p[4] = fma(-fx, gz, fma(fz, gx, fma(b, ry, fma(h4, ny, p[4]))));
-    p[5] = fma(-fy, gx, fma(fx, gy, fma(b, rz, fma(h4, nz, p[5]))));
-}
-
-__device__ __forceinline__ void pair_f64(double tx, double ty, double tz, double x, double y,
-                                         double z, double fx, double fy, double fz, double nx,
-                                         double ny, double nz, double e2, double c375e2,
-                                         double *p) {
-    pair_f64_r(tx - x, ty - y, tz - z, fx, fy, fz, nx, ny, nz, e2, c375e2, p);
-}
-
-// FP64 evaluation of a near pair from FP32 hi/lo positions: the hi and lo
-// differences are exact in FP64, the loads are the record's FP32 values.
-__device__ __forceinline__ void near_pair_f64(float thx, float thy, float thz, float tlx, float tly,
-                                              float tlz, float shx, float shy, float shz, float slx,
-                                              float sly, float slz, float fx, float fy, float fz,
-                                              float nx, float ny, float nz, double *p) {
-    const double rx = ((double)thx - (double)shx) + ((double)tlx - (double)slx);
-    const double ry = ((double)thy - (double)shy) + ((double)tly - (double)sly);
-    const double rz = ((double)thz - (double)shz) + ((double)tlz - (double)slz);
-    pair_f64_r(rx, ry, rz, fx, fy, fz, nx, ny, nz, 1.0, 3.75, p);
-}
-
 // ----------------------------------------------------------------- pairs
-
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-    return v;
-}
 
 // Squared distance between the boxes [lo0, hi0] and [lo1, hi1] (0 if they overlap).
 __device__ __forceinline__ float box_gap2(const float *lo0, const float *hi0, const float *lo1, const float *hi1) {
@@ -176,9 +41,23 @@ __device__ __forceinline__ float box_gap2(const float *lo0, const float *hi0, co
 }
 
 // A wave whose target box is farther than this (squared, in units of eps)
-// from a source block's box has no near pair in it: 17 > (4 + margin)^2 for
-// the hi-part rounding of the boxes (at most 2^-24 of 2^14 per coordinate).
+// from a source block's box has no near pair in it (rho >= 4).  The boxes are
+// taken over the hi parts of the positions and then widened by 2^-23 of
+// their largest coordinate magnitude on every side, which covers the lo parts
+// (|lo| <= 2^-24 |hi|), so the test holds for the exact positions at any
+// distance from the origin.
 constexpr float kFarBoxGap2 = 17.0f;
+constexpr float kBoxWiden = 1.0f / 8388608.0f;  // 2^-23
+
+// Widens a hi-part box [lo, hi] to contain the exact positions.
+__device__ __forceinline__ void widen_box(float *lo, float *hi) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const float m = fmaxf(fabsf(lo[k]), fabsf(hi[k])) * kBoxWiden;
+        lo[k] -= m;
+        hi[k] += m;
+    }
+}
 
 // Anchored far blocks.  Relative to the centre c of a 64-source block's box,
 // a source sits at w = (sh - c) + sl and a target at u = (th - c) + tl, both
@@ -269,6 +148,7 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
     }
 #pragma unroll
     for (int k = 0; k < 3; k++) { tlo[k] = wave_min(tlo[k]); thi[k] = wave_max(thi[k]); }
+    widen_box(tlo, thi);
     for (int base = 0; base < it.nsrc; base += kSrcTile) {
         if (QUAD) {
             if (base + (tid & ~63) >= it.nsrc) break;  // wave-uniform: this wave has no block left
@@ -289,6 +169,7 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
         lo[2] = wave_min(real ? a.z : INFINITY);
         hi[0] = wave_max(real ? a.x : -INFINITY); hi[1] = wave_max(real ? a.y : -INFINITY);
         hi[2] = wave_max(real ? a.z : -INFINITY);
+        widen_box(lo, hi);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             // a block without a real source (never evaluated) gets a finite anchor
@@ -506,12 +387,6 @@ __global__ __launch_bounds__(kBlock) void k_pairs_tile_f64(const EnsDesc *__rest
     if (PERSIST) leave_queue(queue);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // Small-ensemble pair kernel: each wave owns kSplitTargetsPerWave targets and
 // its 64 lanes stride over the item's sources; per-lane sums are combined in
 // FP64 with a butterfly of wave shuffles in a fixed order.
@@ -597,7 +472,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
 #pragma unroll
         for (int t = 0; t < TW; t++)
 #pragma unroll
-            for (int k = 0; k < 6; k++) out[t][k] = wave_sum(((double)s[t][k] - (double)c[t][k]) + pn[t][k]);
+            for (int k = 0; k < 6; k++) out[t][k] = ((double)s[t][k] - (double)c[t][k]) + pn[t][k];
+        wave_sum_n<6 * TW>(&out[0][0]);
     } else {
         const RecF64 *__restrict__ rec = reinterpret_cast<const RecF64 *>(E.rec);
         RecF64 *sRec = reinterpret_cast<RecF64 *>(sBuf);
@@ -627,7 +503,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs_split(const EnsDesc *__restric
 #pragma unroll
         for (int t = 0; t < TW; t++)
 #pragma unroll
-            for (int k = 0; k < 6; k++) out[t][k] = wave_sum(acc[t][k]);
+            for (int k = 0; k < 6; k++) out[t][k] = acc[t][k];
+        wave_sum_n<6 * TW>(&out[0][0]);
     }
     if (lane < 6) {
         const int N = E.N;

@@ -73,6 +73,18 @@ def test_translation_far_from_origin(mrs, ctx, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("eps_units", [1e5, 1e6])
+def test_far_from_origin_in_units_of_eps(mrs, ctx, prec, eps_units):
+    """An ensemble 1e5 and 1e6 eps from the origin (beyond 2^16 in units of
+    eps, where the hi parts of the FP32C positions carry rounding of more than
+    a hundredth of eps): the widened boxes keep the near/far and anchoring
+    tests valid; 3,000 points so that the tiled kernel and its far paths run."""
+    e = synth.filaments(30, 100, 3.0, 124)
+    d = eps_units * e.eps * np.array([0.6, -0.64, 0.48])
+    _check(mrs, ctx, e.X + d, e.f, e.n, e.eps, e.mu, prec, f"offset {eps_units:g} eps")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("eps", [1e-4, 10.0])
 def test_eps_extremes(mrs, ctx, prec, eps):
     X, f, n = _cloud(500, 9, box=1.0)
