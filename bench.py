@@ -489,11 +489,19 @@ def bench_serving(mrs, ctx, n_req, rates, slots, budget, tick_pairs=0):
         kinds = np.array(kinds)
         res = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                "pairs_per_s": stats["pairs"] / wall, "wall_s": wall, "ticks": stats["ticks"],
-               "offered_req_per_s": rate}
+               "offered_req_per_s": rate, "device_busy_s": stats["busy_s"],
+               "device_busy_frac": stats["busy_s"] / wall}
         for k, name in ((0, "eval"), (1, "rk4x50")):
             if np.any(kinds == k):
                 res[f"p50_ms_{name}"] = float(np.percentile(lat[kinds == k], 50))
                 res[f"p99_ms_{name}"] = float(np.percentile(lat[kinds == k], 99))
+        # small requests: fewer points than the median request of the sequence
+        pts = np.array([e.N for e in ens])
+        small = pts < np.median(pts)
+        if np.any(small):
+            res["p50_ms_small"] = float(np.percentile(lat[small], 50))
+            res["p99_ms_small"] = float(np.percentile(lat[small], 99))
+            res["small_max_points"] = int(pts[small].max())
         return res
 
     out["batched"] = {str(r): run(r, slots) for r in rates}

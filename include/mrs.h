@@ -275,16 +275,22 @@ typedef struct {
     int64_t submitted, admitted, completed, rejected;
     int64_t ticks, failed_ticks;
     int64_t pairs;        /* pair interactions evaluated */
-    double busy_s;        /* device time spent in ticks */
+    double busy_s;        /* device time of the ticks (events around each) */
     int32_t active, queued;
     int64_t hbm_in_use, hbm_budget;
+    double wall_s;        /* seconds since mrs_server_start */
 } mrs_server_stats;
 
-/* Start a server thread that owns ctx until mrs_server_stop.  Every tick it
- * admits queued requests (arrival order, first fit) while a slot is free and
- * their device footprint fits in hbm_budget_bytes, launches ONE batched
- * sequence that advances every admitted request by one evaluation or one
- * step, and retires finished requests.  All requests of a server use `prec`.
+/* Start a server thread that owns ctx until mrs_server_stop.  It admits
+ * queued requests (arrival order, first fit) while a slot is free and their
+ * device footprint fits in hbm_budget_bytes, copying their state to the
+ * device on a second stream while earlier work runs; every tick is ONE
+ * batched sequence that advances the admitted requests by one evaluation or
+ * one step, and up to two ticks are queued on the device ahead of the host;
+ * a finished request's results are copied back after its last tick without
+ * stopping the device.  Device memory comes from a cache of the server
+ * (hipMalloc only while it warms up, released at mrs_server_stop).  All
+ * requests of a server use `prec`.
  * Each request's result equals the one it gets alone (its work is split
  * the same way in every batch).  A request larger than the whole budget
  * completes with status MRS_ENOMEM without running.  If the environment variable

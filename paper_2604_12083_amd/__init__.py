@@ -71,7 +71,8 @@ class mrs_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("rejected", ctypes.c_int64), ("ticks", ctypes.c_int64), ("failed_ticks", ctypes.c_int64),
                 ("pairs", ctypes.c_int64), ("busy_s", ctypes.c_double), ("active", ctypes.c_int32),
-                ("queued", ctypes.c_int32), ("hbm_in_use", ctypes.c_int64), ("hbm_budget", ctypes.c_int64)]
+                ("queued", ctypes.c_int32), ("hbm_in_use", ctypes.c_int64), ("hbm_budget", ctypes.c_int64),
+                ("wall_s", ctypes.c_double)]
 
 
 MRS_REQ_EVAL, MRS_REQ_STEPS = 0, 1

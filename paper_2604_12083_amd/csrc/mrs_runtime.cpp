@@ -44,6 +44,48 @@ mrs_status check_host_finite(mrs_context *ctx, const double *p, size_t n, const 
     return MRS_OK;
 }
 
+size_t DevPool::size_class(size_t n) {
+    size_t c = 256;
+    while (c < n) {
+        if (c + c / 2 >= n) return c + c / 2;
+        c *= 2;
+    }
+    return c;
+}
+
+hipError_t DevPool::get(size_t n, void **p, size_t *cap) {
+    const size_t c = size_class(n);
+    auto it = free.find(c);
+    if (it != free.end() && !it->second.empty()) {
+        *p = it->second.back();
+        it->second.pop_back();
+        *cap = c;
+        return hipSuccess;
+    }
+    hipError_t e = hipMalloc(p, c);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        *cap = 0;
+        return e;
+    }
+    held += c;
+    *cap = c;
+    return hipSuccess;
+}
+
+void DevPool::put(void *p, size_t cap) { free[cap].push_back(p); }
+
+DevPool::~DevPool() {
+    for (auto &kv : free)
+        for (void *p : kv.second) (void)hipFree(p);
+}
+
+void plan_use_pool(Plan &P, DevPool *pool) {
+    for (DevBuf *b : {&P.d_desc, &P.d_split, &P.d_tile1, &P.d_tile2, &P.d_quad, &P.d_rods, &P.d_pts, &P.d_lj,
+                      &P.d_ljb, &P.d_queue})
+        b->pool = pool;
+}
+
 Plan::~Plan() {
     for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
 }
@@ -147,6 +189,7 @@ mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out) {
     mrs_context *ctx = E->ctx;
     if (!E->plan[prec]) {
         auto P = std::make_unique<Plan>();
+        plan_use_pool(*P, E->pool);
         P->prec = prec;
         P->n_ens = 1;
         PairCfg c = choose_cfg(ctx, E->N, prec);
@@ -336,10 +379,15 @@ namespace mrs {
 
 // Device arrays of a new ensemble (state, stage state, velocities, records).
 mrs_status ensemble_alloc(mrs_context *ctx, int32_t n_fil, const int32_t *offsets, double eps, double mu,
-                          const mrs_rod_params *rod, bool has_ext, std::unique_ptr<mrs_ensemble> &E) {
+                          const mrs_rod_params *rod, bool has_ext, std::unique_ptr<mrs_ensemble> &E, DevPool *pool,
+                          bool init) {
     static std::atomic<uint64_t> next_uid{1};
     const int64_t n = offsets[n_fil];
     E = std::make_unique<mrs_ensemble>();
+    E->pool = pool;
+    for (DevBuf *b : {&E->off, &E->X, &E->D, &E->U, &E->W, &E->Xs, &E->Ds, &E->Ua, &E->Wa, &E->fext, &E->next,
+                      &E->rec, &E->part, &E->clock, &E->fil, &E->flj, &E->lj_blk, &E->lj_box, &E->lj_mask})
+        b->pool = pool;
     E->ctx = ctx;
     E->uid = next_uid.fetch_add(1);
     E->n_fil = n_fil;
@@ -357,6 +405,7 @@ mrs_status ensemble_alloc(mrs_context *ctx, int32_t n_fil, const int32_t *offset
               E->rec.reserve((size_t)n * sizeof(RecF64)) == hipSuccess && E->clock.reserve(sizeof(double)) == hipSuccess;
     if (ok && has_ext) ok = E->fext.reserve(v3) == hipSuccess && E->next.reserve(v3) == hipSuccess;
     if (!ok) return fail(ctx, MRS_ENOMEM, "ensemble allocation (%lld points)", (long long)n);
+    if (!init) return MRS_OK;
     const double t0 = 0.0;
     if (hipMemcpy(E->off.p, offsets, (n_fil + 1) * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(E->clock.p, &t0, sizeof t0, hipMemcpyHostToDevice) != hipSuccess ||
@@ -388,6 +437,18 @@ static mrs_status lj_buffers(mrs_ensemble *E) {
         hipMemcpy(E->lj_blk.p, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
         return fail(ctx, MRS_EDEVICE, "Lennard-Jones index upload");
     return MRS_OK;
+}
+
+void ensemble_detach(mrs_ensemble *E) {
+    mrs_context *ctx = E->ctx;
+    for (auto it = ctx->batch_plans.begin(); it != ctx->batch_plans.end();) {
+        const auto &v = it->first.first;
+        if (std::find(v.begin(), v.end(), E->uid) != v.end()) it = ctx->batch_plans.erase(it);
+        else ++it;
+    }
+    auto &L = ctx->ensembles;
+    L.erase(std::remove(L.begin(), L.end(), E), L.end());
+    delete E;
 }
 
 // New ensemble with the same layout, parameters, loads and state (device copies).
@@ -875,17 +936,25 @@ mrs_status mrs_rotsqrt_device(mrs_context *ctx, int64_t count, const double *dR,
 
 // ---- ensembles
 
+}  // extern "C"
+
+namespace mrs {
+
 // Row-major caller arrays (n x w) to and from the stored SoA layout; stored
 // point k is caller point perm[k].
-static void aos_to_soa(const double *src, double *dst, int64_t n, int w, const std::vector<int64_t> &perm) {
+void aos_to_soa(const double *src, double *dst, int64_t n, int w, const std::vector<int64_t> &perm) {
     for (int64_t k = 0; k < n; k++)
         for (int c = 0; c < w; c++) dst[(size_t)c * n + k] = src[(size_t)w * perm[k] + c];
 }
 
-static void soa_to_aos(const double *src, double *dst, int64_t n, int w, const std::vector<int64_t> &perm) {
+void soa_to_aos(const double *src, double *dst, int64_t n, int w, const std::vector<int64_t> &perm) {
     for (int64_t k = 0; k < n; k++)
         for (int c = 0; c < w; c++) dst[(size_t)w * perm[k] + c] = src[(size_t)c * n + k];
 }
+
+}  // namespace mrs
+
+extern "C" {
 
 static mrs_status put_soa(mrs_context *ctx, DevBuf &d, const double *src, int64_t n, int w,
                           const std::vector<int64_t> &perm) {
@@ -896,6 +965,10 @@ static mrs_status put_soa(mrs_context *ctx, DevBuf &d, const double *src, int64_
 }
 
 // 21-bit spread for a 63-bit Morton key.
+}  // extern "C"
+
+namespace mrs {
+
 static uint64_t spread3(uint64_t v) {
     v &= 0x1fffff;
     v = (v | v << 32) & 0x1f00000000ffffULL;
@@ -915,7 +988,7 @@ static uint64_t spread3(uint64_t v) {
 // the masked path).  Results are returned in the caller's order; only the
 // order of floating-point sums changes.  Writes the stored offsets and the
 // point permutation (stored point k = caller point perm[k]).
-static void spatial_order(int32_t n_fil, const int32_t *off, const double *X, std::vector<int32_t> &soff,
+void spatial_order(int32_t n_fil, const int32_t *off, const double *X, std::vector<int32_t> &soff,
                           std::vector<int64_t> &perm) {
     const int64_t n = off[n_fil];
     std::vector<double> cen((size_t)n_fil * 3, 0.0);
@@ -949,6 +1022,10 @@ static void spatial_order(int32_t n_fil, const int32_t *off, const double *X, st
         soff[i + 1] = (int32_t)pos;
     }
 }
+
+}  // namespace mrs
+
+extern "C" {
 
 static bool all_finite(const double *p, size_t n) {
     for (size_t i = 0; i < n; i++)
@@ -1150,14 +1227,7 @@ void mrs_ensemble_destroy(mrs_ensemble *E) {
     mrs_context *ctx = E->ctx;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     (void)hipStreamSynchronize(ctx->stream);
-    for (auto it = ctx->batch_plans.begin(); it != ctx->batch_plans.end();) {
-        const auto &v = it->first.first;
-        if (std::find(v.begin(), v.end(), E->uid) != v.end()) it = ctx->batch_plans.erase(it);
-        else ++it;
-    }
-    auto &L = ctx->ensembles;
-    L.erase(std::remove(L.begin(), L.end(), E), L.end());
-    delete E;
+    ensemble_detach(E);
 }
 
 // ---- batching

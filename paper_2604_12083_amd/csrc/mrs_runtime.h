@@ -17,16 +17,40 @@
 
 namespace mrs {
 
-// Device allocation owned by the runtime.
+// Device memory cache: blocks in size classes (powers of two and their
+// 1.5 multiples, from 256 bytes) kept on free lists when released, so that
+// a user that allocates and releases repeatedly (the server: a request's
+// state and work lists) calls hipMalloc only while the cache warms up and
+// never hipFree (which waits for the whole device) until the cache is
+// destroyed.  A block may be released only once no queued device work uses
+// it.  Not thread-safe.
+struct DevPool {
+    std::map<size_t, std::vector<void *>> free;
+    size_t held = 0;  // bytes obtained from hipMalloc
+    static size_t size_class(size_t n);
+    hipError_t get(size_t n, void **p, size_t *cap);
+    void put(void *p, size_t cap);
+    DevPool() = default;
+    DevPool(const DevPool &) = delete;
+    DevPool &operator=(const DevPool &) = delete;
+    ~DevPool();
+};
+
+// Device allocation owned by the runtime, from hipMalloc or, when `pool` is
+// set before the first reserve, from that pool.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DevPool *pool = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (pool) pool->put(p, bytes);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
     }
@@ -34,6 +58,7 @@ struct DevBuf {
     hipError_t reserve(size_t n) {
         if (n <= bytes) return hipSuccess;
         release();
+        if (pool) return pool->get(n, &p, &bytes);
         hipError_t e = hipMalloc(&p, n);
         if (e != hipSuccess) { p = nullptr; return e; }
         bytes = n;
@@ -142,6 +167,7 @@ struct mrs_ensemble {
     mrs::DevBuf fil, flj, lj_blk, lj_box, lj_mask;  // with LJ: filament per point, forces, source
                                                     // blocks and their boxes, masks
     std::unique_ptr<mrs::Plan> plan[2];  // per precision
+    mrs::DevPool *pool = nullptr;        // where its device arrays come from (null: hipMalloc)
 };
 
 namespace mrs {
@@ -162,8 +188,24 @@ void add_lj_items(Plan &P, int e, const mrs_ensemble *E);
 hipError_t finalize_plan(Plan &P);
 hipError_t run_pairs(mrs_context *ctx, Plan &P, hipStream_t s);
 hipEvent_t take_event(mrs_context *ctx);
+// Device arrays of a new ensemble, from `pool` if given.  With init, the
+// offsets, the clock (0) and zero velocities are copied synchronously;
+// without, the caller queues them.
 mrs_status ensemble_alloc(mrs_context *ctx, int32_t n_fil, const int32_t *offsets, double eps, double mu,
-                          const mrs_rod_params *rod, bool has_ext, std::unique_ptr<mrs_ensemble> &E);
+                          const mrs_rod_params *rod, bool has_ext, std::unique_ptr<mrs_ensemble> &E,
+                          DevPool *pool = nullptr, bool init = true);
+// Removes an ensemble from its context and frees it without waiting for the
+// device: no queued work may use it any more.
+void ensemble_detach(mrs_ensemble *E);
+// Stored order of an ensemble's filaments (spatial); stored point k is
+// caller point perm[k].
+void spatial_order(int32_t n_fil, const int32_t *off, const double *X, std::vector<int32_t> &soff,
+                   std::vector<int64_t> &perm);
+// Row-major caller arrays (n x w) to and from the stored SoA layout.
+void aos_to_soa(const double *src, double *dst, int64_t n, int w, const std::vector<int64_t> &perm);
+void soa_to_aos(const double *src, double *dst, int64_t n, int w, const std::vector<int64_t> &perm);
+// Device arrays of every list of a plan come from `pool` (before finalize_plan).
+void plan_use_pool(Plan &P, DevPool *pool);
 mrs_status ensemble_clone(mrs_ensemble *S, mrs_ensemble **out);
 const char *epi_name(int epi);
 

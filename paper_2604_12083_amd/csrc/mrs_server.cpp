@@ -1,17 +1,27 @@
 // Serving loop of the MRS filament library: continuous batching of
 // independent ensemble requests on one device.
 //
-// A scheduler thread owns the context.  Each tick it
-//   1. admits queued requests in arrival order (first fit) while a slot is
-//      free and the request's device footprint fits the HBM budget; the
-//      request's state is copied to the device and stays resident there;
-//   2. launches ONE batched launch sequence that advances every admitted
-//      request by one unit of work: an evaluation, one Euler step or one RK4
-//      step (four stages; evaluation and Euler requests take part in the
-//      first stage only);
-//   3. retires finished requests (copies results to host, frees the slot).
-// Requests arriving while a tick runs join at the next tick, so work of
-// requests of different sizes and kinds overlaps inside the same kernels.
+// A scheduler thread owns the context and keeps the device busy with a
+// pipeline of ticks:
+//   1. admission: queued requests are taken in arrival order (first fit)
+//      while a slot is free and the request's device footprint fits the HBM
+//      budget; its state is staged in pinned memory (filaments in spatial
+//      order, SoA) and copied to the device on an upload stream, into arrays
+//      from the server's device-memory cache, while earlier ticks run;
+//   2. tick: ONE batched launch sequence on the compute stream advances the
+//      selected requests by one unit of work (an evaluation, one Euler step
+//      or one RK step, whose first stage is shared with the evaluation and
+//      Euler requests); it first waits (event) for the uploads of requests
+//      it runs for the first time.  Up to kTicksInFlight ticks are queued
+//      ahead, so the device does not wait for the host between ticks;
+//   3. retirement: after a request's last tick its state and velocities are
+//      copied to pinned memory on the compute stream; when that tick's event
+//      has fired, the results are reordered for the caller and the request's
+//      device arrays go back to the cache.
+// Requests arriving while ticks run join at a later tick, so work of requests
+// of different sizes and kinds overlaps inside the same kernels.  The server
+// calls hipMalloc only while its caches warm up and never hipFree before
+// mrs_server_stop.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -35,6 +45,38 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Ticks queued on the device ahead of the host.
+constexpr int kTicksInFlight = 2;
+
+// Pinned host memory cache (same size classes as DevPool); not thread-safe.
+struct PinPool {
+    std::map<size_t, std::vector<void *>> free;
+    hipError_t get(size_t n, void **p, size_t *cap) {
+        const size_t c = DevPool::size_class(n);
+        auto it = free.find(c);
+        if (it != free.end() && !it->second.empty()) {
+            *p = it->second.back();
+            it->second.pop_back();
+            *cap = c;
+            return hipSuccess;
+        }
+        *cap = c;
+        return hipHostMalloc(p, c, hipHostMallocDefault);
+    }
+    void put(void *p, size_t cap) {
+        if (p) free[cap].push_back(p);
+    }
+    ~PinPool() {
+        for (auto &kv : free)
+            for (void *p : kv.second) (void)hipHostFree(p);
+    }
+};
+
+struct PinBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
 struct Request {
     uint64_t ticket = 0;
     mrs_request spec{};
@@ -42,23 +84,36 @@ struct Request {
     std::vector<double> X, D, f, n;
     mrs_ensemble *ens = nullptr;
     int64_t N = 0;
-    int32_t steps_done = 0;
+    int32_t steps_done = 0;  // units of work queued (steps, or 1 for an evaluation)
     int64_t footprint = -1;
     mrs_result_info info{};
     bool done = false;
+    bool launched_all = false;  // every unit queued; waiting for retirement
     double credit = 0.0;  // pair budget earned and not yet spent (deficit round robin)
     int64_t cost = 0;     // pair interactions of one unit of work (eval or step)
+    hipEvent_t up_event = nullptr;  // upload finished (the first tick waits for it)
+    bool up_wait = false;           // the next tick that runs it must wait for up_event
+    PinBuf pin_in, pin_out;         // pinned staging of the upload and of the results
     std::vector<double> Xo, Do, Uo, Wo;
 };
 
-// Work lists of one tick over the admitted set.
+// Work lists of one tick over a set of requests.
 struct TickPlan {
-    std::vector<uint64_t> key;  // ensemble uids of the admitted set, in order
-    Plan all;       // stage 0 over every admitted request
+    std::vector<uint64_t> key;  // ensemble uids of the set, in order
+    Plan all;       // stage 0 over every request of the set
     Plan rk[2];     // later stages of the RK4 (scheme 0) and RK2 (scheme 1) step requests
     std::vector<PointItem> pts_write, pts_euler, pts_rk0[2];
     DevBuf d_pts_write, d_pts_euler, d_pts_rk0[2];
     bool has_rk[2] = {false, false};
+    int64_t last_tick = -1;  // the last tick that used it (it may be freed once that tick is done)
+};
+
+// A tick queued on the device.
+struct Tick {
+    int64_t index = 0;
+    hipEvent_t start = nullptr, done = nullptr;
+    std::vector<Request *> finishing;  // requests whose last unit ran in it (results copied after it)
+    int64_t pairs = 0;
 };
 
 }  // namespace
@@ -72,20 +127,43 @@ struct mrs_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> queue;
-    std::vector<Request *> active;
+    std::vector<Request *> active;  // admitted and not retired
     std::map<uint64_t, Request *> table;
     int64_t in_use = 0;
     uint64_t next_ticket = 1;
     bool stopping = false;
     mrs_server_stats st{};
+    double t_start = 0.0;
     int64_t fail_tick = -1;
     std::atomic<int64_t> tick_pairs{0};  // 0 = no per-tick bound
-    // tick plans of recently used request sets (small LRU)
+    // scheduler-thread state
+    hipStream_t up_stream = nullptr;
+    DevPool pool;
+    PinPool pins;
+    std::vector<hipEvent_t> events;  // idle events
+    std::deque<Tick> in_flight;
+    int64_t ticks_launched = 0, ticks_completed = 0;
+    // tick plans of recently used request sets (small LRU); declared after
+    // the pool, so that they return their arrays to it before it is freed
     std::vector<std::unique_ptr<TickPlan>> plans;
-    TickPlan *plan = nullptr;
 };
 
 namespace {
+
+hipEvent_t take_event(mrs_server *S) {
+    if (!S->events.empty()) {
+        hipEvent_t e = S->events.back();
+        S->events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void give_event(mrs_server *S, hipEvent_t e) {
+    if (e) S->events.push_back(e);
+}
 
 int64_t request_footprint(mrs_context *ctx, int prec, const Request &r) {
     PairCfg c = choose_cfg(ctx, r.N, prec);
@@ -103,17 +181,22 @@ hipError_t upload_list(DevBuf &d, const std::vector<T> &v) {
 
 constexpr size_t kPlanCache = 16;
 
-// Tick plan of the requests `run` (cached per set; the cache is small LRU).
-mrs_status build_tick_plan(mrs_server *S, const std::vector<Request *> &run) {
+// Tick plan of the requests `run` (cached per set; the cache is small LRU and
+// never frees a plan that a tick still queued on the device may use).
+mrs_status tick_plan(mrs_server *S, const std::vector<Request *> &run, TickPlan **out) {
     std::vector<uint64_t> key;
     for (auto *r : run) key.push_back(r->ens->uid);
     for (size_t i = 0; i < S->plans.size(); i++)
         if (S->plans[i]->key == key) {
             std::rotate(S->plans.begin(), S->plans.begin() + i, S->plans.begin() + i + 1);
-            S->plan = S->plans.front().get();
+            *out = S->plans.front().get();
             return MRS_OK;
         }
     auto T = std::make_unique<TickPlan>();
+    plan_use_pool(T->all, &S->pool);
+    plan_use_pool(T->rk[0], &S->pool);
+    plan_use_pool(T->rk[1], &S->pool);
+    for (DevBuf *b : {&T->d_pts_write, &T->d_pts_euler, &T->d_pts_rk0[0], &T->d_pts_rk0[1]}) b->pool = &S->pool;
     T->key = key;
     T->all.prec = T->rk[0].prec = T->rk[1].prec = S->prec;
     for (size_t e = 0; e < run.size(); e++) {
@@ -148,34 +231,38 @@ mrs_status build_tick_plan(mrs_server *S, const std::vector<Request *> &run) {
         if (he == hipSuccess) he = upload_list(T->d_pts_rk0[k], T->pts_rk0[k]);
     if (he != hipSuccess) return fail(S->ctx, MRS_EDEVICE, "tick plan upload: %s", hipGetErrorString(he));
     S->plans.insert(S->plans.begin(), std::move(T));
-    if (S->plans.size() > kPlanCache) S->plans.pop_back();
-    S->plan = S->plans.front().get();
+    // evict the least recently used plans beyond the cache size whose last tick is done
+    for (size_t i = S->plans.size(); i-- > kPlanCache;)
+        if (S->plans[i]->last_tick < S->ticks_completed) S->plans.erase(S->plans.begin() + i);
+    *out = S->plans.front().get();
     return MRS_OK;
 }
 
-// Forget cached plans that mention a retired request's ensemble.
+// Forget cached plans that mention a retired request's ensemble (their last
+// tick is done: the request's own last tick came after every tick using it).
 void drop_plans(mrs_server *S, uint64_t uid) {
     for (auto it = S->plans.begin(); it != S->plans.end();) {
         const auto &k = (*it)->key;
         if (std::find(k.begin(), k.end(), uid) != k.end()) it = S->plans.erase(it);
         else ++it;
     }
-    S->plan = nullptr;
 }
 
 int evals_per_unit(const Request *r) {
     return (r->spec.kind == MRS_REQ_STEPS && r->spec.integ != MRS_EULER) ? rk_stages(r->spec.integ) : 1;
 }
 
-// Requests that advance in this tick: all of them without a tick bound; with
-// one, deficit round robin over the admitted requests.
-std::vector<Request *> pick_tick(mrs_server *S) {
+int32_t units(const Request *r) { return r->spec.kind == MRS_REQ_EVAL ? 1 : r->spec.nsteps; }
+
+// Requests that advance in the next tick: every launchable one without a tick
+// bound; with one, deficit round robin over them.
+std::vector<Request *> pick_tick(mrs_server *S, const std::vector<Request *> &cand) {
     const int64_t budget = S->tick_pairs.load();
-    if (budget <= 0) return S->active;
+    if (budget <= 0) return cand;
     std::vector<Request *> run;
-    const double quantum = (double)budget / (double)S->active.size();
+    const double quantum = (double)budget / (double)cand.size();
     Request *best = nullptr;
-    for (auto *r : S->active) {
+    for (auto *r : cand) {
         r->credit += quantum;
         if (r->credit >= (double)r->cost) run.push_back(r);
         if (!best || r->credit / (double)r->cost > best->credit / (double)best->cost) best = r;
@@ -185,9 +272,8 @@ std::vector<Request *> pick_tick(mrs_server *S) {
     return run;
 }
 
-hipError_t launch_tick(mrs_server *S) {
+hipError_t launch_tick(mrs_server *S, TickPlan &T) {
     mrs_context *ctx = S->ctx;
-    TickPlan &T = *S->plan;  // set by build_tick_plan
     hipStream_t s = ctx->stream;
     const double nan = std::nan("");
     hipError_t e = timed(ctx, "rod_forces", s, [&] {
@@ -215,7 +301,6 @@ hipError_t launch_tick(mrs_server *S) {
         for (int st = 1; e == hipSuccess && T.has_rk[k] && st < nst; st++)
             e = run_stage(ctx, T.rk[k], 1, -1, st < nst - 1 ? EPI_RK_STAGE : EPI_RK_FINAL, st, k, nan, s);
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e;
 }
 
@@ -248,128 +333,267 @@ std::vector<Request *> select_admissions(mrs_server *S) {
     return pick;
 }
 
-// Copy the picked requests to the device.  Caller holds the context lock only.
-void create_ensembles(mrs_server *S, std::vector<Request *> &pick) {
-    for (auto *r : pick) {
-        const mrs_request &q = r->spec;
-        mrs_ensemble *ens = nullptr;
-        mrs_status st = mrs_ensemble_create(S->ctx, q.n_fil, r->off.data(), r->X.data(), r->D.data(),
-                                            r->f.empty() ? nullptr : r->f.data(),
-                                            r->n.empty() ? nullptr : r->n.data(), q.eps, q.mu, &q.rod, &ens);
-        r->info.t_admit = now_s();
-        r->info.status = st == MRS_OK ? MRS_ENOTREADY : st;
-        r->ens = ens;
-        std::vector<double>().swap(r->X);  // inputs now live on the device
-        std::vector<double>().swap(r->D);
-        std::vector<double>().swap(r->f);
-        std::vector<double>().swap(r->n);
+// Device state of an admitted request: arrays from the cache, the inputs
+// staged in pinned memory (spatial order, SoA) and copied on the upload
+// stream; r->up_event fires when they are on the device.
+mrs_status admit(mrs_server *S, Request *r) {
+    mrs_context *ctx = S->ctx;
+    const mrs_request &q = r->spec;
+    const int64_t n = r->N;
+    const bool ext = !r->f.empty();
+    std::vector<int32_t> soff;
+    std::vector<int64_t> perm;
+    spatial_order(q.n_fil, r->off.data(), r->X.data(), soff, perm);
+    std::unique_ptr<mrs_ensemble> E;
+    mrs_status st = ensemble_alloc(ctx, q.n_fil, soff.data(), q.eps, q.mu, &q.rod, ext, E, &S->pool, false);
+    if (st != MRS_OK) return st;
+    E->perm = std::move(perm);
+    // staging: X (3n), D (9n), [fext (3n), next (3n)], clock, offsets
+    const size_t nd = (size_t)n * (12 + (ext ? 6 : 0)) + 1;
+    const size_t bytes = nd * sizeof(double) + (size_t)(q.n_fil + 1) * sizeof(int32_t);
+    if (S->pins.get(bytes, &r->pin_in.p, &r->pin_in.cap) != hipSuccess) {
+        r->pin_in = PinBuf{};
+        return fail(ctx, MRS_ENOMEM, "pinned staging (%zu bytes)", bytes);
     }
+    double *h = static_cast<double *>(r->pin_in.p);
+    aos_to_soa(r->X.data(), h, n, 3, E->perm);
+    aos_to_soa(r->D.data(), h + 3 * n, n, 9, E->perm);
+    if (ext) {
+        aos_to_soa(r->f.data(), h + 12 * n, n, 3, E->perm);
+        aos_to_soa(r->n.data(), h + 15 * n, n, 3, E->perm);
+    }
+    h[nd - 1] = 0.0;  // clock
+    std::memcpy(h + nd, soff.data(), (size_t)(q.n_fil + 1) * sizeof(int32_t));
+    hipStream_t u = S->up_stream;
+    const size_t v3 = (size_t)n * 3 * sizeof(double);
+    hipError_t he = hipMemcpyAsync(E->X.p, h, v3, hipMemcpyHostToDevice, u);
+    if (he == hipSuccess) he = hipMemcpyAsync(E->D.p, h + 3 * n, 3 * v3, hipMemcpyHostToDevice, u);
+    if (he == hipSuccess && ext) he = hipMemcpyAsync(E->fext.p, h + 12 * n, v3, hipMemcpyHostToDevice, u);
+    if (he == hipSuccess && ext) he = hipMemcpyAsync(E->next.p, h + 15 * n, v3, hipMemcpyHostToDevice, u);
+    if (he == hipSuccess) he = hipMemcpyAsync(E->clock.p, h + nd - 1, sizeof(double), hipMemcpyHostToDevice, u);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(E->off.p, h + nd, (size_t)(q.n_fil + 1) * sizeof(int32_t), hipMemcpyHostToDevice, u);
+    if (he == hipSuccess) he = hipMemsetAsync(E->U.p, 0, v3, u);
+    if (he == hipSuccess) he = hipMemsetAsync(E->W.p, 0, v3, u);
+    if (he == hipSuccess && !(r->up_event = take_event(S))) he = hipErrorOutOfMemory;
+    if (he == hipSuccess) he = hipEventRecord(r->up_event, u);
+    ctx->ensembles.push_back(E.get());
+    r->ens = E.release();
+    if (he != hipSuccess) return fail(ctx, MRS_EDEVICE, "request upload: %s", hipGetErrorString(he));
+    r->up_wait = true;
+    std::vector<double>().swap(r->X);  // inputs now live on the device
+    std::vector<double>().swap(r->D);
+    std::vector<double>().swap(r->f);
+    std::vector<double>().swap(r->n);
+    return MRS_OK;
 }
 
-// Copy results of a finished request to host and free its device state;
-// a result with a non-finite value completes with MRS_ENUMERIC.  Caller
-// holds the context lock only.
-void collect(Request *r, mrs_status status) {
-    if (status == MRS_OK && r->ens) {
-        r->Xo.resize((size_t)r->N * 3);
-        r->Do.resize((size_t)r->N * 9);
-        r->Uo.resize((size_t)r->N * 3);
-        r->Wo.resize((size_t)r->N * 3);
-        status = mrs_ensemble_get(r->ens, r->Xo.data(), r->Do.data(), r->Uo.data(), r->Wo.data());
+// Queue the copy of a finishing request's state and velocities to pinned
+// memory after the tick's kernels (compute stream).
+hipError_t queue_results(mrs_server *S, Request *r) {
+    mrs_ensemble *E = r->ens;
+    const size_t v3 = (size_t)r->N * 3 * sizeof(double);
+    if (S->pins.get(6 * v3, &r->pin_out.p, &r->pin_out.cap) != hipSuccess) {
+        r->pin_out = PinBuf{};
+        return hipErrorOutOfMemory;
     }
-    if (r->ens) mrs_ensemble_destroy(r->ens);
-    r->ens = nullptr;
+    char *h = static_cast<char *>(r->pin_out.p);
+    hipStream_t s = S->ctx->stream;
+    hipError_t e = hipMemcpyAsync(h, E->X.p, v3, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + v3, E->D.p, 3 * v3, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + 4 * v3, E->U.p, v3, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + 5 * v3, E->W.p, v3, hipMemcpyDeviceToHost, s);
+    return e;
+}
+
+// A request leaves the device: results (if any) reordered for the caller,
+// device arrays and pinned buffers back to the caches.  No queued device
+// work uses it any more.
+void retire(mrs_server *S, Request *r, mrs_status status) {
+    if (status == MRS_OK && r->ens && r->pin_out.p) {
+        const int64_t n = r->N;
+        const double *h = static_cast<const double *>(r->pin_out.p);
+        r->Xo.resize((size_t)n * 3);
+        r->Do.resize((size_t)n * 9);
+        r->Uo.resize((size_t)n * 3);
+        r->Wo.resize((size_t)n * 3);
+        soa_to_aos(h, r->Xo.data(), n, 3, r->ens->perm);
+        soa_to_aos(h + 3 * n, r->Do.data(), n, 9, r->ens->perm);
+        soa_to_aos(h + 12 * n, r->Uo.data(), n, 3, r->ens->perm);
+        soa_to_aos(h + 15 * n, r->Wo.data(), n, 3, r->ens->perm);
+        status = check_host_finite(S->ctx, h, (size_t)n * 18, "result");  // MRS_ENUMERIC: results still returned
+    }
+    if (r->ens) {
+        drop_plans(S, r->ens->uid);
+        ensemble_detach(r->ens);
+        r->ens = nullptr;
+    }
+    S->pins.put(r->pin_in.p, r->pin_in.cap);
+    S->pins.put(r->pin_out.p, r->pin_out.cap);
+    r->pin_in = r->pin_out = PinBuf{};
+    give_event(S, r->up_event);
+    r->up_event = nullptr;
     r->info.status = status;
     r->info.steps_done = r->steps_done;
     r->info.t_done = now_s();
 }
 
+// Retire the requests of the oldest queued tick once it has finished (wait:
+// block until it has).  Returns false if there was none to retire.
+bool complete_tick(mrs_server *S, bool wait) {
+    if (S->in_flight.empty()) return false;
+    Tick &T = S->in_flight.front();
+    if (wait) (void)hipEventSynchronize(T.done);
+    else if (hipEventQuery(T.done) != hipSuccess) return false;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, T.start, T.done);
+    for (auto *r : T.finishing) retire(S, r, MRS_OK);
+    S->ticks_completed = T.index + 1;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->st.busy_s += 1e-3 * ms;
+        S->st.pairs += T.pairs;
+        for (auto *r : T.finishing) {
+            S->in_use -= r->footprint;
+            r->done = true;
+            S->st.completed++;
+        }
+        auto &A = S->active;
+        for (auto *r : T.finishing) A.erase(std::remove(A.begin(), A.end(), r), A.end());
+        if (!T.finishing.empty()) S->cv_done.notify_all();
+    }
+    give_event(S, T.start);
+    give_event(S, T.done);
+    S->in_flight.pop_front();
+    return true;
+}
+
+// Every request still on the device ends with `status` once the device has
+// drained; used when a tick cannot be queued.
+void fail_all(mrs_server *S, mrs_status status) {
+    (void)hipStreamSynchronize(S->ctx->stream);
+    (void)hipStreamSynchronize(S->up_stream);
+    while (complete_tick(S, true)) {
+    }
+    std::vector<Request *> act;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        act = S->active;
+    }
+    for (auto *r : act) retire(S, r, status);
+    S->plans.clear();
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (auto *r : act) {
+        S->in_use -= r->footprint;
+        r->done = true;
+        S->st.completed++;
+    }
+    S->active.clear();
+    S->cv_done.notify_all();
+}
+
+// Queue one tick over the requests that still have units to launch; false
+// if there were none.
+bool queue_tick(mrs_server *S) {
+    std::vector<Request *> cand;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto *r : S->active)
+            if (!r->launched_all) cand.push_back(r);
+    }
+    if (cand.empty()) return false;
+    const int64_t index = S->ticks_launched++;
+    for (auto *r : cand)
+        if (r->cost == 0) r->cost = (int64_t)evals_per_unit(r) * r->N * r->N;
+    std::vector<Request *> run = pick_tick(S, cand);
+    if (index + 1 == S->fail_tick) {  // forced failure: nothing queued, every request keeps its state
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->st.ticks++;
+        S->st.failed_ticks++;
+        return true;
+    }
+    mrs_context *ctx = S->ctx;
+    hipStream_t s = ctx->stream;
+    TickPlan *TP = nullptr;
+    mrs_status st = tick_plan(S, run, &TP);
+    Tick T;
+    T.index = index;
+    hipError_t he = st == MRS_OK ? hipSuccess : hipErrorUnknown;
+    for (auto *r : run)
+        if (he == hipSuccess && r->up_wait) {
+            he = hipStreamWaitEvent(s, r->up_event, 0);
+            r->up_wait = false;
+        }
+    if (he == hipSuccess && !((T.start = take_event(S)) && (T.done = take_event(S)))) he = hipErrorOutOfMemory;
+    if (he == hipSuccess) he = hipEventRecord(T.start, s);
+    if (he == hipSuccess) he = launch_tick(S, *TP);
+    if (he == hipSuccess) {
+        TP->last_tick = index;
+        for (auto *r : run) {
+            T.pairs += r->cost;
+            if (++r->steps_done >= units(r)) {
+                r->launched_all = true;
+                T.finishing.push_back(r);
+                if ((he = queue_results(S, r)) != hipSuccess) break;
+            }
+        }
+    }
+    if (he == hipSuccess) he = hipEventRecord(T.done, s);
+    if (he != hipSuccess) {
+        give_event(S, T.start);
+        give_event(S, T.done);
+        if (st == MRS_OK) (void)fail(ctx, MRS_EDEVICE, "tick: %s", hipGetErrorString(he));
+        fail_all(S, st != MRS_OK ? st : MRS_EDEVICE);
+        return true;
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->st.ticks++;
+    }
+    S->in_flight.push_back(std::move(T));
+    return true;
+}
+
 void loop(mrs_server *S) {
     (void)hipSetDevice(S->ctx->device);
-    int64_t tick = 0;
     for (;;) {
         std::vector<Request *> pick;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             pick = select_admissions(S);
-            if (S->active.empty() && pick.empty()) {
+            if (S->active.empty() && pick.empty() && S->in_flight.empty()) {
                 if (S->stopping) break;
                 S->cv_work.wait_for(lk, std::chrono::milliseconds(20));
                 continue;
             }
         }
         std::lock_guard<std::recursive_mutex> ctxlk(S->ctx->mu);
-        if (!pick.empty()) {
-            create_ensembles(S, pick);
+        for (auto *r : pick) {
+            const mrs_status st = admit(S, r);
+            r->info.t_admit = now_s();
+            if (st != MRS_OK) {
+                // nothing of it is queued on the compute stream; its uploads are drained
+                (void)hipStreamSynchronize(S->up_stream);
+                retire(S, r, st);
+            }
             std::lock_guard<std::mutex> lk(S->mu);
-            for (auto *r : pick) {
-                if (r->ens) {
-                    S->active.push_back(r);
-                    S->st.admitted++;
-                } else {
-                    S->in_use -= r->footprint;
-                    r->info.t_done = now_s();
-                    r->done = true;
-                    S->st.rejected++;
-                }
+            if (st == MRS_OK) {
+                r->info.status = MRS_ENOTREADY;
+                S->active.push_back(r);
+                S->st.admitted++;
+            } else {
+                S->in_use -= r->footprint;
+                r->done = true;
+                S->st.rejected++;
+                S->cv_done.notify_all();
             }
-            S->cv_done.notify_all();
         }
-        if (S->active.empty()) continue;
-        tick++;
-        for (auto *r : S->active)
-            if (r->cost == 0) r->cost = (int64_t)evals_per_unit(r) * r->N * r->N;
-        std::vector<Request *> run = pick_tick(S);
-        mrs_status st = build_tick_plan(S, run);
-        const double t0 = now_s();
-        hipError_t he = hipSuccess;
-        bool failed = false;
-        if (st == MRS_OK) {
-            if (tick == S->fail_tick) failed = true;  // forced failure: nothing launched, state unchanged
-            else he = launch_tick(S);
+        // retire what has finished, then keep kTicksInFlight ticks queued
+        while (complete_tick(S, false)) {
         }
-        const double t1 = now_s();
-        if (failed) {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->st.ticks++;
-            S->st.failed_ticks++;
-            continue;  // every request retries this tick from its step-boundary state
-        }
-        std::vector<Request *> keep, finished;
-        int64_t pairs = 0;
-        const bool ok = st == MRS_OK && he == hipSuccess;
-        for (auto *r : S->active) {
-            if (!ok) {
-                finished.push_back(r);
-                continue;
-            }
-            if (std::find(run.begin(), run.end(), r) == run.end()) {  // did not run this tick
-                keep.push_back(r);
-                continue;
-            }
-            pairs += r->cost;
-            const bool fin = r->spec.kind == MRS_REQ_EVAL || ++r->steps_done >= r->spec.nsteps;
-            (fin ? finished : keep).push_back(r);
-        }
-        for (auto *r : finished) {
-            if (r->ens) drop_plans(S, r->ens->uid);
-            collect(r, ok ? MRS_OK : (st != MRS_OK ? st : MRS_EDEVICE));
-        }
-        if (!ok) {
-            S->plans.clear();
-            S->plan = nullptr;
-        }
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->st.ticks++;
-        S->st.busy_s += t1 - t0;
-        S->st.pairs += pairs;
-        for (auto *r : finished) {
-            S->in_use -= r->footprint;
-            r->done = true;
-            S->st.completed++;
-        }
-        S->active.swap(keep);
-        if (!finished.empty()) S->cv_done.notify_all();
+        bool queued = false;
+        while ((int)S->in_flight.size() < kTicksInFlight && queue_tick(S)) queued = true;
+        if (!queued && !S->in_flight.empty()) complete_tick(S, true);  // nothing more to queue: wait for the oldest
     }
 }
 
@@ -409,7 +633,13 @@ mrs_status mrs_server_start(mrs_context *ctx, mrs_precision prec, int64_t hbm_bu
     S->budget = hbm_budget_bytes;
     S->max_slots = max_slots;
     S->st.hbm_budget = hbm_budget_bytes;
+    S->t_start = now_s();
     if (const char *v = std::getenv("MRS_DEBUG_FAIL_TICK")) S->fail_tick = std::atoll(v);
+    (void)hipSetDevice(ctx->device);
+    if (hipStreamCreateWithFlags(&S->up_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete S;
+        return fail(ctx, MRS_EDEVICE, "upload stream");
+    }
     S->th = std::thread(loop, S);
     *out = S;
     return MRS_OK;
@@ -519,6 +749,7 @@ mrs_status mrs_server_stats_get(mrs_server *S, mrs_server_stats *out) {
     out->active = (int32_t)S->active.size();
     out->queued = (int32_t)S->queue.size();
     out->hbm_in_use = S->in_use;
+    out->wall_s = now_s() - S->t_start;
     return MRS_OK;
 }
 
@@ -535,8 +766,12 @@ mrs_status mrs_server_stop(mrs_server *S) {
         S->cv_work.notify_all();
     }
     if (S->th.joinable()) S->th.join();
+    (void)hipStreamSynchronize(S->ctx->stream);
+    (void)hipStreamSynchronize(S->up_stream);
     for (auto &kv : S->table) delete kv.second;
     S->plans.clear();
+    for (auto e : S->events) (void)hipEventDestroy(e);
+    if (S->up_stream) (void)hipStreamDestroy(S->up_stream);
     delete S;
     return MRS_OK;
 }

@@ -102,6 +102,50 @@ def test_served_equals_alone(mrs, prec, tick_pairs):
         mrs.mrs_context_destroy(ctx)
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_large_and_long_requests_served_equal_alone(mrs, prec):
+    """Requests at the serving workload's extremes in one mix, under a tick
+    pair budget (deficit round robin): an evaluation of 400 filaments x 256
+    points (102,400 points), a request of 50 RK4 steps and a 10-step RK2 one.
+    Each result equals the same request run alone, bit for bit; the large
+    evaluation also matches the oracle on 512 seeded targets."""
+    ctx = mrs.mrs_context_create(0)
+    try:
+        big = synth.filaments(400, 256, 10.0, 610)
+        reqs = [(big, 0, "RK4"), (synth.filaments(4, 128, 10.0, 611), 1, "RK4"),
+                (synth.filaments(20, 100, 10.0, 612), 1, "RK2")]
+        steps = [1, 50, 10]
+        srv = mrs.mrs_server_start(ctx, prec, 8 << 30, 16)
+        mrs.mrs_server_set_tick_pairs(srv, 2_000_000_000)
+        try:
+            tickets = [mrs.mrs_server_submit(srv, kind, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu,
+                                             rod_of(mrs, e.rod()), dt=1e-5, nsteps=ns, integ=getattr(mrs, "MRS_" + integ))
+                       for (e, kind, integ), ns in zip(reqs, steps)]
+            served = []
+            for (e, kind, integ), t in zip(reqs, tickets):
+                st, info, out = mrs.mrs_server_wait(srv, t, e.N, timeout_s=120)
+                assert st == mrs.MRS_OK, st
+                served.append(out)
+            stats = mrs.mrs_server_stats_get(srv)
+        finally:
+            mrs.mrs_server_stop(srv)
+        say(f"prec={prec}: {stats['ticks']} ticks, {stats['pairs']:.3e} pairs")
+        for (e, kind, integ), ns, out in zip(reqs, steps, served):
+            alone = _alone(mrs, ctx, e, kind, integ, prec, ns, 1e-5)
+            for name, x, y in zip("XDUW", out, alone):
+                np.testing.assert_array_equal(x, y, err_msg=f"N={e.N} {name}")
+            say(f"N={e.N} kind={kind} {integ} x{ns}: served == alone")
+        idx = np.sort(np.random.default_rng(613).choice(big.N, 512, replace=False))
+        g, m = oracle.rod_forces(big.offsets, big.X, big.D, big.rod(), big.f, big.n)
+        Uo, Wo = oracle.mrs_field(big.X[idx], big.X, g, m, big.eps, big.mu)
+        tol = 1e-5 if prec == 1 else 1e-12
+        eu, ew = oracle.rel_err(served[0][2][idx], Uo), oracle.rel_err(served[0][3][idx], Wo)
+        say(f"102,400-point served evaluation vs oracle (512 targets): U {eu:.3e} W {ew:.3e}")
+        assert eu <= tol and ew <= tol
+    finally:
+        mrs.mrs_context_destroy(ctx)
+
+
 def test_admission_by_hbm_budget(mrs):
     ctx = mrs.mrs_context_create(0)
     try:
