@@ -335,6 +335,57 @@ def oracle_large_subset(subset):
                       f"({dt:.1f} s)"}, errs
 
 
+def bench_tune(mrs, sizes, reps=7, tune_reps=5):
+    """The tuner against the automatic configuration: for each size (sinusoidal
+    128-point filaments at the density of 100 in a box of side 10; the tuner
+    itself times straight ones) and precision, mrs_autotune in a fresh
+    context, then `reps` interleaved evaluations (mrs_eval_device, device time
+    of all its kernels) with the automatic entry and with the tuned one."""
+    import torch
+
+    import synth
+
+    rows = []
+    for n in sizes:
+        F = n // 128
+        e = synth.filaments(F, 128, 10.0 * (F / 100.0) ** (1.0 / 3.0), 4000 + F)
+        dX, df, dn = (torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0") for a in (e.X, e.f, e.n))
+        dU, dW = torch.empty_like(dX), torch.empty_like(dX)
+        s = torch.cuda.current_stream()
+        for prec, tag in ((mrs.MRS_FP32C, "fp32c"), (mrs.MRS_FP64, "fp64")):
+            ctx = mrs.mrs_context_create(0)
+            try:
+                auto = mrs.mrs_tune_get(ctx, e.N, prec)
+                auto_entry = (auto["mode"], auto["targets_per_lane"], 1 if auto["mode"] == 1 else 0, 0)
+                log(f"tune N={e.N} {tag}: automatic {auto}")
+                t0 = time.perf_counter()
+                best, best_ms = mrs.mrs_autotune(ctx, e.N, prec, tune_reps)
+                tune_s = time.perf_counter() - t0
+                tuned = mrs.mrs_tune_get(ctx, e.N, prec)
+                entry = (best["mode"], best["targets_per_lane"], best["chunks"], best["schedule"])
+                times = {"automatic": [], "tuned": []}
+                for r in range(reps + 1):
+                    for name, cfg in (("automatic", auto_entry), ("tuned", entry)):
+                        mrs.mrs_tune_set(ctx, e.N, prec, *cfg)
+                        mrs.mrs_profile_reset(ctx)
+                        mrs.mrs_profile_select(ctx, "")
+                        mrs.mrs_profile_enable(ctx, True)
+                        mrs.mrs_eval_device(ctx, e.N, dX, df, dn, e.eps, e.mu, prec, dU, dW, s)
+                        mrs.mrs_profile_enable(ctx, False)
+                        _, ms = mrs.mrs_profile_query(ctx)
+                        if r > 0:
+                            times[name].append(ms)
+                mrs.mrs_profile_reset(ctx)
+                a, t = float(np.median(times["automatic"])), float(np.median(times["tuned"]))
+                rows.append({"n_points": e.N, "prec": tag, "automatic": auto, "tuned": tuned,
+                             "automatic_us": 1e3 * a, "tuned_us": 1e3 * t, "ratio": t / a,
+                             "tuner_best_us": 1e3 * best_ms, "tune_s": tune_s})
+                log(f"  tuned {tuned} in {tune_s:.1f} s: automatic {1e3 * a:.1f} us, tuned {1e3 * t:.1f} us")
+            finally:
+                mrs.mrs_context_destroy(ctx)
+    return rows
+
+
 def bench_slices(mrs, ctx, steps, args):
     """16 Parareal fine slices (32 x 100 points each), RK4 at dt = 1e-5, FP32C:
     one batched launch sequence replayed from HIP graphs vs one launch per
@@ -516,7 +567,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ens12800",
                     choices=["rod64", "ens12800", "ens256000", "swim", "swim25", "slices", "serving", "parareal",
-                             "copy"])
+                             "copy", "tune"])
     ap.add_argument("--requests", type=int, default=32, help="serving: prefix of the request sequence")
     ap.add_argument("--rates", default="10,100,1000", help="serving: Poisson arrival rates (req/s)")
     ap.add_argument("--slots", type=int, default=64)
@@ -558,6 +609,17 @@ def main():
                           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
                           "config": {"workload": "copy of 256 MiB float64", "bytes_read": nbytes,
                                      "bytes_written": nbytes}}), flush=True)
+        return
+    if args.workload == "tune":
+        sizes = (1536, 3200, 6400, 12800, 25600, 51200, 102400, 256000)
+        rows = bench_tune(mrs, sizes)
+        worst = max(r["ratio"] for r in rows)
+        print(json.dumps({"metric": "pair-kernel tuner: tuned / automatic evaluation time, worst size",
+                          "value": worst, "unit": "ratio", "n_gpus": 1, "steps": 7, "warmup": 1,
+                          "ms_per_step": None, "higher_is_better": False, "scaling": "strong",
+                          "vs_baseline": None, "dtype": "f32c+f64", "data": "synthetic",
+                          "config": {"workload": "tuner: sinusoidal 128-point filaments, 1,536 to 256,000 points"},
+                          "tune": rows}), flush=True)
         return
     if args.workload in ("slices", "serving", "parareal"):
         ctx = mrs.mrs_context_create(0)

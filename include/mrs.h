@@ -77,8 +77,14 @@ typedef enum { MRS_FP64 = 0, MRS_FP32C = 1 } mrs_precision;
 /* Forward Euler (Eqs. newx, newD), the second-order Runge-Kutta method of
  * the paper's fine propagator (Sec. III.A, n = 2; midpoint rule) and the
  * classical four-stage Runge-Kutta method.  Runge-Kutta stage states are
- * X_s = X + c_s dt U_{s-1}, D_s = Rod(c_s dt Omega_{s-1}) D; a step ends with
- * X += dt sum w_s U_s, D = Rod(dt sum w_s Omega_s) D (Rod = Eq. newD). */
+ * X_s = X + c_s dt U_{s-1}, D_s = Rod(c_s dt k_{s-1}) D; a step ends with
+ * X += dt sum w_s U_s, D = Rod(dt sum w_s k_s) D (Rod = Eq. newD), where
+ * k_s = Omega_s for RK2 and, for RK4, the Runge-Kutta-Munthe-Kaas form
+ * k_0 = Omega_0, k_s = Omega_s - theta_s x Omega_s / 2 +
+ * theta_s x (theta_s x Omega_s) / 12 with theta_s = c_s dt k_{s-1}.  Orders:
+ * 1, 2 and 4 in positions and frames, also with the rod forces on (without
+ * the correction the RK4 frames, and through the rod forces the positions,
+ * would be second order once Omega varies within a step). */
 typedef enum { MRS_EULER = 1, MRS_RK2 = 2, MRS_RK4 = 4 } mrs_integrator;
 
 /* Rod moduli (Sec. II.A, Eq. constitutive_N_F): a = bending, bending, twist;
@@ -347,12 +353,47 @@ typedef struct {
 } mrs_pair_config;
 
 /* Time candidate configurations on a seeded synthetic ensemble of n points
- * in precision `prec` (each candidate `reps` times, median kept) and store
- * the fastest for every n of the same power-of-two size class.  *best (may
- * be NULL) receives it and *best_ms its median pair-kernel time.  Ensembles
- * already created keep the configuration they were planned with. */
+ * (straight 128-point filaments at the density of 100 in a box of side 10)
+ * in precision `prec` and store the fastest for every n of the same
+ * power-of-two size class.  The candidates are the automatic configuration
+ * itself (stored as chunks = 0, which keeps its chunking and tail split),
+ * one and two targets per lane with automatic chunking on either schedule
+ * and with the chunk counts that give 1 to 64 blocks per compute unit, the
+ * four-wave split (FP32C) and, up to 8,192 points, the wave-split mode.
+ * The time of a candidate is the device time of one mrs_eval_device call
+ * (every kernel of it).  Every candidate runs once; the fastest quarter (at
+ * least four) and the automatic configuration then run `reps` (1..20)
+ * more times each, interleaved, and the medians decide.  The automatic
+ * configuration is kept unless another is more than 1% faster, so a tuned
+ * size class is never measurably slower than an untuned one.  *best (may be
+ * NULL) receives the stored configuration and *best_ms its median time.
+ * Ensembles already planned keep the configuration they were planned with.
+ * With a table file set by mrs_tune_on_first_use the file is rewritten. */
 mrs_status mrs_autotune(mrs_context *ctx, int64_t n, mrs_precision prec, int32_t reps,
                         mrs_pair_config *best, double *best_ms);
+/* Tune on first use: with reps > 0, a size class without a stored
+ * configuration is tuned (mrs_autotune with `reps`) when a plan of an
+ * ensemble of that class is first built, i.e. on the first
+ * mrs_ensemble_eval, mrs_ensemble_step, mrs_batch_step or mrs_parareal call
+ * for it in a precision; reps = 0 (the default) turns this off.  Never
+ * while the context's stream is being captured, and never for mrs_eval_device,
+ * mrs_eval_device_noalloc, mrs_eval_host or the server, which use the table
+ * or the automatic configuration as it stands.  table_path (may be NULL):
+ * a tuning table file (format of mrs_tune_save) that is read now if it
+ * exists, and rewritten after every tuning.  Errors: MRS_EINVAL for reps
+ * outside 0..20 or a table that cannot be read or was written for another
+ * device kind (architecture name and compute-unit count). */
+mrs_status mrs_tune_on_first_use(mrs_context *ctx, int32_t reps, const char *table_path);
+/* Write the tuning table to `path` (text: a header line
+ * "mrs-pair-tuning 1 <architecture> <compute units> <unix time>", then one
+ * line per entry: precision, log2 size class, mode, targets_per_lane,
+ * chunks, schedule, tuned and automatic median ms (-1 if set by hand);
+ * written to path.tmp and renamed).  Read one back with mrs_tune_load,
+ * which adds its entries (replacing those of the same class) or changes
+ * nothing and returns MRS_EINVAL if the file is malformed or from another
+ * device kind. */
+mrs_status mrs_tune_save(mrs_context *ctx, const char *path);
+mrs_status mrs_tune_load(mrs_context *ctx, const char *path);
 /* Host only (no device is touched): the pair-kernel work list that the
  * automatic configuration builds for one ensemble of n points on a device
  * with n_cu compute units, in dispatch order.  *mode, *targets_per_lane,

@@ -548,7 +548,7 @@ void oracle_step_ex(int32_t nfil, const int32_t *off, double *X, double *D,
     int64_t n = off[nfil];
     size_t v3 = sizeof(double) * 3 * (size_t)n, v9 = sizeof(double) * 9 * (size_t)n;
     double *U = malloc(v3), *W = malloc(v3), *Ua = malloc(v3), *Wa = malloc(v3);
-    double *Xs = malloc(v3), *Ds = malloc(v9);
+    double *Xs = malloc(v3), *Ds = malloc(v9), *K = malloc(v3);
     for (int32_t step = 0; step < nsteps; step++) {
         if (integrator == 1) {
             oracle_velocities_ex(nfil, off, X, D, a, b, om0, ds, fext, next, eps, mu, include_elastic, wave, tnow,
@@ -582,6 +582,23 @@ void oracle_step_ex(int32_t nfil, const int32_t *off, double *X, double *D,
                     if (Uout) memcpy(Uout, U, v3);
                     if (Wout) memcpy(Wout, W, v3);
                 }
+                if (nstage == 4 && s > 0) {
+                    /* Runge-Kutta-Munthe-Kaas: the stage frame is exp(theta) D with
+                     * theta = c_s dt k_{s-1}; the angular velocity there enters as
+                     * k_s = dexp^{-1}_theta(Omega) = Omega - theta x Omega / 2 +
+                     * theta x (theta x Omega) / 12 (the inverse derivative of the
+                     * exponential map on so(3), truncated after the terms a
+                     * fourth-order method needs); W holds k_{s-1} on entry to the
+                     * stage and k_s after it */
+                    for (int64_t k = 0; k < n; k++) {
+                        double th[3], t1[3], t2[3];
+                        for (int c = 0; c < 3; c++) th[c] = cnode[s] * dt * K[3 * k + c];
+                        cross3(th, &W[3 * k], t1);
+                        cross3(th, t1, t2);
+                        for (int c = 0; c < 3; c++) W[3 * k + c] = W[3 * k + c] - 0.5 * t1[c] + t2[c] / 12.0;
+                    }
+                }
+                if (nstage == 4) memcpy(K, W, v3);
                 for (int64_t i = 0; i < 3 * n; i++) {
                     Ua[i] += wgt[s] * U[i];
                     Wa[i] += wgt[s] * W[i];
@@ -595,7 +612,7 @@ void oracle_step_ex(int32_t nfil, const int32_t *off, double *X, double *D,
         tnow += dt;
     }
     if (t) *t = tnow;
-    free(U); free(W); free(Ua); free(Wa); free(Xs); free(Ds);
+    free(U); free(W); free(Ua); free(Wa); free(Xs); free(Ds); free(K);
 }
 
 void oracle_step(int32_t nfil, const int32_t *off, double *X, double *D,

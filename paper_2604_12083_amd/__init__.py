@@ -133,6 +133,9 @@ _SIGS = {
                             ctypes.POINTER(_dbl)]),
     "mrs_tune_get": (_int, [_vp, _i64, _int, ctypes.POINTER(mrs_pair_config)]),
     "mrs_tune_set": (_int, [_vp, _i64, _int, ctypes.POINTER(mrs_pair_config)]),
+    "mrs_tune_on_first_use": (_int, [_vp, ctypes.c_int32, ctypes.c_char_p]),
+    "mrs_tune_save": (_int, [_vp, ctypes.c_char_p]),
+    "mrs_tune_load": (_int, [_vp, ctypes.c_char_p]),
     "mrs_parareal": (_int, [_vp, ctypes.c_int32, _int, _dbl, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dbl,
                             _int, _int, _vp, ctypes.POINTER(ctypes.c_int32)]),
     "mrs_plan_items": (_int, [ctypes.c_int64, _int, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, _vp,
@@ -452,7 +455,8 @@ def mrs_server_stop(srv) -> None:
 
 
 def mrs_autotune(ctx, n, prec=MRS_FP32C, reps=3):
-    """Returns ({mode, targets_per_lane, chunks}, best pair-kernel ms)."""
+    """Returns ({mode, targets_per_lane, chunks, schedule}, median device ms
+    of one evaluation with it)."""
     c = mrs_pair_config()
     ms = _dbl()
     _check(_lib.mrs_autotune(ctx, int(n), int(prec), int(reps), ctypes.byref(c), ctypes.byref(ms)), ctx)
@@ -483,6 +487,22 @@ def mrs_plan_items(n, prec, n_cu=256):
 def mrs_tune_set(ctx, n, prec, mode, targets_per_lane=1, chunks=0, schedule=0) -> None:
     c = mrs_pair_config(int(mode), int(targets_per_lane), int(chunks), int(schedule))
     _check(_lib.mrs_tune_set(ctx, int(n), int(prec), ctypes.byref(c)), ctx)
+
+
+def mrs_tune_on_first_use(ctx, reps=3, table_path=None) -> None:
+    """Tune unseen size classes when an ensemble plan is first built (reps = 0
+    turns it off); table_path: tuning table read now and rewritten after every
+    tuning."""
+    path = None if table_path is None else os.fsencode(table_path)
+    _check(_lib.mrs_tune_on_first_use(ctx, int(reps), path), ctx)
+
+
+def mrs_tune_save(ctx, path) -> None:
+    _check(_lib.mrs_tune_save(ctx, os.fsencode(path)), ctx)
+
+
+def mrs_tune_load(ctx, path) -> None:
+    _check(_lib.mrs_tune_load(ctx, os.fsencode(path)), ctx)
 
 
 # ---- Parareal -----------------------------------------------------------

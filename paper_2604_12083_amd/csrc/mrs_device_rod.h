@@ -320,10 +320,19 @@ __device__ __forceinline__ void check_finite(const EnsDesc &E, const double *v, 
 // (re-orthonormalised); EPI_RK_STAGE accumulates the weighted stage sums and
 // builds the next stage state from the step-start state (xv, dv); EPI_RK_FINAL
 // finishes the step from the weighted sums (uav, wav: the sums so far).
+//
+// Frames under RK4 follow Runge-Kutta-Munthe-Kaas: stage s's frame is
+// exp(theta_s) D with theta_s = c_s dt k_{s-1}, and the angular velocity
+// Omega found there enters the stage sums and the next stage frame as
+// k_s = dexp^{-1}_{theta_s}(Omega) = Omega - theta_s x Omega / 2 +
+// theta_s x (theta_s x Omega) / 12 (the series of the inverse derivative of
+// the exponential map on so(3), cut after the terms a fourth-order method
+// needs; k_0 = Omega).  kv holds k_{s-1} (stage > 0); E.Ks receives k_s.
+// RK2 (midpoint) needs no correction for its order and uses Omega as is.
 template <int EPI>
 __device__ __forceinline__ void epilogue_point(const EnsDesc &E, int N, int i, const double *acc, const double *xv,
-                                               const double *dv, const double *uav, const double *wav, int stage,
-                                               int scheme, double dt) {
+                                               const double *dv, const double *uav, const double *wav,
+                                               const double *kv, int stage, int scheme, double dt) {
     FP_STRICT;
     const double U[3] = {acc[0] * E.cU, acc[1] * E.cU, acc[2] * E.cU};
     const double W[3] = {acc[3] * E.cW, acc[4] * E.cW, acc[5] * E.cW};
@@ -354,6 +363,16 @@ __device__ __forceinline__ void epilogue_point(const EnsDesc &E, int N, int i, c
     }
     // Runge-Kutta stage `stage` of `scheme`, evaluated at the stage state.
     const double wgt = kRkWeight[scheme][stage];
+    double k[3] = {W[0], W[1], W[2]};
+    if (scheme == 0 && stage > 0) {
+        const double c_dt = kRkNextNode[scheme][stage - 1] * dt;
+        const double th[3] = {c_dt * kv[0], c_dt * kv[1], c_dt * kv[2]};
+        const double t1[3] = {th[1] * W[2] - th[2] * W[1], th[2] * W[0] - th[0] * W[2], th[0] * W[1] - th[1] * W[0]};
+        const double t2[3] = {th[1] * t1[2] - th[2] * t1[1], th[2] * t1[0] - th[0] * t1[2],
+                              th[0] * t1[1] - th[1] * t1[0]};
+#pragma unroll
+        for (int c = 0; c < 3; c++) k[c] = W[c] - 0.5 * t1[c] + t2[c] / 12.0;
+    }
     double ua[3], wa[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -361,10 +380,10 @@ __device__ __forceinline__ void epilogue_point(const EnsDesc &E, int N, int i, c
             E.U[(size_t)c * N + i] = U[c];
             E.W[(size_t)c * N + i] = W[c];
             ua[c] = wgt * U[c];
-            wa[c] = wgt * W[c];
+            wa[c] = wgt * k[c];
         } else {
             ua[c] = uav[c] + wgt * U[c];
-            wa[c] = wav[c] + wgt * W[c];
+            wa[c] = wav[c] + wgt * k[c];
         }
     }
     if (EPI == EPI_RK_STAGE) {
@@ -374,8 +393,9 @@ __device__ __forceinline__ void epilogue_point(const EnsDesc &E, int N, int i, c
             E.Ua[(size_t)c * N + i] = ua[c];
             E.Wa[(size_t)c * N + i] = wa[c];
             E.Xs[(size_t)c * N + i] = xv[c] + h * U[c];
+            if (scheme == 0) E.Ks[(size_t)c * N + i] = k[c];
         }
-        rotate_frame(dv, E.Ds, N, i, h * W[0], h * W[1], h * W[2], false);
+        rotate_frame(dv, E.Ds, N, i, h * k[0], h * k[1], h * k[2], false);
     } else {
         double xn[3];
 #pragma unroll

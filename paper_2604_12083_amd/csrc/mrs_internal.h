@@ -46,6 +46,7 @@ struct EnsDesc {
     double *Xs, *Ds;   // RK stage state (SoA)
     double *U, *W;     // velocities (SoA, or AoS when aos_io)
     double *Ua, *Wa;   // RK weighted sums (SoA)
+    double *Ks;        // RK4: the last stage's corrected angular velocity k (SoA)
     const double *fext, *next;  // external loads (SoA, or AoS when aos_io), may be null
     const double *Xin_aos;      // AoS positions when aos_io
     void *rec;         // source records (RecF32 or RecF64), N entries

@@ -228,6 +228,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(int stage, int scheme
     // wave 0 loads the state its epilogue updates before the partial sums,
     // so that the two memory latencies overlap
     double xv[3] = {0.0, 0.0, 0.0}, dv[9], uav[3] = {0.0, 0.0, 0.0}, wav[3] = {0.0, 0.0, 0.0};
+    double kv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < 9; k++) dv[k] = 0.0;
     if (EPI != EPI_WRITE && w == 0 && i < N) {
@@ -240,6 +241,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(int stage, int scheme
             for (int c = 0; c < 3; c++) {
                 uav[c] = E.Ua[(size_t)c * N + i];
                 wav[c] = E.Wa[(size_t)c * N + i];
+                if (scheme == 0) kv[c] = E.Ks[(size_t)c * N + i];
             }
         }
     }
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(int stage, int scheme
     if (dt != dt) dt = E.dt;  // NaN: per-ensemble step size
     // the step's last epilogue advances the ensemble clock (one writer)
     if ((EPI == EPI_EULER || EPI == EPI_RK_FINAL) && i == 0 && E.clock) *E.clock += dt;
-    epilogue_point<EPI>(E, N, i, acc, xv, dv, uav, wav, stage, scheme, dt);
+    epilogue_point<EPI>(E, N, i, acc, xv, dv, uav, wav, kv, stage, scheme, dt);
 }
 
 // ------------------------------------------------------ Parareal correction

@@ -68,11 +68,11 @@ PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
         c.mode = split_mode(N, prec) ? PAIR_SPLIT : PAIR_TILE;
         c.tpl = (prec == MRS_FP32C) ? 1 : 2;
         c.K = 0;
-        if (c.mode == PAIR_TILE) {
-            if (prec == MRS_FP64 && fp64_one_target(N, n_cu)) c.tpl = 1;
-            small = small_grid(N, c.tpl, n_cu);
-        }
+        if (c.mode == PAIR_TILE && prec == MRS_FP64 && fp64_one_target(N, n_cu)) c.tpl = 1;
     }
+    // automatic chunking (also of a stored configuration with chunks = 0):
+    // 64-source chunks in small grids, as without a stored configuration
+    if (c.mode == PAIR_TILE && c.K <= 0) small = small_grid(N, c.tpl, n_cu);
     if (c.mode == PAIR_SPLIT) {
         c.K = 1;
         c.chunk = (int)N;

@@ -148,6 +148,7 @@ static EnsDesc ensemble_desc(mrs_ensemble *E, int prec, const PairCfg &c) {
     d.W = E->W.as<double>();
     d.Ua = E->Ua.as<double>();
     d.Wa = E->Wa.as<double>();
+    d.Ks = E->Ks.as<double>();
     d.fext = E->has_ext ? E->fext.as<double>() : nullptr;
     d.next = E->has_ext ? E->next.as<double>() : nullptr;
     d.Xin_aos = nullptr;
@@ -185,9 +186,13 @@ static EnsDesc ensemble_desc(mrs_ensemble *E, int prec, const PairCfg &c) {
 }
 
 // Plan of one ensemble for one precision (built once, reused).
-mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out) {
+mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out, bool may_tune) {
     mrs_context *ctx = E->ctx;
     if (!E->plan[prec]) {
+        if (may_tune) {
+            mrs_status st = tune_if_unseen(ctx, E->N, prec);
+            if (st != MRS_OK) return st;
+        }
         auto P = std::make_unique<Plan>();
         plan_use_pool(*P, E->pool);
         P->prec = prec;
@@ -385,7 +390,7 @@ mrs_status ensemble_alloc(mrs_context *ctx, int32_t n_fil, const int32_t *offset
     const int64_t n = offsets[n_fil];
     E = std::make_unique<mrs_ensemble>();
     E->pool = pool;
-    for (DevBuf *b : {&E->off, &E->X, &E->D, &E->U, &E->W, &E->Xs, &E->Ds, &E->Ua, &E->Wa, &E->fext, &E->next,
+    for (DevBuf *b : {&E->off, &E->X, &E->D, &E->U, &E->W, &E->Xs, &E->Ds, &E->Ua, &E->Wa, &E->Ks, &E->fext, &E->next,
                       &E->rec, &E->part, &E->clock, &E->fil, &E->flj, &E->lj_blk, &E->lj_box, &E->lj_mask})
         b->pool = pool;
     E->ctx = ctx;
@@ -401,7 +406,7 @@ mrs_status ensemble_alloc(mrs_context *ctx, int32_t n_fil, const int32_t *offset
     bool ok = E->off.reserve((n_fil + 1) * sizeof(int32_t)) == hipSuccess && E->X.reserve(v3) == hipSuccess &&
               E->D.reserve(v9) == hipSuccess && E->U.reserve(v3) == hipSuccess && E->W.reserve(v3) == hipSuccess &&
               E->Xs.reserve(v3) == hipSuccess && E->Ds.reserve(v9) == hipSuccess &&
-              E->Ua.reserve(v3) == hipSuccess && E->Wa.reserve(v3) == hipSuccess &&
+              E->Ua.reserve(v3) == hipSuccess && E->Wa.reserve(v3) == hipSuccess && E->Ks.reserve(v3) == hipSuccess &&
               E->rec.reserve((size_t)n * sizeof(RecF64)) == hipSuccess && E->clock.reserve(sizeof(double)) == hipSuccess;
     if (ok && has_ext) ok = E->fext.reserve(v3) == hipSuccess && E->next.reserve(v3) == hipSuccess;
     if (!ok) return fail(ctx, MRS_ENOMEM, "ensemble allocation (%lld points)", (long long)n);
@@ -558,6 +563,13 @@ mrs_status mrs_context_create(int device, mrs_context **out) {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         ctx->n_cu = ncu;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        ctx->arch = prop.gcnArchName;
+        const size_t colon = ctx->arch.find(':');  // drop the target features
+        if (colon != std::string::npos) ctx->arch.resize(colon);
+    }
+    if (ctx->arch.empty()) ctx->arch = "unknown";
     void *flag = nullptr;
     if (hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->stage_event, hipEventDisableTiming) != hipSuccess ||

@@ -140,6 +140,11 @@ struct mrs_context {
     std::vector<hipEvent_t> event_pool;
     // tuning table: (prec, log2 bucket of N) -> config
     std::map<std::pair<int, int>, mrs::PairCfg> tune;
+    // measured evaluation times of tuned entries: (tuned ms, automatic ms)
+    std::map<std::pair<int, int>, std::pair<double, double>> tune_ms;
+    std::string arch;          // device architecture name (tuning tables are per device kind)
+    int tune_first_use = 0;    // > 0: tune unseen size classes when a plan is built, with this many runs
+    std::string tune_path;     // tuning table file, rewritten after every tuning (empty: none)
     // batch plans
     std::map<std::pair<std::vector<uint64_t>, int>, std::unique_ptr<mrs::Plan>> batch_plans;
     std::vector<mrs_ensemble *> ensembles;
@@ -161,7 +166,7 @@ struct mrs_ensemble {
     // swimming (Sec. IV): waveform (A, k, f) and Lennard-Jones (sigma, energy)
     bool has_wave = false, has_lj = false;
     double wave[3] = {0, 0, 0}, lj[2] = {0, 0};
-    mrs::DevBuf off, X, D, U, W, Xs, Ds, Ua, Wa, fext, next, rec, part;
+    mrs::DevBuf off, X, D, U, W, Xs, Ds, Ua, Wa, Ks, fext, next, rec, part;
     mrs::DevBuf clock;              // time at the start of the next step (one double)
     int32_t n_ljblk = 0;
     mrs::DevBuf fil, flj, lj_blk, lj_box, lj_mask;  // with LJ: filament per point, forces, source
@@ -181,7 +186,11 @@ void numeric_reset(mrs_context *ctx);
 mrs_status numeric_check(mrs_context *ctx);
 // MRS_ENUMERIC if any of p[0..n) is not finite.
 mrs_status check_host_finite(mrs_context *ctx, const double *p, size_t n, const char *what);
-mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out);
+// may_tune: a missing size class may be tuned first (tune on first use)
+mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out, bool may_tune = true);
+// Tune the size class of n in precision prec if tuning on first use is on
+// and the class has no entry yet (never while ctx->stream is capturing).
+mrs_status tune_if_unseen(mrs_context *ctx, int64_t n, int prec);
 void add_items(Plan &P, int e, int64_t N, int n_fil, const PairCfg &c);
 // Lennard-Jones blocks of ensemble e of plan P when it has the repulsion on.
 void add_lj_items(Plan &P, int e, const mrs_ensemble *E);

@@ -202,7 +202,7 @@ mrs_status tick_plan(mrs_server *S, const std::vector<Request *> &run, TickPlan 
     for (size_t e = 0; e < run.size(); e++) {
         Request *r = run[e];
         Plan *single;
-        mrs_status st = ensemble_plan(r->ens, S->prec, &single);
+        mrs_status st = ensemble_plan(r->ens, S->prec, &single, /*may_tune=*/false);
         if (st != MRS_OK) return st;
         EnsDesc d = single->h_desc[0];
         d.dt = r->spec.dt;

@@ -6,6 +6,11 @@ the fine propagator of Sec. III.A is an explicit Runge-Kutta method).
     at order 1, the midpoint RK2 at order 2 and the classical RK4 at order
     4 (error ratios ~2, ~4 and ~16 when dt halves), measured against a much
     finer RK4 solution.
+  * With the elastic coupling on, the angular velocity changes within a step
+    and the frames feed back into the forces: RK4 (frames by
+    Runge-Kutta-Munthe-Kaas) must still converge at order 4 in both the
+    frames and the positions, and RK2 at order 2 (a frame update that skips
+    the dexp^-1 terms, or gets their sign wrong, falls to order 2).
   * One Euler step equals its definition composed from the pinned pieces
     (rod forces, MRS sum, Rodrigues update, re-orthonormalisation).
   * Frames stay orthonormal and right-handed over many steps.
@@ -45,6 +50,65 @@ def test_convergence_orders(oracle_mod):
     assert all(1.8 < r < 2.3 for r in r_e), (errs[1], r_e)
     assert all(3.5 < r < 4.6 for r in r_2), (errs[2], r_2)
     assert all(13.0 < r < 19.0 for r in r_4), (errs[4], r_4)
+
+
+def test_convergence_orders_with_elastic_coupling(oracle_mod):
+    e = _small()
+    rod = e.rod(a=(1e-3,) * 3, b=(1e-2,) * 3)
+    T = 1e-3
+    Xref, Dref = _run(oracle_mod, e, rod, oracle_mod.RK4, T, 128, elastic=True)
+    for integ, steps, lo, hi in ((oracle_mod.RK4, (4, 8, 16), 14.0, 18.0), (oracle_mod.RK2, (8, 16, 32), 3.6, 4.4)):
+        ex, ed = [], []
+        for s in steps:
+            X, D = _run(oracle_mod, e, rod, integ, T, s, elastic=True)
+            ex.append(np.abs(X - Xref).max())
+            ed.append(np.abs(D - Dref).max())
+        rx = [ex[i] / ex[i + 1] for i in range(2)]
+        rd = [ed[i] / ed[i + 1] for i in range(2)]
+        assert all(lo < r < hi for r in rx), (integ, ex, rx)
+        assert all(lo < r < hi for r in rd), (integ, ed, rd)
+
+
+def test_rkmk_stage_correction(oracle_mod):
+    """The second RK4 stage from a state whose first-stage Omega is w0: the
+    stage frame is Rod(dt/2 w0) D, and the step's frame sums take
+    k = Omega - theta x Omega / 2 + theta x (theta x Omega) / 12 with
+    theta = dt/2 w0.  Checked on one step against the four stages composed
+    from the oracle's own velocities and Rodrigues update."""
+    e = _small(7)
+    rod = e.rod(a=(1e-3,) * 3, b=(1e-2,) * 3)
+    dt = 2e-3
+    X0, D0 = e.X.copy(), e.D.copy()
+
+    def vel(X, D):
+        return oracle_mod.velocities(e.offsets, X, D, rod, e.f, e.n, e.eps, e.mu)
+
+    def rot(W, h, D):
+        out = np.empty_like(D)
+        for k in range(len(D)):
+            for i in range(3):
+                out[k, 3 * i:3 * i + 3] = oracle_mod.rodrigues(h * W[k], D[k, 3 * i:3 * i + 3])
+        return out
+
+    c, w = (0.0, 0.5, 0.5, 1.0), (1 / 6, 2 / 6, 2 / 6, 1 / 6)
+    Ua, Wa = np.zeros_like(X0), np.zeros_like(X0)
+    U, k = None, None
+    for s in range(4):
+        Xs = X0 if s == 0 else X0 + c[s] * dt * U
+        Ds = D0 if s == 0 else rot(k, c[s] * dt, D0)
+        U, W = vel(Xs, Ds)
+        if s > 0:
+            th = c[s] * dt * k
+            t1 = np.cross(th, W)
+            W = W - 0.5 * t1 + np.cross(th, t1) / 12.0
+        k = W
+        Ua += w[s] * U
+        Wa += w[s] * k
+    X1 = X0 + dt * Ua
+    D1 = oracle_mod.reorthonormalize(rot(Wa, dt, D0))
+    Xs, Ds, _, _ = oracle_mod.step(e.offsets, X0, D0, rod, e.f, e.n, e.eps, e.mu, oracle_mod.RK4, dt, 1)
+    np.testing.assert_allclose(Xs, X1, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(Ds, D1, rtol=0, atol=1e-14)
 
 
 def test_euler_step_composition(oracle_mod):
