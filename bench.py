@@ -36,10 +36,11 @@ FLOPS_PER_PAIR = 92       # algorithmic flops of one (target, source) evaluation
 
 # HBM bytes per pair-kernel launch from hardware counters (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, the factors a 256 MiB device copy reads), valid only for
-# the pair-kernel source (its sha256) and the exact work list (sha256 of the
-# blocks `mrs_plan_items` gives for the workload) they were taken on: any
-# other kernel or decomposition reports null.
-KERNEL_SRC = os.path.join(ROOT, "paper_2604_12083_amd", "csrc", "mrs_pairs.hip")
+# the pair-kernel source (sha256 of the kernel file and its device header,
+# concatenated) and the exact work list (sha256 of the blocks
+# `mrs_plan_items` gives for the workload) they were taken on: any other
+# kernel or decomposition reports null.
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_12083_amd", "csrc", f) for f in ("mrs_pairs.hip", "mrs_device_pairs.h")]
 KERNEL_SHA = "30ba426091534d1ca9c03f292a90ea92b429d48142b109c54bc52ebb22006047"
 MEASURED_TRAFFIC = {
     ("ens12800", "fp32c", "678ec7c5e5d82ecf"): (2706.80 * 2.0 + 37200.0) * 1024,
@@ -54,11 +55,14 @@ MEASURED_TRAFFIC = {
 def measured_traffic(mrs, workload_name, tag, n, prec, n_cu):
     import hashlib
 
+    h = hashlib.sha256()
     try:
-        with open(KERNEL_SRC, "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest() != KERNEL_SHA:
-                return None
+        for src in KERNEL_SRCS:
+            with open(src, "rb") as fh:
+                h.update(fh.read())
     except OSError:
+        return None
+    if h.hexdigest() != KERNEL_SHA:
         return None
     _, items = mrs.mrs_plan_items(n, prec, n_cu)
     v = MEASURED_TRAFFIC.get((workload_name, tag, hashlib.sha256(items.tobytes()).hexdigest()[:16]))
@@ -502,9 +506,10 @@ def bench_schedules(mrs, ctx, prec, integ="RK4", iters=4, fine_steps=(5, 20, 50,
     return out
 
 
-def bench_serving(mrs, ctx, n_req, rates, slots, budget, tick_pairs=0):
+def bench_serving(mrs, ctx, n_req, rates, slots, budget, tick_pairs=0, admission=0, max_wait=0.0):
     """Serving: the fixed request sequence at Poisson arrival rates; continuous
-    batching (many slots) vs one request at a time (one slot)."""
+    batching (many slots, admission order `admission`) vs one request at a
+    time (one slot, arrival order)."""
     import synth
 
     reqs = synth.serving_requests()[:n_req]
@@ -517,6 +522,8 @@ def bench_serving(mrs, ctx, n_req, rates, slots, budget, tick_pairs=0):
         arr = synth.poisson_arrivals(n_req, rate)
         srv = mrs.mrs_server_start(ctx, mrs.MRS_FP32C, budget, nslots)
         mrs.mrs_server_set_tick_pairs(srv, int(tick_pairs) if nslots > 1 else 0)
+        if nslots > 1:
+            mrs.mrs_server_set_admission(srv, admission, max_wait)
         tickets = []
         try:
             t0 = time.monotonic()
@@ -555,6 +562,8 @@ def bench_serving(mrs, ctx, n_req, rates, slots, budget, tick_pairs=0):
             res["small_max_points"] = int(pts[small].max())
         return res
 
+    out["admission"] = {"order": ["arrival", "least-work"][admission], "max_wait_s": max_wait,
+                        "tick_pairs": tick_pairs, "slots": slots}
     out["batched"] = {str(r): run(r, slots) for r in rates}
     out["one_at_a_time"] = {str(rates[-1]): run(rates[-1], 1)}
     return out
@@ -572,7 +581,11 @@ def main():
     ap.add_argument("--rates", default="10,100,1000", help="serving: Poisson arrival rates (req/s)")
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--budget-gb", type=float, default=64.0)
-    ap.add_argument("--tick-pairs", type=float, default=2e10, help="serving: pair budget of one serving tick")
+    ap.add_argument("--tick-pairs", type=float, default=5e9, help="serving: pair budget of one serving tick")
+    ap.add_argument("--admission", default="least-work", choices=["arrival", "least-work"],
+                    help="serving: admission order of queued requests")
+    ap.add_argument("--max-wait", type=float, default=10.0,
+                    help="serving, least-work order: age (s) after which a request is admitted in arrival order")
     ap.add_argument("--dt", type=float, default=None, help="time step (default 1e-4 for rod64, else 1e-6)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
@@ -648,7 +661,7 @@ def main():
             else:
                 rates = [float(x) for x in args.rates.split(",")]
                 r = bench_serving(mrs, ctx, args.requests, rates, args.slots, int(args.budget_gb * (1 << 30)),
-                                  args.tick_pairs)
+                                  args.tick_pairs, ["arrival", "least-work"].index(args.admission), args.max_wait)
                 best = r["batched"][str(rates[-1])]
                 line = {"metric": METRIC, "value": best["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
                         "steps": args.requests, "warmup": 0, "ms_per_step": best["p50_ms"],

@@ -288,7 +288,8 @@ typedef struct {
 } mrs_server_stats;
 
 /* Start a server thread that owns ctx until mrs_server_stop.  It admits
- * queued requests (arrival order, first fit) while a slot is free and their
+ * queued requests (arrival order by default, first fit; see
+ * mrs_server_set_admission) while a slot is free and their
  * device footprint fits in hbm_budget_bytes, copying their state to the
  * device on a second stream while earlier work runs; every tick is ONE
  * batched sequence that advances the admitted requests by one evaluation or
@@ -311,6 +312,16 @@ mrs_status mrs_server_start(mrs_context *ctx, mrs_precision prec, int64_t hbm_bu
  * round robin): small requests advance every tick, larger ones every few
  * ticks, so a large request does not hold every small one to its pace. */
 mrs_status mrs_server_set_tick_pairs(mrs_server *srv, int64_t max_pairs);
+/* Order in which queued requests are admitted (first fit in that order, as
+ * slots and the HBM budget allow).  MRS_ADMIT_ARRIVAL (the default):
+ * arrival order.  MRS_ADMIT_LEAST_WORK: least total work (pair interactions
+ * of all the request's evaluations) first, which cuts the wait of small
+ * requests queued behind large ones; requests that have waited longer than
+ * max_wait_s (> 0; 0 = no bound) go first, in arrival order, so no request
+ * waits for ever.  Applies from the next admission on; results do not
+ * depend on it.  Errors: MRS_EINVAL for another order or max_wait_s < 0. */
+typedef enum { MRS_ADMIT_ARRIVAL = 0, MRS_ADMIT_LEAST_WORK = 1 } mrs_admission;
+mrs_status mrs_server_set_admission(mrs_server *srv, int32_t order, double max_wait_s);
 /* Any host thread.  *ticket identifies the request. */
 mrs_status mrs_server_submit(mrs_server *srv, const mrs_request *req, uint64_t *ticket);
 /* Non-blocking.  MRS_ENOTREADY until the request is done; then fills info,

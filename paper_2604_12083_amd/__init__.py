@@ -76,6 +76,7 @@ class mrs_server_stats(ctypes.Structure):
 
 
 MRS_REQ_EVAL, MRS_REQ_STEPS = 0, 1
+MRS_ADMIT_ARRIVAL, MRS_ADMIT_LEAST_WORK = 0, 1
 
 
 class mrs_pair_config(ctypes.Structure):
@@ -129,6 +130,7 @@ _SIGS = {
     "mrs_server_stats_get": (_int, [_vp, ctypes.POINTER(mrs_server_stats)]),
     "mrs_server_stop": (_int, [_vp]),
     "mrs_server_set_tick_pairs": (_int, [_vp, _i64]),
+    "mrs_server_set_admission": (_int, [_vp, ctypes.c_int32, _dbl]),
     "mrs_autotune": (_int, [_vp, _i64, _int, ctypes.c_int32, ctypes.POINTER(mrs_pair_config),
                             ctypes.POINTER(_dbl)]),
     "mrs_tune_get": (_int, [_vp, _i64, _int, ctypes.POINTER(mrs_pair_config)]),
@@ -445,6 +447,12 @@ def mrs_server_stats_get(srv):
 
 def mrs_server_set_tick_pairs(srv, max_pairs) -> None:
     _check(_lib.mrs_server_set_tick_pairs(srv, int(max_pairs)))
+
+
+def mrs_server_set_admission(srv, order, max_wait_s=0.0) -> None:
+    """order: MRS_ADMIT_ARRIVAL or MRS_ADMIT_LEAST_WORK (requests waiting
+    longer than max_wait_s > 0 go first, in arrival order)."""
+    _check(_lib.mrs_server_set_admission(srv, int(order), float(max_wait_s)))
 
 
 def mrs_server_stop(srv) -> None:

@@ -136,6 +136,8 @@ struct mrs_server {
     double t_start = 0.0;
     int64_t fail_tick = -1;
     std::atomic<int64_t> tick_pairs{0};  // 0 = no per-tick bound
+    std::atomic<int32_t> admit_order{MRS_ADMIT_ARRIVAL};
+    std::atomic<double> admit_max_wait{0.0};  // least-work order: age after which arrival order applies
     // scheduler-thread state
     hipStream_t up_stream = nullptr;
     DevPool pool;
@@ -304,30 +306,52 @@ hipError_t launch_tick(mrs_server *S, TickPlan &T) {
     return e;
 }
 
-// Pick queued requests to admit (arrival order, first fit).  Caller holds S->mu.
+// Pair interactions of a request's whole work.
+double total_work(const Request *r) {
+    return (double)evals_per_unit(r) * (double)r->N * (double)r->N * (double)units(r);
+}
+
+// Pick queued requests to admit, first fit, in the server's admission
+// order: arrival order, or least total work first with the requests that
+// have waited longer than the age bound taken first, in arrival order.
+// Caller holds S->mu.
 std::vector<Request *> select_admissions(mrs_server *S) {
+    std::vector<Request *> order(S->queue.begin(), S->queue.end());
+    if (S->admit_order.load() == MRS_ADMIT_LEAST_WORK) {
+        const double max_wait = S->admit_max_wait.load(), now = now_s();
+        auto aged = [&](const Request *r) { return max_wait > 0.0 && now - r->info.t_submit > max_wait; };
+        std::stable_sort(order.begin(), order.end(), [&](const Request *a, const Request *b) {
+            const bool ag = aged(a), bg = aged(b);
+            if (ag != bg) return ag;
+            if (ag) return false;  // both aged: arrival order (stable)
+            return total_work(a) < total_work(b);
+        });
+    }
     std::vector<Request *> pick;
+    std::vector<Request *> drop;  // leave the queue: admitted or rejected
     int64_t used = S->in_use;
-    for (auto it = S->queue.begin(); it != S->queue.end();) {
+    for (Request *r : order) {
         if ((int32_t)(S->active.size() + pick.size()) >= S->max_slots) break;
-        Request *r = *it;
         if (r->footprint < 0) r->footprint = request_footprint(S->ctx, S->prec, *r);
         if (r->footprint > S->budget) {  // can never fit
             r->info.status = MRS_ENOMEM;
             r->info.t_admit = r->info.t_done = now_s();
             r->done = true;
             S->st.rejected++;
-            it = S->queue.erase(it);
+            drop.push_back(r);
             S->cv_done.notify_all();
             continue;
         }
-        if (used + r->footprint > S->budget) {
-            ++it;
-            continue;
-        }
+        if (used + r->footprint > S->budget) continue;
         used += r->footprint;
         pick.push_back(r);
-        it = S->queue.erase(it);
+        drop.push_back(r);
+    }
+    if (!drop.empty()) {
+        std::sort(drop.begin(), drop.end());
+        S->queue.erase(std::remove_if(S->queue.begin(), S->queue.end(),
+                                      [&](Request *r) { return std::binary_search(drop.begin(), drop.end(), r); }),
+                       S->queue.end());
     }
     S->in_use = used;
     return pick;
@@ -739,6 +763,15 @@ mrs_status mrs_server_wait(mrs_server *S, uint64_t ticket, double timeout_s, mrs
 mrs_status mrs_server_set_tick_pairs(mrs_server *S, int64_t max_pairs) {
     if (!S || max_pairs < 0) return MRS_EINVAL;
     S->tick_pairs.store(max_pairs);
+    return MRS_OK;
+}
+
+mrs_status mrs_server_set_admission(mrs_server *S, int32_t order, double max_wait_s) {
+    if (!S || (order != MRS_ADMIT_ARRIVAL && order != MRS_ADMIT_LEAST_WORK) || !(max_wait_s >= 0.0))
+        return MRS_EINVAL;
+    S->admit_max_wait.store(max_wait_s);
+    S->admit_order.store(order);
+    S->cv_work.notify_one();
     return MRS_OK;
 }
 

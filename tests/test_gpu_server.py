@@ -207,3 +207,58 @@ def test_invalid_requests(mrs):
             mrs.mrs_server_stop(srv)
     finally:
         mrs.mrs_context_destroy(ctx)
+
+
+@pytest.mark.parametrize("order,max_wait", [(0, 0.0), (1, 0.0), (1, 1e-6)])
+def test_admission_order(mrs, order, max_wait):
+    """One slot, a long request A running, then B (as long), C and D (small)
+    queued behind it: in arrival order B is admitted before C and D; in
+    least-work order C and D go first; with an age bound already passed the
+    least-work order falls back to arrival order.  Results do not depend on
+    the order."""
+    ctx = mrs.mrs_context_create(0)
+    try:
+        big = [synth.filaments(100, 128, 10.0, 900 + k) for k in range(2)]
+        small = [synth.filaments(4, 64, 10.0, 910 + k) for k in range(2)]
+        srv = mrs.mrs_server_start(ctx, mrs.MRS_FP32C, 8 << 30, 1)
+        try:
+            mrs.mrs_server_set_admission(srv, order, max_wait)
+            tickets = []
+            for e in big:
+                tickets.append(mrs.mrs_server_submit(srv, 1, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu,
+                                                     rod_of(mrs, e.rod()), dt=1e-5, nsteps=50, integ=mrs.MRS_RK4))
+            for e in small:
+                tickets.append(mrs.mrs_server_submit(srv, 0, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu,
+                                                     rod_of(mrs, e.rod())))
+            res = [mrs.mrs_server_wait(srv, t, e.N, timeout_s=120) for t, e in zip(tickets, big + small)]
+        finally:
+            mrs.mrs_server_stop(srv)
+        assert all(st == mrs.MRS_OK for st, _, _ in res)
+        A, B, C, D = (info for _, info, _ in res)
+        say(f"order {order} max_wait {max_wait}: admitted A {A.t_admit - A.t_submit:.4f} "
+            f"B {B.t_admit - A.t_submit:.4f} C {C.t_admit - A.t_submit:.4f} D {D.t_admit - A.t_submit:.4f} "
+            f"(A done {A.t_done - A.t_submit:.4f})")
+        assert max(B.t_submit, C.t_submit, D.t_submit) < A.t_done  # all queued while A ran
+        if order == 1 and max_wait == 0.0:
+            assert C.t_admit < B.t_admit and D.t_admit < B.t_admit
+        else:
+            assert B.t_admit < C.t_admit < D.t_admit
+        U = res[2][2][2]
+        _, _, Ua, _ = _alone(mrs, ctx, small[0], 0, "RK4", mrs.MRS_FP32C, 0, 0.0)
+        assert np.array_equal(U, Ua)
+    finally:
+        mrs.mrs_context_destroy(ctx)
+
+
+def test_admission_rejects_bad_arguments(mrs):
+    ctx = mrs.mrs_context_create(0)
+    try:
+        srv = mrs.mrs_server_start(ctx, mrs.MRS_FP32C, 1 << 30, 4)
+        try:
+            for order, wait in ((2, 0.0), (-1, 0.0), (1, -1.0), (0, float("nan"))):
+                with pytest.raises(mrs.MrsError):
+                    mrs.mrs_server_set_admission(srv, order, wait)
+        finally:
+            mrs.mrs_server_stop(srv)
+    finally:
+        mrs.mrs_context_destroy(ctx)
