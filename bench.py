@@ -41,14 +41,14 @@ FLOPS_PER_PAIR = 92       # algorithmic flops of one (target, source) evaluation
 # `mrs_plan_items` gives for the workload) they were taken on: any other
 # kernel or decomposition reports null.
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_12083_amd", "csrc", f) for f in ("mrs_pairs.hip", "mrs_device_pairs.h")]
-KERNEL_SHA = "30ba426091534d1ca9c03f292a90ea92b429d48142b109c54bc52ebb22006047"
+KERNEL_SHA = "93f31f8aa13e776c9919c6fd2ce97086acc00c664205b879c5dcb3b4c893c0ff"
 MEASURED_TRAFFIC = {
-    ("ens12800", "fp32c", "678ec7c5e5d82ecf"): (2706.80 * 2.0 + 37200.0) * 1024,
-    ("ens12800", "fp64", "adb3c89bda2d142d"): (4134.21 * 2.0 + 30000.0) * 1024,
-    ("ens256000", "fp32c", "4a2b01f9e8a27aa9"): (183528.43 * 2.0 + 264000.0) * 1024,
-    ("ens256000", "fp64", "571ba5e594123b76"): (471076.54 * 2.0 + 396000.0) * 1024,
-    ("swim", "fp32c", "72ec18efbf0e53ad"): (34185.52 * 2.0 + 176908.05) * 1024,
-    ("swim", "fp64", "df10004c75444124"): (90377.61 * 2.0 + 148221.08) * 1024,
+    ("ens12800", "fp32c", "678ec7c5e5d82ecf"): (2709.84 * 2.0 + 37200.0) * 1024,
+    ("ens12800", "fp64", "adb3c89bda2d142d"): (4131.13 * 2.0 + 30000.0) * 1024,
+    ("ens256000", "fp32c", "4a2b01f9e8a27aa9"): (183495.38 * 2.0 + 264000.0) * 1024,
+    ("ens256000", "fp64", "571ba5e594123b76"): (470563.64 * 2.0 + 396000.0) * 1024,
+    ("swim", "fp32c", "72ec18efbf0e53ad"): (34167.39 * 2.0 + 176909.73) * 1024,
+    ("swim", "fp64", "df10004c75444124"): (90345.04 * 2.0 + 148220.88) * 1024,
 }
 
 
@@ -282,7 +282,7 @@ def roofline(pairs_per_launch, avg_s, peak_tflops, traffic=None):
             "frac": round(ach / peak_tflops, 4), "traffic": traffic}
 
 
-def bench_large(mrs, ctx, reps32=3, reps64=2):
+def bench_large(mrs, ctx, n_cu, reps32=3, reps64=2):
     """One-shot U, Omega evaluations (rod forces + MRS sum + reduction) of the
     256,000-point ensemble, FP32C then FP64, with HIP events around the pair
     kernel; returns the leg's summary and the GPU results on the seeded
@@ -314,7 +314,8 @@ def bench_large(mrs, ctx, reps32=3, reps64=2):
             subset[tag] = (U[idx], W[idx])
             out[tag] = {"evals": reps, "ms_per_eval": 1e3 * wall, "pairs_per_s": e.N * e.N / wall,
                         "pair_kernel_us": 1e3 * ms_k / n_k,
-                        "roofline": roofline(e.N * e.N, 1e-3 * ms_k / n_k, peak)}
+                        "roofline": roofline(e.N * e.N, 1e-3 * ms_k / n_k, peak,
+                                             measured_traffic(mrs, "ens256000", tag, e.N, prec, n_cu))}
     finally:
         mrs.mrs_ensemble_destroy(ens)
     return out, subset
@@ -439,18 +440,26 @@ def bench_parareal(mrs, ctx, prec, tol, coarse_steps):
     # ~3e4 rad/s and no explicit-Euler coarse step of the slice is meaningful
     tq = 1e-2 * base.n
     mk = lambda: mrs.mrs_ensemble_create(ctx, base.offsets, base.X, base.D, base.f, tq, base.eps, base.mu, rod)
+
+    def reset(h):
+        mrs.mrs_ensemble_set_state(ctx, h, base.X, base.D)
+        mrs.mrs_ensemble_set_time(ctx, h, 0.0)
+
     a, b = mk(), mk()
     try:
-        # warm both paths (plans, graphs) on throwaway copies
-        w = mk()
-        mrs.mrs_parareal(ctx, w, 16, mrs.MRS_RK4, 1e-5, 200, coarse_steps, 1, 0.0, prec, True)
-        mrs.mrs_ensemble_step(ctx, w, mrs.MRS_RK4, 1e-5, 10, prec, True)
-        mrs.mrs_ensemble_destroy(w)
+        # warm-up calls: the slice workers and the plans and graphs of every
+        # iteration's batch (slices k..16) stay with the ensemble
+        mrs.mrs_parareal(ctx, a, 16, mrs.MRS_RK4, 1e-5, 200, coarse_steps, 16, tol, prec, True)
+        mrs.mrs_ensemble_step(ctx, b, mrs.MRS_RK4, 1e-5, 10, prec, True)
+        reset(a)
+        reset(b)
         t0 = time.perf_counter()
         it, hist = mrs.mrs_parareal(ctx, a, 16, mrs.MRS_RK4, 1e-5, 200, coarse_steps, 16, tol, prec, True)
         tpar = time.perf_counter() - t0
         c = mk()
         try:
+            mrs.mrs_parareal_pipelined(ctx, c, 16, mrs.MRS_RK4, 1e-5, 200, coarse_steps, 16, tol, prec, True)
+            reset(c)
             t0 = time.perf_counter()
             itp, histp = mrs.mrs_parareal_pipelined(ctx, c, 16, mrs.MRS_RK4, 1e-5, 200, coarse_steps, 16, tol, prec,
                                                     True)
@@ -481,7 +490,10 @@ def bench_schedules(mrs, ctx, prec, integ="RK4", iters=4, fine_steps=(5, 20, 50,
     """Regular against pipelined Parareal (Sec. II.D) on one GPU for several
     fine/coarse cost ratios r: 16 slices of the 3,200-point slice ensemble,
     fine `integ` x fine_steps, coarse Euler x coarse_steps, a fixed number of
-    iterations (tol = 0), so both schedules do the same work."""
+    iterations (tol = 0), so both schedules do the same work.  Each schedule
+    runs twice on one ensemble from the same start state: the first call
+    builds the slice workers, plans and graphs (`*_first_s`), the second
+    reuses them (`*_s`)."""
     import synth
 
     base, _ = synth.slices(n_slices=1)
@@ -497,9 +509,13 @@ def bench_schedules(mrs, ctx, prec, integ="RK4", iters=4, fine_steps=(5, 20, 50,
             log(f"parareal schedules: {name} {integ} fine_steps={fs}")
             h = mk()
             try:
-                t0 = time.perf_counter()
-                fn(ctx, h, 16, getattr(mrs, "MRS_" + integ), 1e-5, fs, coarse_steps, iters, 0.0, prec, True, **kw)
-                row[name + "_s"] = time.perf_counter() - t0
+                for key in ("_first_s", "_s"):
+                    mrs.mrs_ensemble_set_state(ctx, h, base.X, base.D)
+                    mrs.mrs_ensemble_set_time(ctx, h, 0.0)
+                    t0 = time.perf_counter()
+                    fn(ctx, h, 16, getattr(mrs, "MRS_" + integ), 1e-5, fs, coarse_steps, iters, 0.0, prec, True,
+                       **kw)
+                    row[name + key] = time.perf_counter() - t0
             finally:
                 mrs.mrs_ensemble_destroy(h)
         out.append(row)
@@ -693,7 +709,7 @@ def main():
         extra = args.workload == "ens12800" and not args.no_extra
         large = slices_leg = large_subset = None
         if extra:
-            large, large_subset = bench_large(mrs, ctx)
+            large, large_subset = bench_large(mrs, ctx, n_cu)
             log(f"16 slices x 3,200 points, {args.steps} RK4 steps: batched graph vs plain")
             slices_leg = bench_slices(mrs, ctx, args.steps, args)
         cpu, errs = (None, None)
