@@ -443,7 +443,11 @@ mrs_status mrs_tune_set(mrs_context *ctx, int64_t n, mrs_precision prec, const m
  * state stays on the device; one host copy of the positions per iteration
  * evaluates the increment.  Each propagation of slice n starts at the slice
  * boundary time (the ensemble clock plus n fine steps, accumulated as the
- * serial run would), and the clock ends at the last boundary. */
+ * serial run would), and the clock ends at the last boundary.  The slice
+ * workers (n_slices + 1 device copies of the ensemble) stay with `ens`
+ * after the call, so later calls reuse them with their launch plans and
+ * graphs; they are rebuilt when its loads or swimming settings change and
+ * freed with it. */
 mrs_status mrs_parareal(mrs_ensemble *ens, int32_t n_slices, mrs_integrator fine_integ, double fine_dt,
                         int32_t fine_steps, int32_t coarse_steps, int32_t max_iter, double tol,
                         mrs_precision prec, int include_elastic, double *history, int32_t *iters);

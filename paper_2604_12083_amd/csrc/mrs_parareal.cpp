@@ -66,8 +66,9 @@ struct Events {
 };
 
 // What both schedules share: arguments, the coarse worker W[0] and one fine
-// worker W[n] per slice (clones of the ensemble), the slice boundary times,
-// the state buffers and events.  Destruction waits for both streams first.
+// worker W[n] per slice (clones of the ensemble, kept with it between calls
+// so that their batch plans and graphs are reused), the slice boundary
+// times, the state buffers and events.  Destruction waits for the streams.
 struct Solve {
     mrs_context *ctx = nullptr;
     mrs_ensemble *E = nullptr;
@@ -88,8 +89,6 @@ struct Solve {
             for (auto a : ctx->aux_stream)
                 if (a) (void)hipStreamSynchronize(a);
         }
-        for (auto *w : W)
-            if (w) mrs_ensemble_destroy(w);
     }
 
     mrs_status init(mrs_ensemble *ens, int32_t n_slices, mrs_integrator integ, double dt, int32_t fine_steps,
@@ -111,11 +110,8 @@ struct Solve {
         el = include_elastic ? 1 : 0;
         N = E->N;
         numeric_reset(ctx);
-        W.assign(ns + 1, nullptr);
-        for (int n = 0; n <= ns; n++) {
-            mrs_status st = ensemble_clone(E, &W[n]);
-            if (st != MRS_OK) return st;
-        }
+        mrs_status wst = ensemble_workers(E, ns + 1, W);
+        if (wst != MRS_OK) return wst;
         // slice boundary times, accumulated step by step exactly as the
         // device clock of a serial fine run accumulates them
         T.assign(ns + 1, 0.0);

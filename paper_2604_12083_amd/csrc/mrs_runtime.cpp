@@ -446,6 +446,11 @@ static mrs_status lj_buffers(mrs_ensemble *E) {
 
 void ensemble_detach(mrs_ensemble *E) {
     mrs_context *ctx = E->ctx;
+    while (!E->workers.empty()) ensemble_detach(E->workers.back());
+    if (E->owner) {
+        auto &O = E->owner->workers;
+        O.erase(std::remove(O.begin(), O.end(), E), O.end());
+    }
     for (auto it = ctx->batch_plans.begin(); it != ctx->batch_plans.end();) {
         const auto &v = it->first.first;
         if (std::find(v.begin(), v.end(), E->uid) != v.end()) it = ctx->batch_plans.erase(it);
@@ -479,6 +484,22 @@ mrs_status ensemble_clone(mrs_ensemble *S, mrs_ensemble **out) {
         return fail(ctx, MRS_EDEVICE, "ensemble clone");
     ctx->ensembles.push_back(E.get());
     *out = E.release();
+    return MRS_OK;
+}
+
+mrs_status ensemble_workers(mrs_ensemble *E, int n_workers, std::vector<mrs_ensemble *> &out) {
+    if (E->workers_uid != E->uid || E->workers_loads != E->loads_gen)
+        while (!E->workers.empty()) ensemble_detach(E->workers.back());
+    E->workers_uid = E->uid;
+    E->workers_loads = E->loads_gen;
+    while ((int)E->workers.size() < n_workers) {
+        mrs_ensemble *w = nullptr;
+        mrs_status st = ensemble_clone(E, &w);
+        if (st != MRS_OK) return st;
+        w->owner = E;
+        E->workers.push_back(w);
+    }
+    out.assign(E->workers.begin(), E->workers.begin() + n_workers);
     return MRS_OK;
 }
 
@@ -597,8 +618,8 @@ void mrs_context_destroy(mrs_context *ctx) {
     (void)hipStreamSynchronize(ctx->own_stream);
     for (auto a : ctx->aux_stream)
         if (a) (void)hipStreamSynchronize(a);
-    auto ens = ctx->ensembles;
-    for (auto *e : ens) mrs_ensemble_destroy(e);
+    // each destruction also removes the ensemble's Parareal workers
+    while (!ctx->ensembles.empty()) mrs_ensemble_destroy(ctx->ensembles.back());
     ctx->batch_plans.clear();
     for (auto &r : ctx->prof) {
         (void)hipEventDestroy(r.start);
@@ -1154,6 +1175,7 @@ mrs_status mrs_ensemble_set_external(mrs_ensemble *E, const double *f_ext, const
     }
     std::vector<double> z(f_ext && n_ext ? 0 : (size_t)3 * n, 0.0);
     mrs_status st;
+    E->loads_gen++;
     if ((st = put_soa(ctx, E->fext, f_ext ? f_ext : z.data(), n, 3, E->perm)) != MRS_OK) return st;
     return put_soa(ctx, E->next, n_ext ? n_ext : z.data(), n, 3, E->perm);
 }

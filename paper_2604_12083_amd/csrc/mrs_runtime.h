@@ -173,6 +173,13 @@ struct mrs_ensemble {
                                                     // blocks and their boxes, masks
     std::unique_ptr<mrs::Plan> plan[2];  // per precision
     mrs::DevPool *pool = nullptr;        // where its device arrays come from (null: hipMalloc)
+    uint64_t loads_gen = 0;              // bumped whenever the external loads change
+    // Parareal workers: clones of this ensemble kept between calls (their
+    // batch plans and graphs with them), valid while workers_uid == uid and
+    // workers_loads == loads_gen; a worker's owner is the ensemble it copies
+    std::vector<mrs_ensemble *> workers;
+    uint64_t workers_uid = 0, workers_loads = 0;
+    mrs_ensemble *owner = nullptr;
 };
 
 namespace mrs {
@@ -197,6 +204,8 @@ void add_lj_items(Plan &P, int e, const mrs_ensemble *E);
 hipError_t finalize_plan(Plan &P);
 hipError_t run_pairs(mrs_context *ctx, Plan &P, hipStream_t s);
 hipEvent_t take_event(mrs_context *ctx);
+// Parareal workers of E for n_slices slices (clones made or reused).
+mrs_status ensemble_workers(mrs_ensemble *E, int n_workers, std::vector<mrs_ensemble *> &out);
 // Device arrays of a new ensemble, from `pool` if given.  With init, the
 // offsets, the clock (0) and zero velocities are copied synchronously;
 // without, the caller queues them.

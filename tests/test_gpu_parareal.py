@@ -168,3 +168,44 @@ def test_pipelined_invalid_group(mrs, ctx):
             mrs.mrs_parareal_pipelined(ctx, h, 2, mrs.MRS_RK4, 1e-5, 4, 1, 3)  # max_iter > n_slices
     finally:
         mrs.mrs_ensemble_destroy(h)
+
+
+def test_workers_kept_between_calls(mrs, ctx):
+    """Repeated calls on one ensemble reuse its Parareal workers (and their
+    plans and graphs): from the same start state they give the same bits,
+    with more slices than before too; after the loads change the workers
+    are rebuilt and the result is that of a fresh ensemble with the new
+    loads; destroying the ensemble releases its workers."""
+    e = synth.filaments(4, 50, 2.0, 31)
+    rng = np.random.default_rng(32)
+    f2 = rng.normal(size=e.X.shape)
+    ns, steps, dt = 4, 6, 1e-5
+    h = _ens(mrs, ctx, e)
+    try:
+        runs = []
+        for k, nsl in enumerate((ns, ns, ns + 2, ns)):
+            mrs.mrs_ensemble_set_state(ctx, h, e.X, e.D)
+            mrs.mrs_ensemble_set_time(ctx, h, 0.0)
+            it, hist = mrs.mrs_parareal(ctx, h, nsl, mrs.MRS_RK4, dt, steps, 1, 2, 0.0, mrs.MRS_FP32C, True)
+            X, D, _, _ = mrs.mrs_ensemble_get(ctx, h)
+            runs.append((nsl, X, D, hist))
+            say(f"call {k}: {nsl} slices, increments {hist}")
+        for a, b in ((0, 1), (0, 3)):
+            assert np.array_equal(runs[a][1], runs[b][1]) and np.array_equal(runs[a][2], runs[b][2])
+            assert np.array_equal(runs[a][3], runs[b][3])
+        # new loads: same result as a fresh ensemble created with them
+        mrs.mrs_ensemble_set_external(ctx, h, f2, e.n)
+        mrs.mrs_ensemble_set_state(ctx, h, e.X, e.D)
+        mrs.mrs_ensemble_set_time(ctx, h, 0.0)
+        mrs.mrs_parareal(ctx, h, ns, mrs.MRS_RK4, dt, steps, 1, 2, 0.0, mrs.MRS_FP32C, True)
+        Xh, Dh, _, _ = mrs.mrs_ensemble_get(ctx, h)
+        g = mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, f2, e.n, e.eps, e.mu, rod_of(mrs, e.rod()))
+        try:
+            mrs.mrs_parareal(ctx, g, ns, mrs.MRS_RK4, dt, steps, 1, 2, 0.0, mrs.MRS_FP32C, True)
+            Xg, Dg, _, _ = mrs.mrs_ensemble_get(ctx, g)
+        finally:
+            mrs.mrs_ensemble_destroy(g)
+        assert np.array_equal(Xh, Xg) and np.array_equal(Dh, Dg)
+        assert not np.array_equal(Xh, runs[0][1])
+    finally:
+        mrs.mrs_ensemble_destroy(h)
