@@ -108,9 +108,25 @@ def test_coincident_points(mrs, ctx, prec):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_linearity_and_zero_loads(mrs, ctx, prec):
+    """U, Omega are linear in the loads (Eq. superposition): zero loads give
+    exactly zero; scaling both loads by 4 scales the results by exactly 4
+    (a power of two commutes with every rounding, FP32C records included);
+    forces alone plus torques alone give the result of both, per point within
+    10x the tolerance times the size of the two parts."""
     X, f, n = _cloud(700, 3)
-    U, W = eval_dev(mrs, ctx, X, np.zeros_like(f), np.zeros_like(n), 0.05, 1.0, prec)
+    z = np.zeros_like(f)
+    U, W = eval_dev(mrs, ctx, X, z, z, 0.05, 1.0, prec)
     assert np.all(U == 0) and np.all(W == 0)
+    U1, W1 = eval_dev(mrs, ctx, X, f, n, 0.05, 1.0, prec)
+    U4, W4 = eval_dev(mrs, ctx, X, 4.0 * f, 4.0 * n, 0.05, 1.0, prec)
+    assert np.array_equal(U4, 4.0 * U1) and np.array_equal(W4, 4.0 * W1)
+    Uf, Wf = eval_dev(mrs, ctx, X, f, z, 0.05, 1.0, prec)
+    Un, Wn = eval_dev(mrs, ctx, X, z, n, 0.05, 1.0, prec)
+    for tot, a, b in ((U1, Uf, Un), (W1, Wf, Wn)):
+        d = np.linalg.norm(tot - a - b, axis=1)
+        scale = np.linalg.norm(a, axis=1) + np.linalg.norm(b, axis=1)
+        say(f"superposition prec={prec}: max |d| / (|a| + |b|) = {np.max(d / scale):.3e}")
+        assert np.all(d <= 10 * TOL[prec] * scale)
 
 
 def test_host_entry_matches_device(mrs, ctx):

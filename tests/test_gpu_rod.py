@@ -109,3 +109,16 @@ def test_rod_forces_parity(mrs, ctx, case):
     eg, em = np.abs(g - go).max() / sg, np.abs(m - mo).max() / sm
     say(f"  max err g {eg:.3e} m {em:.3e}")
     assert eg <= 1e-12 and em <= 1e-12
+    # per point: a point's force is the difference of its two segment forces
+    # plus its external force (Eq. discrete_f), so its error is measured
+    # against the size of those terms; the segment forces are the running
+    # sums of (g - f) along each filament (the last one is zero)
+    worst = 0.0
+    for a, b in zip(e.offsets[:-1], e.offsets[1:]):
+        seg = np.cumsum(go[a:b] - e.f[a:b], axis=0)
+        prev = np.vstack([np.zeros((1, 3)), seg[:-1]])
+        scale = np.linalg.norm(seg, axis=1) + np.linalg.norm(prev, axis=1) + np.linalg.norm(e.f[a:b], axis=1)
+        d = np.linalg.norm(g[a:b] - go[a:b], axis=1)
+        worst = max(worst, float(np.max(d / np.where(scale > 0, scale, 1.0))))
+        assert np.all(d <= 1e-12 * scale + 1e-300)
+    say(f"  per-point g error / size of its terms: {worst:.3e}")
