@@ -386,14 +386,17 @@ mrs_status mrs_autotune(mrs_context *ctx, int64_t n, mrs_precision prec, int32_t
  * configuration is tuned (mrs_autotune with `reps`) when a plan of an
  * ensemble of that class is first built, i.e. on the first
  * mrs_ensemble_eval, mrs_ensemble_step, mrs_batch_step or mrs_parareal call
- * for it in a precision; reps = 0 (the default) turns this off.  Never
- * while the context's stream is being captured, and never for mrs_eval_device,
+ * for it in a precision, for ensembles of at most 262,144 points (a
+ * tuning pass costs about 60 evaluations); reps = 0 (the default) turns
+ * this off.  Never while the context's stream is being captured, and never
+ * for mrs_eval_device,
  * mrs_eval_device_noalloc, mrs_eval_host or the server, which use the table
  * or the automatic configuration as it stands.  table_path (may be NULL):
  * a tuning table file (format of mrs_tune_save) that is read now if it
- * exists, and rewritten after every tuning.  Errors: MRS_EINVAL for reps
- * outside 0..20 or a table that cannot be read or was written for another
- * device kind (architecture name and compute-unit count). */
+ * exists, written at once (with the entries now in the table) and
+ * rewritten after every tuning.  Errors: MRS_EINVAL for reps outside
+ * 0..20, or a table that cannot be read, cannot be written or was written
+ * for another device kind (architecture name and compute-unit count). */
 mrs_status mrs_tune_on_first_use(mrs_context *ctx, int32_t reps, const char *table_path);
 /* Write the tuning table to `path` (text: a header line
  * "mrs-pair-tuning 1 <architecture> <compute units> <unix time>", then one

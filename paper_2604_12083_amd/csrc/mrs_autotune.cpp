@@ -205,8 +205,15 @@ double median(std::vector<double> v) {
 
 namespace mrs {
 
+// Largest ensemble tuned on first use: a tuning pass takes about 60
+// evaluations, 7 s in FP64 at 256,000 points; larger size classes keep the
+// table or the automatic configuration unless mrs_autotune is called.
+constexpr int64_t kFirstUseMaxPoints = 1 << 18;
+
 mrs_status tune_if_unseen(mrs_context *ctx, int64_t n, int prec) {
-    if (ctx->tune_first_use <= 0 || ctx->tune.count({prec, size_bucket(std::max<int64_t>(n, 1))})) return MRS_OK;
+    if (ctx->tune_first_use <= 0 || n > kFirstUseMaxPoints ||
+        ctx->tune.count({prec, size_bucket(std::max<int64_t>(n, 1))}))
+        return MRS_OK;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(ctx->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return MRS_OK;
     return mrs_autotune(ctx, n, (mrs_precision)prec, ctx->tune_first_use, nullptr, nullptr);
@@ -253,6 +260,9 @@ mrs_status mrs_tune_on_first_use(mrs_context *ctx, int32_t reps, const char *tab
     if (table_path && *table_path) {
         mrs_status st = load_table(ctx, table_path, true);
         if (st != MRS_OK) return st;
+        // written once now, so that a path that cannot be written is
+        // refused here and not by a later evaluation that tunes
+        if ((st = save_table(ctx, table_path)) != MRS_OK) return st;
         ctx->tune_path = table_path;
     } else {
         ctx->tune_path.clear();

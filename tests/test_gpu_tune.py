@@ -102,7 +102,8 @@ def test_first_use_tuning_persists_table(mrs, tmp_path):
 def test_foreign_and_malformed_tables_refused(mrs, tmp_path):
     """A table written for another device kind, a malformed one or a missing
     one (mrs_tune_load) is refused and leaves the table unchanged; a missing
-    file is no error for tuning on first use."""
+    file is no error for tuning on first use (it is written at once), a path
+    that cannot be written is."""
     c = mrs.mrs_context_create(0)
     try:
         own = str(tmp_path / "own.txt")
@@ -128,6 +129,9 @@ def test_foreign_and_malformed_tables_refused(mrs, tmp_path):
         with pytest.raises(mrs.MrsError):
             mrs.mrs_tune_on_first_use(c, 1, str(tmp_path / "arch.txt"))
         mrs.mrs_tune_on_first_use(c, 1, str(tmp_path / "missing.txt"))
+        assert open(tmp_path / "missing.txt").read().startswith("mrs-pair-tuning 1 ")  # written at once
+        with pytest.raises(mrs.MrsError):  # a table that cannot be written
+            mrs.mrs_tune_on_first_use(c, 1, str(tmp_path / "no_such_dir" / "t.txt"))
         mrs.mrs_tune_on_first_use(c, 0, None)
         with pytest.raises(mrs.MrsError):
             mrs.mrs_tune_on_first_use(c, 21, None)
