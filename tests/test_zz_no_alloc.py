@@ -98,3 +98,23 @@ def test_noalloc_rejects_sizes_beyond_the_scratch(mrs):
         say(f"rejected: {ex.value}")
     finally:
         mrs.mrs_context_destroy(ctx)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_noalloc_with_tuned_schedules(mrs, prec):
+    """Table entries with the persistent schedule and the four-wave split
+    (FP32C; FP64 falls back to the tiled kernel): the work-queue counters of
+    the allocation-free call live in its scratch and start at zero on every
+    call, so two calls in a row give the allocating call's sums."""
+    ctx = mrs.mrs_context_create(0)
+    try:
+        for cfg in ((2, 1, 0, 1), (0, 1, 0, 1), (2, 1, 9, 0)):
+            for N, seed in ((3000, 11), (2100, 12)):
+                mrs.mrs_tune_set(ctx, N, prec, *cfg)
+                X, f, n, eps = _cloud(N, seed)
+                (U0, W0), (U1, W1) = _both(mrs, ctx, X, f, n, eps, prec)
+                eu, ew = oracle.rel_err(U1, U0), oracle.rel_err(W1, W0)
+                say(f"noalloc cfg {cfg} N={N} prec={prec}: vs mrs_eval_device U {eu:.3e} W {ew:.3e}")
+                assert eu <= TOL[prec] and ew <= TOL[prec], (cfg, N, eu, ew)
+    finally:
+        mrs.mrs_context_destroy(ctx)
