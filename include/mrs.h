@@ -402,7 +402,8 @@ mrs_status mrs_tune_on_first_use(mrs_context *ctx, int32_t reps, const char *tab
  * "mrs-pair-tuning 1 <architecture> <compute units> <unix time>", then one
  * line per entry: precision, log2 size class, mode, targets_per_lane,
  * chunks, schedule, tuned and automatic median ms (-1 if set by hand);
- * written to path.tmp and renamed).  Read one back with mrs_tune_load,
+ * written to a temporary file beside it and renamed over it, so that
+ * readers see the old or the new table, never part of one).  Read one back with mrs_tune_load,
  * which adds its entries (replacing those of the same class) or changes
  * nothing and returns MRS_EINVAL if the file is malformed or from another
  * device kind. */

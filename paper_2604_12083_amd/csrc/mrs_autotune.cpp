@@ -7,6 +7,8 @@
 #include <ctime>
 #include <vector>
 
+#include <unistd.h>
+
 #include "mrs_runtime.h"
 
 using namespace mrs;
@@ -117,7 +119,9 @@ std::vector<PairCfg> candidates(int64_t n, int prec, int n_cu) {
 long long now_s() { return (long long)std::time(nullptr); }
 
 mrs_status save_table(mrs_context *ctx, const char *path) {
-    const std::string tmp = std::string(path) + ".tmp";
+    // written beside the table and renamed over it, so that a reader never
+    // sees half a table (one temporary name per process)
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid());
     FILE *fp = std::fopen(tmp.c_str(), "w");
     if (!fp) return fail(ctx, MRS_EINVAL, "cannot write %s", tmp.c_str());
     std::fprintf(fp, "mrs-pair-tuning 1 %s %d %lld\n", ctx->arch.c_str(), ctx->n_cu, now_s());
