@@ -137,3 +137,32 @@ def test_foreign_and_malformed_tables_refused(mrs, tmp_path):
             mrs.mrs_tune_on_first_use(c, 21, None)
     finally:
         mrs.mrs_context_destroy(c)
+
+
+def test_server_and_one_shot_calls_never_tune(mrs, tmp_path):
+    """Tuning on first use applies to plans of resident ensembles only: the
+    server loop and the one-shot evaluation keep the table as it is."""
+    c = mrs.mrs_context_create(0)
+    try:
+        path = str(tmp_path / "t.txt")
+        mrs.mrs_tune_on_first_use(c, 1, path)
+        e = synth.filaments(30, 100, 6.0, 93)  # 3,000 points, size class 11
+        eval_dev(mrs, c, e.X, e.f, e.n, e.eps, e.mu, 1)
+        srv = mrs.mrs_server_start(c, mrs.MRS_FP32C, 1 << 30, 4)
+        try:
+            t = mrs.mrs_server_submit(srv, 0, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, e.rod()))
+            st, _, _ = mrs.mrs_server_wait(srv, t, e.N, timeout_s=60)
+            assert st == mrs.MRS_OK
+        finally:
+            mrs.mrs_server_stop(srv)
+        _, rows = _table(path)
+        assert rows == []
+        h = mrs.mrs_ensemble_create(c, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, e.rod()))
+        try:
+            mrs.mrs_ensemble_eval(c, h, mrs.MRS_FP32C, True)
+        finally:
+            mrs.mrs_ensemble_destroy(h)
+        _, rows = _table(path)
+        assert [(int(r[0]), int(r[1])) for r in rows] == [(1, 11)]
+    finally:
+        mrs.mrs_context_destroy(c)
