@@ -427,6 +427,41 @@ def bench_slices(mrs, ctx, steps, args):
             "plain_pairs_per_s": pairs / tp, "speedup": tp / tb, "identical_results": bool(same)}
 
 
+def bench_copies(mrs, ctx, e, dt, copies=(4, 8), reps=10):
+    """The FP32C pair kernel over one launch of n copies of the ensemble
+    (`reps` batched forward-Euler steps queued back to back, as the
+    headline's steps are) for the two copy counts, interleaved, HIP events
+    around the pair launches: the marginal cost of one copy in a longer grid
+    (difference of the two, which cancels the fixed cost of a launch and is
+    taken under the same sustained load), with its roofline, and the fixed
+    cost that remains of the smaller launch."""
+    rod = mrs.rod_params(*(getattr(e.rod(), k) for k in ("a", "b", "omega0", "ds")))
+    lo, hi = copies
+    hs = [mrs.mrs_ensemble_create(ctx, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod) for _ in range(hi)]
+    try:
+        times = {lo: [], hi: []}
+        for n in times:  # plans and warm-up
+            mrs.mrs_batch_step(ctx, hs[:n], mrs.MRS_EULER, dt, 2, mrs.MRS_FP32C, True, use_graph=False)
+        for _ in range(3):
+            for n in times:
+                mrs.mrs_profile_reset(ctx)
+                mrs.mrs_profile_select(ctx, "pairs_tile")
+                mrs.mrs_profile_enable(ctx, True)
+                mrs.mrs_batch_step(ctx, hs[:n], mrs.MRS_EULER, dt, reps, mrs.MRS_FP32C, True, use_graph=False)
+                mrs.mrs_profile_enable(ctx, False)
+                k, ms = mrs.mrs_profile_query(ctx, "pairs_tile")
+                times[n].append(1e3 * ms / k)
+        mrs.mrs_profile_reset(ctx)
+    finally:
+        for h in hs:
+            mrs.mrs_ensemble_destroy(h)
+    tl, th = float(np.median(times[lo])), float(np.median(times[hi]))
+    marginal = (th - tl) / (hi - lo)
+    return {"copies": list(copies), "pair_launch_us": {str(lo): tl, str(hi): th},
+            "fixed_us": tl - lo * marginal, "marginal_us_per_copy": marginal,
+            "marginal_roofline": roofline(e.N * e.N, 1e-6 * marginal, PEAK_FP32_TFLOPS)}
+
+
 def bench_parareal(mrs, ctx, prec, tol, coarse_steps):
     """Parareal on one GPU for the 3,200-point slice base ensemble (external torques
     scaled by 1e-2): 16 slices of 200 RK4 steps at dt = 1e-5 (fine), forward
@@ -707,11 +742,13 @@ def main():
             res[tag]["chunks"] = mrs.mrs_tune_get(ctx, e.N, prec)["chunks"]
             res[tag]["traffic"] = measured_traffic(mrs, args.workload, tag, e.N, prec, n_cu)
         extra = args.workload == "ens12800" and not args.no_extra
-        large = slices_leg = large_subset = None
+        large = slices_leg = large_subset = copies_leg = None
         if extra:
             large, large_subset = bench_large(mrs, ctx, n_cu)
             log(f"16 slices x 3,200 points, {args.steps} RK4 steps: batched graph vs plain")
             slices_leg = bench_slices(mrs, ctx, args.steps, args)
+            log("12,800-point pair kernel: 4 and 8 copies in one launch")
+            copies_leg = bench_copies(mrs, ctx, e, args.dt)
         cpu, errs = (None, None)
         if not args.no_cpu:
             log("cpu baseline (oracle)")
@@ -773,6 +810,7 @@ def main():
         line["large_256000"] = large
     if slices_leg is not None:
         line["slices_16x3200"] = slices_leg
+        line["pairs_copies_12800"] = copies_leg
     print(json.dumps(line), flush=True)
 
 
