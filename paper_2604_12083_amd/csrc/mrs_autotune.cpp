@@ -312,7 +312,7 @@ mrs_status mrs_autotune(mrs_context *ctx, int64_t n, mrs_precision prec, int32_t
             if (st == MRS_OK && r >= 0) times[i].push_back(ms);
         }
     };
-    // round 1: every candidate once; round 2: the fastest quarter (at least
+    // first pass: every candidate once; second pass: the fastest quarter (at least
     // four) and the automatic configuration `reps` more times, interleaved
     // so that slow drifts of the clock touch every candidate alike
     for (size_t i = 0; i < cands.size() && st == MRS_OK; i++) run(i, 1);
