@@ -11,19 +11,28 @@ import subprocess
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SKIP_DIRS = {".git", "_work", "gpurun_out", "_build", "__pycache__", ".pytest_cache", "profiles", "tests"}
+# what build() compiles and imports: the package, the oracle, the C header,
+# the input generators and the entry module (sources only)
+SOURCE_ROOTS = ("paper_2604_12083_amd", "oracle", "include", "synth", "__graft_entry__.py")
+SKIP_DIRS = {"_build", "__pycache__"}
 SKIP_EXT = (".so", ".o", ".a", ".pyc", ".log")
 
 
 def _copy_sources(dst):
-    for dirpath, dirnames, filenames in os.walk(ROOT):
-        dirnames[:] = [d for d in dirnames if d not in SKIP_DIRS and not d.startswith(".")]
-        rel = os.path.relpath(dirpath, ROOT)
-        os.makedirs(os.path.join(dst, rel), exist_ok=True)
-        for f in filenames:
-            if f.endswith(SKIP_EXT) or ".so.tmp" in f:
-                continue
-            shutil.copy2(os.path.join(dirpath, f), os.path.join(dst, rel, f))
+    os.makedirs(dst, exist_ok=True)
+    for top in SOURCE_ROOTS:
+        src = os.path.join(ROOT, top)
+        if os.path.isfile(src):
+            shutil.copy2(src, os.path.join(dst, top))
+            continue
+        for dirpath, dirnames, filenames in os.walk(src):
+            dirnames[:] = [d for d in dirnames if d not in SKIP_DIRS and not d.startswith(".")]
+            rel = os.path.relpath(dirpath, ROOT)
+            os.makedirs(os.path.join(dst, rel), exist_ok=True)
+            for f in filenames:
+                if f.endswith(SKIP_EXT) or ".so.tmp" in f:
+                    continue
+                shutil.copy2(os.path.join(dirpath, f), os.path.join(dst, rel, f))
 
 
 def test_build_from_clean_tree(tmp_path):
