@@ -261,16 +261,18 @@ def cpu_model():
     return None
 
 
-# Algorithmic bytes per point of the frame update in FP64: the rod stage reads
-# X, D (96 B) and writes the point loads (48 B); the Euler update reads X, D,
-# U, Omega (144 B) and writes X, D (96 B).
-ROD_BYTES_PER_POINT = 144
+# Algorithmic bytes per point of the frame update: the rod stage reads X, D
+# (96 B) and writes the point's source record (48 B); with FP32C it also
+# writes the source-block descriptors, reading X again (24 B) and writing the
+# anchored position (16 B) and 1/64 of a 64-B block descriptor.  The Euler
+# update reads X, D, U, Omega (144 B) and writes X, D (96 B).
+ROD_BYTES_PER_POINT = {"fp64": 144, "fp32c": 144 + 24 + 16 + 1}
 EULER_BYTES_PER_POINT = 240
 
 
-def frame_update_gbps(n_points, kernels):
+def frame_update_gbps(n_points, kernels, prec="fp64"):
     out = {}
-    for name, nbytes in (("rod_forces", ROD_BYTES_PER_POINT), ("reduce_euler", EULER_BYTES_PER_POINT)):
+    for name, nbytes in (("rod_forces", ROD_BYTES_PER_POINT[prec]), ("reduce_euler", EULER_BYTES_PER_POINT)):
         if name in kernels and kernels[name]["avg_us"] > 0:
             out[name] = round(nbytes * n_points / (kernels[name]["avg_us"] * 1e-6) / 1e9, 1)
     return out
@@ -771,7 +773,7 @@ def main():
             "settle_s": round(r["settle_s"], 3),
             "clock_mhz": r["clock_mhz"],
             "kernels_avg_us": {k: round(v["avg_us"], 2) for k, v in r["kernels"].items()},
-            "frame_update_GBps": frame_update_gbps(e.N, r["kernels"]),
+            "frame_update_GBps": frame_update_gbps(e.N, r["kernels"], tag),
         }
 
     s32 = summary(res["fp32c"], PEAK_FP32_TFLOPS, "fp32c")

@@ -151,6 +151,53 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Source blocks of the FP32C tiled kernels.  Boxes are taken over the hi
+// parts of the positions and then widened by 2^-23 of their largest
+// coordinate magnitude on every side, which covers the lo parts
+// (|lo| <= 2^-24 |hi|), so box tests hold for the exact positions.
+constexpr float kBoxWiden = 1.0f / 8388608.0f;  // 2^-23
+
+// Widens a hi-part box [lo, hi] to contain the exact positions.
+__device__ __forceinline__ void widen_box(float *lo, float *hi) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const float m = fmaxf(fabsf(lo[k]), fabsf(hi[k])) * kBoxWiden;
+        lo[k] -= m;
+        hi[k] += m;
+    }
+}
+
+// Descriptor of the aligned 64-point block b of an ensemble, computed by one
+// wave whose lane l holds point 64 b + l (real: below N) with position hi + lo
+// (the record's split): the widened box of the real points' hi parts, its
+// centre c, the squared half-diagonal, and every real point's anchored
+// position w = (hi - c) + lo.  The tiled pair kernels read these instead of
+// reducing every staged block again (the same values for every target tile).
+// A block's box and centre depend on its real points only, in any order.
+__device__ __forceinline__ void src_block_desc(float4 *__restrict__ wanch, float *__restrict__ blk, int b, int i,
+                                               bool real, float hx, float hy, float hz, float lx, float ly,
+                                               float lz) {
+    float lo[3], hi[3], ctr[3], hd2 = 0.0f;
+    lo[0] = wave_min(real ? hx : INFINITY); lo[1] = wave_min(real ? hy : INFINITY);
+    lo[2] = wave_min(real ? hz : INFINITY);
+    hi[0] = wave_max(real ? hx : -INFINITY); hi[1] = wave_max(real ? hy : -INFINITY);
+    hi[2] = wave_max(real ? hz : -INFINITY);
+    widen_box(lo, hi);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        ctr[k] = 0.5f * (lo[k] + hi[k]);
+        const float h = 0.5f * (hi[k] - lo[k]);
+        hd2 = fmaf(h, h, hd2);
+    }
+    if (real) wanch[i] = make_float4((hx - ctr[0]) + lx, (hy - ctr[1]) + ly, (hz - ctr[2]) + lz, 0.0f);
+    if ((threadIdx.x & 63) == 0) {
+        float *d = blk + (size_t)kDescFloats * b;
+#pragma unroll
+        for (int k = 0; k < 3; k++) { d[k] = lo[k]; d[3 + k] = hi[k]; d[6 + k] = ctr[k]; }
+        d[9] = hd2;
+    }
+}
+
 // wave_sum of M values at once, level by level, so that the M exchanges of
 // a level are in flight together; each value is added exactly as wave_sum
 // adds it (same partners, same order), so the bits are the same.

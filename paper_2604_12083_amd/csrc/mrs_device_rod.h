@@ -20,13 +20,23 @@ namespace mrs {
 
 // ------------------------------------------------------- source records
 
+// FP32C position coordinate: x / eps split into hi + lo (the record form;
+// the block descriptors take their boxes from the same split).
+__device__ __forceinline__ void split_pos(double x, double inv_eps, float &h, float &l) {
+    FP_STRICT;
+    const double sx = x * inv_eps;
+    h = (float)sx;
+    l = (float)(sx - (double)h);
+}
+
 __device__ __forceinline__ RecF32 make_rec_f32(double x, double y, double z, double fx, double fy,
                                                double fz, double nx, double ny, double nz,
                                                double inv_eps) {
     FP_STRICT;
-    const double sx = x * inv_eps, sy = y * inv_eps, sz = z * inv_eps;
-    const float hx = (float)sx, hy = (float)sy, hz = (float)sz;
-    const float lx = (float)(sx - (double)hx), ly = (float)(sy - (double)hy), lz = (float)(sz - (double)hz);
+    float hx, hy, hz, lx, ly, lz;
+    split_pos(x, inv_eps, hx, lx);
+    split_pos(y, inv_eps, hy, ly);
+    split_pos(z, inv_eps, hz, lz);
     const double ie2 = inv_eps * inv_eps;
     RecF32 r;
     r.a = make_float4(hx, hy, hz, (float)(fx * inv_eps));

@@ -33,6 +33,21 @@ struct alignas(16) RecF64 {
     double x, y, z, fx, fy, fz, nx, ny, nz, pad;
 };
 
+// Source-block descriptor of the FP32C tiled pair kernels (one per aligned
+// 64-point block), padded to 64 bytes.
+constexpr int kDescFloats = 16;
+constexpr int kDescPoints = 64;
+
+// Bytes of a record buffer for n points in either precision: FP64 records,
+// or FP32C records followed by the anchored positions and the block
+// descriptors.
+inline size_t rec_buffer_bytes(int64_t n) {
+    const size_t f64 = (size_t)n * sizeof(RecF64);
+    const size_t f32 = (size_t)n * (sizeof(RecF32) + sizeof(float4)) +
+                       (size_t)((n + kDescPoints - 1) / kDescPoints) * kDescFloats * sizeof(float);
+    return f64 > f32 ? f64 : f32;
+}
+
 // Everything a kernel needs to know about one ensemble.  Arrays are SoA:
 // component c of point i of an N-point vector field lives at [c * N + i];
 // director i, component c of point k at [(3 i + c) * N + k].
@@ -50,6 +65,14 @@ struct EnsDesc {
     const double *fext, *next;  // external loads (SoA, or AoS when aos_io), may be null
     const double *Xin_aos;      // AoS positions when aos_io
     void *rec;         // source records (RecF32 or RecF64), N entries
+    // FP32C tiled pair kernels: per point its position relative to the centre
+    // of its aligned 64-point block (anchored form), and per block the
+    // descriptor (kDescFloats floats: widened hi-part box lo[3], hi[3],
+    // centre[3], squared half-diagonal); both follow the records in the same
+    // buffer (set_records) and are written with them (k_rod_forces
+    // descriptor items, k_pack_aos)
+    float4 *wanch;
+    float *blk;
     double *part;      // split-K partial sums [K][6][N]
     double *g_out, *m_out;  // optional AoS copies of the rod loads (tests)
     double eps, inv_eps, mu;
@@ -85,7 +108,9 @@ struct PairItem {
     int32_t ens, tgt0, ntgt, src0, nsrc, chunk;
 };
 
-// One block of the rod-force kernel: filament `fil` of ensemble `ens`.
+// One block of the rod-force kernel: filament `fil` of ensemble `ens`; or,
+// with fil = -1 - g (FP32C tiled configurations), the source-block
+// descriptors of blocks kBlock / 64 * g ... of ensemble `ens`, one per wave.
 struct RodItem {
     int32_t ens, fil;
 };
@@ -109,6 +134,16 @@ enum Epilogue : int {
 
 // Runge-Kutta schemes of the stage epilogue.
 enum RkScheme : int { RK_SCHEME_RK4 = 0, RK_SCHEME_RK2 = 1 };
+
+// Points the records of an ensemble of n points at rec (a buffer of
+// rec_buffer_bytes(n)); FP32C also places the anchored positions and block
+// descriptors behind the records, FP64 leaves them null.
+inline void set_records(EnsDesc &d, void *rec, int64_t n, bool fp32c) {
+    d.rec = rec;
+    char *b = static_cast<char *>(rec);
+    d.wanch = fp32c ? reinterpret_cast<float4 *>(b + (size_t)n * sizeof(RecF32)) : nullptr;
+    d.blk = fp32c ? reinterpret_cast<float *>(b + (size_t)n * (sizeof(RecF32) + sizeof(float4))) : nullptr;
+}
 
 // Launch wrappers (mrs_pairs.hip, mrs_kernels.hip).  All return the launch's hipError_t.
 hipError_t launch_pack_aos(int prec, const EnsDesc *d_desc, const EnsDesc &h_desc,

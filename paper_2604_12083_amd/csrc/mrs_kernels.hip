@@ -16,6 +16,7 @@
 // hi + lo, forces f/eps and torques n/eps^2; FP64 records hold x, f, n.
 #include <hip/hip_runtime.h>
 
+#include "mrs_device_pairs.h"
 #include "mrs_device_rod.h"
 #include "mrs_internal.h"
 
@@ -35,21 +36,46 @@ __global__ __launch_bounds__(kBlock) void k_rotsqrt(int64_t count, const double 
 
 // ------------------------------------------------------------ pack / rod
 
+// Descriptor of source block b from the positions X (SoA, or AoS with
+// aos), one wave: the same hi/lo split as the records (split_pos).
+__device__ __forceinline__ void block_desc_from_x(const EnsDesc &E, const double *__restrict__ X, bool aos, int b) {
+    const int N = E.N;
+    const int i = b * kDescPoints + (int)(threadIdx.x & 63);
+    const bool real = i < N;
+    float h[3] = {0.f, 0.f, 0.f}, l[3] = {0.f, 0.f, 0.f};
+    if (real) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) split_pos(aos ? X[3 * (size_t)i + c] : X[(size_t)c * N + i], E.inv_eps, h[c], l[c]);
+    }
+    src_block_desc(E.wanch, E.blk, b, i, real, h[0], h[1], h[2], l[0], l[1], l[2]);
+}
+
+// One thread per point; with FP32C block descriptors (E.blk set) every wave
+// (64 consecutive points, block-aligned) also writes its block's descriptor.
 __global__ __launch_bounds__(kBlock) void k_pack_aos(int prec, const EnsDesc *__restrict__ desc) {
     const EnsDesc &E = desc[0];
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= E.N) return;
     const double *X = E.Xin_aos, *f = E.fext, *n = E.next;
-    store_rec(prec, E.rec, i, X[3 * i], X[3 * i + 1], X[3 * i + 2], f[3 * i], f[3 * i + 1],
-              f[3 * i + 2], n[3 * i], n[3 * i + 1], n[3 * i + 2], E.inv_eps);
+    if (i < E.N)
+        store_rec(prec, E.rec, i, X[3 * i], X[3 * i + 1], X[3 * i + 2], f[3 * i], f[3 * i + 1],
+                  f[3 * i + 2], n[3 * i], n[3 * i + 1], n[3 * i + 2], E.inv_eps);
+    const int b = i / kDescPoints;  // wave-uniform
+    if (prec == 1 && E.blk && b * kDescPoints < E.N) block_desc_from_x(E, X, true, b);
 }
 
-// One block per filament (rod_filament).
+// One block per filament (rod_filament), or one wave per source-block
+// descriptor (RodItem with fil < 0): the descriptors depend only on the
+// positions, so they are written beside the filaments' records.
 __global__ __launch_bounds__(kBlock) void k_rod_forces(int prec, int stage_state, int elastic, int scheme,
                                                        int stage, double dt, const EnsDesc *__restrict__ desc,
                                                        const RodItem *__restrict__ items) {
     const RodItem it = items[blockIdx.x];
     const EnsDesc &E = desc[it.ens];
+    if (it.fil < 0) {  // the whole block takes this branch
+        const int b = (-1 - it.fil) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+        if (b * kDescPoints < E.N) block_desc_from_x(E, stage_state ? E.Xs : E.X, false, b);
+        return;
+    }
     rod_filament<kBlock>(prec, stage_state, elastic, scheme, stage, dt, E, it.fil, E.rec);
 }
 

@@ -41,31 +41,19 @@ __device__ __forceinline__ float box_gap2(const float *lo0, const float *hi0, co
 }
 
 // A wave whose target box is farther than this (squared, in units of eps)
-// from a source block's box has no near pair in it (rho >= 4).  The boxes are
-// taken over the hi parts of the positions and then widened by 2^-23 of
-// their largest coordinate magnitude on every side, which covers the lo parts
-// (|lo| <= 2^-24 |hi|), so the test holds for the exact positions at any
-// distance from the origin.
+// from a source block's box has no near pair in it (rho >= 4).  The boxes
+// are the widened hi-part boxes of the block descriptors (src_block_desc),
+// which contain the exact positions at any distance from the origin.
 constexpr float kFarBoxGap2 = 17.0f;
-constexpr float kBoxWiden = 1.0f / 8388608.0f;  // 2^-23
-
-// Widens a hi-part box [lo, hi] to contain the exact positions.
-__device__ __forceinline__ void widen_box(float *lo, float *hi) {
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-        const float m = fmaxf(fabsf(lo[k]), fabsf(hi[k])) * kBoxWiden;
-        lo[k] -= m;
-        hi[k] += m;
-    }
-}
 
 // Anchored far blocks.  Relative to the centre c of a 64-source block's box,
-// a source sits at w = (sh - c) + sl and a target at u = (th - c) + tl, both
-// rounded once to FP32, and r = u - w costs 3 instead of 9 operations.  Each
-// rounding is at most 2^-24 of |u| <= |r| + |w| or of |w|; with the gap
-// between the boxes at least 4 times the block's half-diagonal, |w| <= |r|/4
-// and r keeps a relative error below 2^-21, against 2^-23 for the exact
-// hi/lo difference of the other paths.
+// a source sits at w = (sh - c) + sl (stored with the block descriptors) and
+// a target at u = (th - c) + tl, both rounded once to FP32, and r = u - w
+// costs 3 instead of 9 operations.  Each rounding is at most 2^-24 of
+// |u| <= |r| + |w| or of |w|; with the gap between the boxes at least 4
+// times the block's half-diagonal, |w| <= |r|/4 and r keeps a relative error
+// below 2^-21, against 2^-23 for the exact hi/lo difference of the other
+// paths.
 constexpr float kAnchorGapRatio2 = 16.0f;
 
 // Persistent schedule.  The grid holds as many blocks as the device keeps
@@ -120,9 +108,8 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
     // nx, ny), sN = (nz, lo), sH = (hi, 0)
     __shared__ float4 sW[kSrcTile], sF[kSrcTile], sN[kSrcTile], sH[kSrcTile];
     __shared__ double sNear[6][T][kBlock];  // FP64 near-pair sums, one slot per lane and target
-    // per 64-source block: hi-part box lo, hi, anchor c, squared half-diagonal
-    __shared__ float sBox[kSrcTile / kKahanBlock][10];
-    static_assert(kSrcTile / kKahanBlock == kBlock / 64, "one source block per wave");
+    static_assert(kSrcTile / kKahanBlock == kBlock / 64 && kKahanBlock == kDescPoints,
+                  "one source block (one descriptor) per wave");
     __shared__ int sNext;
     int idx = PERSIST ? claim_item(queue, &sNext) : (int)blockIdx.x;
     while (idx < n_items) {
@@ -134,6 +121,9 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
     const int tl = QUAD ? (tid & 63) : tid;
     float thx[T], thy[T], thz[T], tlx[T], tly[T], tlz[T];
     float s[T][6], c[T][6];
+    // box of this wave's targets: the descriptors of the blocks they lie in
+    // (tiles start on block boundaries; lanes past the tile repeat its last
+    // target, which lies in the block of the last real lane)
     float tlo[3] = {INFINITY, INFINITY, INFINITY}, thi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
     for (int t = 0; t < T; t++) {
@@ -141,14 +131,13 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
         const RecF32 r = rec[it.tgt0 + li];
         thx[t] = r.a.x; thy[t] = r.a.y; thz[t] = r.a.z;
         tlx[t] = r.b.x; tly[t] = r.b.y; tlz[t] = r.b.z;
-        tlo[0] = fminf(tlo[0], thx[t]); tlo[1] = fminf(tlo[1], thy[t]); tlo[2] = fminf(tlo[2], thz[t]);
-        thi[0] = fmaxf(thi[0], thx[t]); thi[1] = fmaxf(thi[1], thy[t]); thi[2] = fmaxf(thi[2], thz[t]);
+        const int wb = (it.tgt0 + min((tl & ~63) + t * kBlock, it.ntgt - 1)) / kDescPoints;  // wave-uniform
+        const float *d = E.blk + (size_t)kDescFloats * wb;
+#pragma unroll
+        for (int k = 0; k < 3; k++) { tlo[k] = fminf(tlo[k], d[k]); thi[k] = fmaxf(thi[k], d[3 + k]); }
 #pragma unroll
         for (int k = 0; k < 6; k++) { s[t][k] = 0.0f; c[t][k] = 0.0f; sNear[k][t][tid] = 0.0; }
     }
-#pragma unroll
-    for (int k = 0; k < 3; k++) { tlo[k] = wave_min(tlo[k]); thi[k] = wave_max(thi[k]); }
-    widen_box(tlo, thi);
     for (int base = 0; base < it.nsrc; base += kSrcTile) {
         if (QUAD) {
             if (base + (tid & ~63) >= it.nsrc) break;  // wave-uniform: this wave has no block left
@@ -156,26 +145,15 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
         } else {
             __syncthreads();
         }
+        // this wave stages source block tid / 64 (its anchored positions
+        // from the descriptors); padding lanes stage zero loads
         const int j = base + tid;
         const bool real = j < it.nsrc;
-        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, cc = a;
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, cc = a, w = a;
         if (real) {
             const RecF32 r = rec[it.src0 + j];
             a = r.a; b = r.b; cc = r.c;
-        }
-        // this wave stages source block tid / 64: its box (padding excluded) and anchor
-        float lo[3], hi[3], ctr[3], hd2 = 0.0f;
-        lo[0] = wave_min(real ? a.x : INFINITY); lo[1] = wave_min(real ? a.y : INFINITY);
-        lo[2] = wave_min(real ? a.z : INFINITY);
-        hi[0] = wave_max(real ? a.x : -INFINITY); hi[1] = wave_max(real ? a.y : -INFINITY);
-        hi[2] = wave_max(real ? a.z : -INFINITY);
-        widen_box(lo, hi);
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            // a block without a real source (never evaluated) gets a finite anchor
-            ctr[k] = lo[k] <= hi[k] ? 0.5f * (lo[k] + hi[k]) : 0.0f;
-            const float h = lo[k] <= hi[k] ? 0.5f * (hi[k] - lo[k]) : 0.0f;
-            hd2 = fmaf(h, h, hd2);
+            w = E.wanch[it.src0 + j];
         }
         // a source with contact forces enters the FP32 sums with zero loads;
         // the FP64 pass evaluates it with its own loads
@@ -184,16 +162,10 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
             const int jg = it.src0 + j;
             contact = (E.lj_mask[jg / kLjMaskPoints] >> (jg % kLjMaskPoints)) & 1;
         }
-        sW[tid] = make_float4((a.x - ctr[0]) + b.x, (a.y - ctr[1]) + b.y, (a.z - ctr[2]) + b.z, contact ? 0.0f : a.w);
+        sW[tid] = make_float4(w.x, w.y, w.z, contact ? 0.0f : a.w);
         sF[tid] = contact ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(b.w, cc.x, cc.y, cc.z);
         sN[tid] = make_float4(contact ? 0.0f : cc.w, b.x, b.y, b.z);
         sH[tid] = make_float4(a.x, a.y, a.z, 0.0f);
-        if ((tid & 63) == 0) {
-            float *bx = sBox[tid >> 6];
-#pragma unroll
-            for (int k = 0; k < 3; k++) { bx[k] = lo[k]; bx[3 + k] = hi[k]; bx[6 + k] = ctr[k]; }
-            bx[9] = hd2;
-        }
         if (QUAD) wave_sync();
         else __syncthreads();
         const int cnt = min(kSrcTile, it.nsrc - base);
@@ -225,7 +197,8 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
 #pragma unroll
                 for (int k = 0; k < 6; k++) p[t][k] = 0.0f;
             }
-            const float *bx = sBox[sb / kKahanBlock];
+            // descriptor of this source block (wave-uniform: scalar loads)
+            const float *bx = E.blk + (size_t)kDescFloats * ((it.src0 + base + sb) / kDescPoints);
             const float gap2 = box_gap2(tlo, thi, bx, bx + 3);
             // sources of this block that carry contact forces (wave-uniform)
             const uint64_t ljm = E.lj_mask ? E.lj_mask[(it.src0 + base + sb) / kLjMaskPoints] : 0;

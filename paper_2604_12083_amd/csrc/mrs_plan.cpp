@@ -134,6 +134,12 @@ void add_items(Plan &P, int e, int64_t N, int n_fil, const PairCfg &c) {
                                 (int)std::min<int64_t>(c.tail_chunk, N - s0), k});
     }
     for (int f = 0; f < n_fil; f++) P.rods.push_back({e, f});
+    // FP32C tiled kernels read the source-block descriptors, which the rod
+    // launch writes: one item per kBlock / 64 blocks
+    if (P.prec == MRS_FP32C && c.mode != PAIR_SPLIT && n_fil > 0) {
+        const int64_t groups = (N + kBlock - 1) / kBlock;
+        for (int64_t g = 0; g < groups; g++) P.rods.push_back({e, (int)(-1 - g)});
+    }
     for (int64_t p0 = 0; p0 < N; p0 += kReducePoints) P.pts.push_back({e, (int)p0});
     P.pairs_per_eval += N * N;
 }

@@ -152,7 +152,7 @@ static EnsDesc ensemble_desc(mrs_ensemble *E, int prec, const PairCfg &c) {
     d.fext = E->has_ext ? E->fext.as<double>() : nullptr;
     d.next = E->has_ext ? E->next.as<double>() : nullptr;
     d.Xin_aos = nullptr;
-    d.rec = E->rec.p;
+    set_records(d, E->rec.p, E->N, prec == MRS_FP32C);
     d.part = E->part.as<double>();
     d.g_out = d.m_out = nullptr;
     d.eps = E->eps;
@@ -372,10 +372,10 @@ hipError_t upload(mrs_context *ctx, void *dst, const void *src, size_t bytes, hi
 }
 
 size_t ensemble_bytes(int64_t N, int n_fil, bool has_ext, int K64, int K32) {
-    size_t per = (3 + 9 + 3 + 3 + 3 + 9 + 3 + 3) * sizeof(double) + sizeof(RecF64);
+    size_t per = (3 + 9 + 3 + 3 + 3 + 9 + 3 + 3) * sizeof(double);
     if (has_ext) per += 6 * sizeof(double);
     per += (size_t)std::max(K64, K32) * 6 * sizeof(double);
-    return per * (size_t)N + (size_t)(n_fil + 1) * sizeof(int32_t);
+    return per * (size_t)N + rec_buffer_bytes(N) + (size_t)(n_fil + 1) * sizeof(int32_t);
 }
 
 }  // namespace mrs
@@ -407,7 +407,7 @@ mrs_status ensemble_alloc(mrs_context *ctx, int32_t n_fil, const int32_t *offset
               E->D.reserve(v9) == hipSuccess && E->U.reserve(v3) == hipSuccess && E->W.reserve(v3) == hipSuccess &&
               E->Xs.reserve(v3) == hipSuccess && E->Ds.reserve(v9) == hipSuccess &&
               E->Ua.reserve(v3) == hipSuccess && E->Wa.reserve(v3) == hipSuccess && E->Ks.reserve(v3) == hipSuccess &&
-              E->rec.reserve((size_t)n * sizeof(RecF64)) == hipSuccess && E->clock.reserve(sizeof(double)) == hipSuccess;
+              E->rec.reserve(rec_buffer_bytes(n)) == hipSuccess && E->clock.reserve(sizeof(double)) == hipSuccess;
     if (ok && has_ext) ok = E->fext.reserve(v3) == hipSuccess && E->next.reserve(v3) == hipSuccess;
     if (!ok) return fail(ctx, MRS_ENOMEM, "ensemble allocation (%lld points)", (long long)n);
     if (!init) return MRS_OK;
@@ -697,7 +697,8 @@ static void eval_layout(EvalLayout &L, int64_t n, const double *dX, const double
     d.next = dt;
     d.U = dU;
     d.W = dW;
-    d.rec = sc.rec;
+    // FP32C block descriptors only for the tiled kernels (k_pack_aos writes them)
+    set_records(d, sc.rec, n, p == MRS_FP32C && c.mode != PAIR_SPLIT);
     d.part = sc.part;
     d.eps = eps;
     d.inv_eps = 1.0 / eps;
@@ -760,7 +761,7 @@ mrs_status mrs_eval_device(mrs_context *ctx, int64_t n, const double *dX, const 
     // the scratch below is shared by every evaluation of the context: this
     // one waits on its stream for the previous one (any stream) to finish,
     // and growing a buffer (which frees the old one) first waits on the host
-    const size_t rec_bytes = (size_t)n * sizeof(RecF64);
+    const size_t rec_bytes = rec_buffer_bytes(n);
     const size_t part_bytes = (size_t)c.K * 6 * (size_t)n * sizeof(double);
     if (ctx->eval_pending) {
         if (rec_bytes > ctx->eval_rec.bytes || part_bytes > ctx->eval_part.bytes)
@@ -798,10 +799,11 @@ mrs_status mrs_eval_device_noalloc(mrs_context *ctx, int64_t n, const double *dX
     hipStream_t s = pick_stream(ctx, stream);
     const int p = (int)prec;
     // [descriptor + work lists | source records | partial sums]: the records
-    // take the FP64 size in both precisions; the partials take the rest, and
-    // a configuration whose source chunks need more gets fewer, longer chunks
+    // take the larger size of the two precisions (rec_buffer_bytes); the
+    // partials take the rest, and a configuration whose source chunks need
+    // more gets fewer, longer chunks
     const size_t rec_off = kNoallocListBytes;
-    const size_t part_off = rec_off + (((size_t)n * sizeof(RecF64) + 255) & ~size_t(255));
+    const size_t part_off = rec_off + ((rec_buffer_bytes(n) + 255) & ~size_t(255));
     const size_t per_chunk = (size_t)n * 6 * sizeof(double);
     const int64_t k_room = (int64_t)((kNoallocBytes - part_off) / per_chunk);
     PairCfg c = choose_cfg(ctx, n, p);

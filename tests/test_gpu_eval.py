@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import eval_dev, say
+from tests.gpu_util import eval_dev, rod_of, say
 
 pytestmark = pytest.mark.gpu
 
@@ -272,5 +272,36 @@ def test_fp32c_every_block_path_far_from_origin(mrs, tpl):
         _check(mrs, c, X, f, n, eps, 1.0, 1, f"paths-tpl{tpl}")
         Xs = X + np.array([8000.0, -6000.0, 7000.0]) * eps
         _check(mrs, c, Xs, f, n, eps, 1.0, 1, f"paths-shifted-tpl{tpl}")
+    finally:
+        mrs.mrs_context_destroy(c)
+
+
+@pytest.mark.parametrize("mode,tpl", [(0, 1), (0, 2), (2, 1)])
+def test_fp32c_tiled_block_descriptors_small_and_ragged(mrs, mode, tpl):
+    """The tiled FP32C kernels (one or two targets per lane, and the
+    four-wave split) read a descriptor per aligned 64-point block (box,
+    centre, anchored positions) written beside the records: by the pack
+    kernel of a one-shot evaluation and by the rod launch of a resident
+    ensemble.  Forced onto sizes below one block, one block and ragged last
+    blocks, both routes match the oracle."""
+    c = mrs.mrs_context_create(0)
+    try:
+        for N in (1, 2, 3, 5, 63, 64, 65, 300):
+            X, f, n = _cloud(N, 900 + N, box=0.3)
+            mrs.mrs_tune_set(c, N, 1, mode, tpl, 0)
+            _check(mrs, c, X, f, n, 0.02, 1.0, 1, f"tiled-mode{mode}-tpl{tpl}")
+        for nfil, M in ((1, 3), (1, 64), (5, 13), (4, 75), (3, 129)):
+            e = synth.filaments(nfil, M, 2.0, 50 + nfil * M)
+            mrs.mrs_tune_set(c, e.N, 1, mode, tpl, 0)
+            h = mrs.mrs_ensemble_create(c, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, e.rod()))
+            try:
+                mrs.mrs_ensemble_eval(c, h, mrs.MRS_FP32C, False)
+                _, _, U, W = mrs.mrs_ensemble_get(c, h)
+            finally:
+                mrs.mrs_ensemble_destroy(h)
+            Uo, Wo = oracle.mrs_eval(e.X, e.f, e.n, e.eps, e.mu)
+            eu, ew = oracle.rel_err(U, Uo), oracle.rel_err(W, Wo)
+            say(f"ensemble {nfil}x{M} mode={mode} tpl={tpl}: U {eu:.3e} W {ew:.3e}")
+            assert eu <= TOL[1] and ew <= TOL[1], (nfil, M)
     finally:
         mrs.mrs_context_destroy(c)
