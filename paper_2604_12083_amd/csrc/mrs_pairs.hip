@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
 #pragma unroll
                 for (int k = 0; k < 6; k++) p[t][k] = 0.0f;
             }
-            // descriptor of this source block (wave-uniform: scalar loads)
+            // descriptor of this source block (wave-uniform)
             const float *bx = E.blk + (size_t)kDescFloats * ((it.src0 + base + sb) / kDescPoints);
             const float gap2 = box_gap2(tlo, thi, bx, bx + 3);
             // sources of this block that carry contact forces (wave-uniform)
