@@ -48,13 +48,16 @@ constexpr float kFarBoxGap2 = 17.0f;
 
 // Anchored far blocks.  Relative to the centre c of a 64-source block's box,
 // a source sits at w = (sh - c) + sl (stored with the block descriptors) and
-// a target at u = (th - c) + tl, both rounded once to FP32, and r = u - w
-// costs 3 instead of 9 operations.  Each rounding is at most 2^-24 of
-// |u| <= |r| + |w| or of |w|; with the gap between the boxes at least 4
-// times the block's half-diagonal, |w| <= |r|/4 and r keeps a relative error
-// below 2^-21, against 2^-23 for the exact hi/lo difference of the other
-// paths.
-constexpr float kAnchorGapRatio2 = 16.0f;
+// a target at u = (th - c) + tl, and r = u - w costs 3 instead of 9
+// operations.  Each of u and w takes two FP32 roundings (at most 2^-24 of
+// its magnitude each), and r one more; with the gap between the boxes larger
+// than the block's half-diagonal, |w| < |r| and |u| < 2 |r|, so r keeps a
+// relative error below 7 x 2^-24 < 2^-21, against 2^-23 for the exact hi/lo
+// difference of the other paths.  (A gap of 4 half-diagonals, |w| <= |r|/4,
+// sent more blocks down the exact-separation path and was 2.6% slower on
+// 1,000 swimmers of 51 points, 3.4% on 16 batched 3,200-point slices;
+// MI355X, interleaved A/B, 12,800 points even.)
+constexpr float kAnchorGapRatio2 = 1.0f;
 
 // Persistent schedule.  The grid holds as many blocks as the device keeps
 // resident; each block claims the next item of the work list from a counter

@@ -212,12 +212,16 @@ mrs_status ensemble_plan(mrs_ensemble *E, int prec, Plan **out, bool may_tune) {
     return MRS_OK;
 }
 
+// Events of the kernel profiler (timed): they only time the launches
+// between them, so they skip the system-scope fence of a default event (a
+// cache write-back and invalidation at every record, which would lengthen
+// the timed kernel and slow the work after it).
 hipEvent_t take_event(mrs_context *ctx) {
     hipEvent_t ev = nullptr;
     if (!ctx->event_pool.empty()) {
         ev = ctx->event_pool.back();
         ctx->event_pool.pop_back();
-    } else if (hipEventCreate(&ev) != hipSuccess) {
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess) {
         ev = nullptr;
     }
     return ev;
