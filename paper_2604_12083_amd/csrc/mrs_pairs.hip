@@ -59,6 +59,16 @@ constexpr float kFarBoxGap2 = 17.0f;
 // MI355X, interleaved A/B, 12,800 points even.)
 constexpr float kAnchorGapRatio2 = 1.0f;
 
+// Block descriptors and contact masks are written before the pair launch and
+// only read by it, so the kernel reads them through the constant address
+// space: the loads are wave-uniform and go through the scalar cache into
+// scalar registers.
+typedef __attribute__((address_space(4))) const float desc_float;
+typedef __attribute__((address_space(4))) const uint64_t mask_word;
+__device__ __forceinline__ const desc_float *desc_at(const float *blk, int64_t b) {
+    return (const desc_float *)(blk + (size_t)kDescFloats * b);
+}
+
 // Persistent schedule.  The grid holds as many blocks as the device keeps
 // resident; each block claims the next item of the work list from a counter
 // (queue[0], an ordinary vector atomic from one lane) until the list is
@@ -135,7 +145,7 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
         thx[t] = r.a.x; thy[t] = r.a.y; thz[t] = r.a.z;
         tlx[t] = r.b.x; tly[t] = r.b.y; tlz[t] = r.b.z;
         const int wb = (it.tgt0 + min((tl & ~63) + t * kBlock, it.ntgt - 1)) / kDescPoints;  // wave-uniform
-        const float *d = E.blk + (size_t)kDescFloats * wb;
+        const desc_float *d = desc_at(E.blk, wb);
 #pragma unroll
         for (int k = 0; k < 3; k++) { tlo[k] = fminf(tlo[k], d[k]); thi[k] = fmaxf(thi[k], d[3 + k]); }
 #pragma unroll
@@ -201,10 +211,15 @@ __global__ __launch_bounds__(kBlock, T == 1 ? 5 : 3) void k_pairs_tile_f32(const
                 for (int k = 0; k < 6; k++) p[t][k] = 0.0f;
             }
             // descriptor of this source block (wave-uniform)
-            const float *bx = E.blk + (size_t)kDescFloats * ((it.src0 + base + sb) / kDescPoints);
+            float bx[10];
+            {
+                const desc_float *bd = desc_at(E.blk, (it.src0 + base + sb) / kDescPoints);
+#pragma unroll
+                for (int k = 0; k < 10; k++) bx[k] = bd[k];
+            }
             const float gap2 = box_gap2(tlo, thi, bx, bx + 3);
             // sources of this block that carry contact forces (wave-uniform)
-            const uint64_t ljm = E.lj_mask ? E.lj_mask[(it.src0 + base + sb) / kLjMaskPoints] : 0;
+            const uint64_t ljm = E.lj_mask ? ((const mask_word *)E.lj_mask)[(it.src0 + base + sb) / kLjMaskPoints] : 0;
             if (gap2 > kFarBoxGap2 && gap2 > kAnchorGapRatio2 * bx[9]) {
                 // wave-uniform: no near pair, separation from the block's anchor
                 float ux[T], uy[T], uz[T];
