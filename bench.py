@@ -41,14 +41,14 @@ FLOPS_PER_PAIR = 92       # algorithmic flops of one (target, source) evaluation
 # `mrs_plan_items` gives for the workload) they were taken on: any other
 # kernel or decomposition reports null.
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_12083_amd", "csrc", f) for f in ("mrs_pairs.hip", "mrs_device_pairs.h")]
-KERNEL_SHA = "1266edb956335be458933664b7e6eecf5c9e1cfb3bfbc47c076137895cf9c43e"
+KERNEL_SHA = "40f34d49df4e05869d604daebf4eddf5ac4a3fb0ed492161478c62626b0aa46b"
 MEASURED_TRAFFIC = {
-    ("ens12800", "fp32c", "678ec7c5e5d82ecf"): (3545.20 * 2.0 + 37200.0) * 1024,
+    ("ens12800", "fp32c", "678ec7c5e5d82ecf"): (3544.88 * 2.0 + 37200.0) * 1024,
     ("ens12800", "fp64", "adb3c89bda2d142d"): (4134.13 * 2.0 + 30000.0) * 1024,
-    ("ens256000", "fp32c", "4a2b01f9e8a27aa9"): (226300.99 * 2.0 + 264000.0) * 1024,
-    ("ens256000", "fp64", "571ba5e594123b76"): (470570.40 * 2.0 + 396000.0) * 1024,
-    ("swim", "fp32c", "72ec18efbf0e53ad"): (41945.61 * 2.0 + 176934.68) * 1024,
-    ("swim", "fp64", "df10004c75444124"): (90395.70 * 2.0 + 148220.83) * 1024,
+    ("ens256000", "fp32c", "4a2b01f9e8a27aa9"): (228559.03 * 2.0 + 264000.0) * 1024,
+    ("ens256000", "fp64", "571ba5e594123b76"): (470549.45 * 2.0 + 396000.0) * 1024,
+    ("swim", "fp32c", "72ec18efbf0e53ad"): (42130.44 * 2.0 + 176944.22) * 1024,
+    ("swim", "fp64", "df10004c75444124"): (90394.48 * 2.0 + 148220.80) * 1024,
 }
 
 
