@@ -479,7 +479,10 @@ mrs_status mrs_parareal_pipelined(mrs_ensemble *ens, int32_t n_slices, mrs_integ
 /* When enabled, every kernel launch of the context is bracketed by HIP events
  * on the stream it is launched on.  mrs_profile_query waits for the recorded
  * events and returns the launch count and summed duration (milliseconds) of
- * the kernels whose name contains `kernel` (NULL or "" = all). */
+ * the kernels whose name contains `kernel` (NULL or "" = all).  The events
+ * only time: they skip the system-scope fence of a default event (no cache
+ * write-back or invalidation around the timed kernel), so they make no
+ * device memory visible to the host by themselves. */
 mrs_status mrs_profile_enable(mrs_context *ctx, int on);
 /* Restricts the bracketing to launches whose kernel name contains `kernel`
  * (NULL or "" = every launch), so that timing one kernel adds no events
