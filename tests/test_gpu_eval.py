@@ -305,3 +305,33 @@ def test_fp32c_tiled_block_descriptors_small_and_ragged(mrs, mode, tpl):
             assert eu <= TOL[1] and ew <= TOL[1], (nfil, M)
     finally:
         mrs.mrs_context_destroy(c)
+
+
+@pytest.mark.parametrize("cfg", [None, (0, 2, 0), (2, 1, 0)])
+def test_fp32c_descriptors_follow_the_state(mrs, cfg):
+    """The block descriptors (boxes, centres, anchored positions) are
+    rewritten with the records at every evaluation of a resident ensemble:
+    after its state moves to another geometry and then far from the origin,
+    each evaluation matches the oracle of the new state (a stale centre
+    would shift every anchored separation by the distance moved)."""
+    c = mrs.mrs_context_create(0)
+    try:
+        e = synth.filaments(20, 128, 4.0, 201)  # 2,560 points: tiled kernels
+        e2 = synth.filaments(20, 128, 4.0, 202)
+        if cfg is not None:
+            mrs.mrs_tune_set(c, e.N, 1, *cfg)
+        h = mrs.mrs_ensemble_create(c, e.offsets, e.X, e.D, e.f, e.n, e.eps, e.mu, rod_of(mrs, e.rod()))
+        try:
+            for tag, X, D in (("initial", e.X, e.D), ("moved", e2.X, e2.D),
+                              ("shifted", e2.X + np.array([40.0, -25.0, 60.0]), e2.D), ("back", e.X, e.D)):
+                mrs.mrs_ensemble_set_state(c, h, X, D)
+                mrs.mrs_ensemble_eval(c, h, mrs.MRS_FP32C, False)
+                _, _, U, W = mrs.mrs_ensemble_get(c, h)
+                Uo, Wo = oracle.mrs_eval(X, e.f, e.n, e.eps, e.mu)
+                eu, ew = oracle.rel_err(U, Uo), oracle.rel_err(W, Wo)
+                say(f"{tag} cfg={cfg}: U {eu:.3e} W {ew:.3e}")
+                assert eu <= TOL[1] and ew <= TOL[1], (tag, cfg)
+        finally:
+            mrs.mrs_ensemble_destroy(h)
+    finally:
+        mrs.mrs_context_destroy(c)
