@@ -77,7 +77,7 @@ PairCfg stored(int mode, int tpl, int K, int sched) {
 // automatic chunking, tail split included, so storing it changes nothing.
 PairCfg automatic_entry(int64_t n, int prec, int n_cu) {
     const PairCfg a = choose_cfg_for(nullptr, n, prec, n_cu);
-    return stored(a.mode, a.tpl, a.mode == PAIR_SPLIT ? 1 : 0, SCHED_GRID);
+    return stored(a.mode, a.tpl, a.mode == PAIR_SPLIT ? 1 : 0, a.sched);
 }
 
 // Candidates for n points; the first is the automatic configuration.

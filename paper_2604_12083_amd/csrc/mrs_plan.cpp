@@ -57,6 +57,15 @@ static bool small_grid(int64_t N, int tpl, int n_cu) { return blocks_at(N, tpl) 
 // stays where the batched cost is still moderate.
 static bool split_mode(int64_t N, int) { return N <= 1024; }
 
+// Automatic tiled configurations with at least this many blocks per CU run
+// the persistent schedule (blocks claim items from a queue).  In grids this
+// deep it was faster than the hardware grid on MI355X (interleaved A/B of
+// the pair kernel: 256,000 points -1.3% FP32C and -1.5% FP64, 1,000
+// swimmers (51,000 points, 58 blocks per CU) -1.4% FP32C; the tuner's
+// one-shot evaluations: 102,400 points -1.3% and -1.1%); in shallow grids
+// it is much slower (12,800 points, 12 blocks per CU: +20%).
+constexpr int kPersistentBlocksPerCu = 48;
+
 PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
     PairCfg c;
     bool small = false;
@@ -94,6 +103,8 @@ PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
     c.K = (int)std::max<int64_t>(1, (N + c.chunk - 1) / c.chunk);
     c.k_big = c.K;
     c.tail_start = c.tail_chunk = 0;
+    if (!tuned && c.mode == PAIR_TILE && tiles * c.K >= (int64_t)kPersistentBlocksPerCu * n_cu)
+        c.sched = SCHED_PERSISTENT;
     if (automatic && prec == MRS_FP32C && tiles * c.K >= (int64_t)4 * n_cu) {
         const int64_t tc = std::max<int64_t>(kKahanBlock, (c.chunk / kTailDiv + kKahanBlock - 1) / kKahanBlock * kKahanBlock);
         const int64_t tail = (N * kTailPercent / 100 + tc - 1) / tc * tc;
