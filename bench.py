@@ -37,22 +37,22 @@ FLOPS_PER_PAIR = 92       # algorithmic flops of one (target, source) evaluation
 # HBM bytes per pair-kernel launch from hardware counters (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, the factors a 256 MiB device copy reads), valid only for
 # the pair-kernel source (sha256 of the kernel file and its device header,
-# concatenated) and the exact work list (sha256 of the blocks
-# `mrs_plan_items` gives for the workload) they were taken on: any other
-# kernel or decomposition reports null.
+# concatenated), the exact work list (sha256 of the blocks `mrs_plan_items`
+# gives for the workload) and the schedule (0 grid, 1 persistent) they were
+# taken on: any other kernel, decomposition or schedule reports null.
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_12083_amd", "csrc", f) for f in ("mrs_pairs.hip", "mrs_device_pairs.h")]
 KERNEL_SHA = "40f34d49df4e05869d604daebf4eddf5ac4a3fb0ed492161478c62626b0aa46b"
 MEASURED_TRAFFIC = {
-    ("ens12800", "fp32c", "678ec7c5e5d82ecf"): (3544.88 * 2.0 + 37200.0) * 1024,
-    ("ens12800", "fp64", "adb3c89bda2d142d"): (4134.13 * 2.0 + 30000.0) * 1024,
-    ("ens256000", "fp32c", "4a2b01f9e8a27aa9"): (228559.03 * 2.0 + 264000.0) * 1024,
-    ("ens256000", "fp64", "571ba5e594123b76"): (470549.45 * 2.0 + 396000.0) * 1024,
-    ("swim", "fp32c", "72ec18efbf0e53ad"): (42130.44 * 2.0 + 176944.22) * 1024,
-    ("swim", "fp64", "df10004c75444124"): (90394.48 * 2.0 + 148220.80) * 1024,
+    ("ens12800", "fp32c", "678ec7c5e5d82ecf", 0): (3544.88 * 2.0 + 37200.0) * 1024,
+    ("ens12800", "fp64", "adb3c89bda2d142d", 0): (4134.13 * 2.0 + 30000.0) * 1024,
+    ("ens256000", "fp32c", "4a2b01f9e8a27aa9", 1): (321384.91 * 2.0 + 264767.56) * 1024,
+    ("ens256000", "fp64", "571ba5e594123b76", 1): (467335.21 * 2.0 + 396579.69) * 1024,
+    ("swim", "fp32c", "72ec18efbf0e53ad", 1): (41755.88 * 2.0 + 177654.17) * 1024,
+    ("swim", "fp64", "df10004c75444124", 0): (90352.73 * 2.0 + 148221.23) * 1024,
 }
 
 
-def measured_traffic(mrs, workload_name, tag, n, prec, n_cu):
+def measured_traffic(mrs, workload_name, tag, n, prec, n_cu, sched=0):
     import hashlib
 
     h = hashlib.sha256()
@@ -65,7 +65,7 @@ def measured_traffic(mrs, workload_name, tag, n, prec, n_cu):
     if h.hexdigest() != KERNEL_SHA:
         return None
     _, items = mrs.mrs_plan_items(n, prec, n_cu)
-    v = MEASURED_TRAFFIC.get((workload_name, tag, hashlib.sha256(items.tobytes()).hexdigest()[:16]))
+    v = MEASURED_TRAFFIC.get((workload_name, tag, hashlib.sha256(items.tobytes()).hexdigest()[:16], int(sched)))
     return None if v is None else round(v)
 
 
@@ -317,7 +317,8 @@ def bench_large(mrs, ctx, n_cu, reps32=3, reps64=2):
             out[tag] = {"evals": reps, "ms_per_eval": 1e3 * wall, "pairs_per_s": e.N * e.N / wall,
                         "pair_kernel_us": 1e3 * ms_k / n_k,
                         "roofline": roofline(e.N * e.N, 1e-3 * ms_k / n_k, peak,
-                                             measured_traffic(mrs, "ens256000", tag, e.N, prec, n_cu))}
+                                             measured_traffic(mrs, "ens256000", tag, e.N, prec, n_cu,
+                                                              mrs.mrs_tune_get(ctx, e.N, prec)["schedule"]))}
     finally:
         mrs.mrs_ensemble_destroy(ens)
     return out, subset
@@ -742,7 +743,8 @@ def main():
             log(f"measure {tag} N={e.N} steps={args.steps}")
             res[tag] = measure(mrs, ctx, e, prec, args.steps, args.warmup, args.dt, integ, swim)
             res[tag]["chunks"] = mrs.mrs_tune_get(ctx, e.N, prec)["chunks"]
-            res[tag]["traffic"] = measured_traffic(mrs, args.workload, tag, e.N, prec, n_cu)
+            res[tag]["traffic"] = measured_traffic(mrs, args.workload, tag, e.N, prec, n_cu,
+                                                   mrs.mrs_tune_get(ctx, e.N, prec)["schedule"])
         extra = args.workload == "ens12800" and not args.no_extra
         large = slices_leg = large_subset = copies_leg = None
         if extra:
