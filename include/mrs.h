@@ -349,8 +349,9 @@ mrs_status mrs_server_stop(mrs_server *srv);
  * 128 would give at most one block per compute unit).  An automatic FP32C
  * configuration of a large grid
  * also splits the last ~8% of every target tile's sources into shorter
- * chunks dispatched last; mrs_tune_get reports `chunks` as the total number
- * of chunks (partial sums per target). */
+ * chunks dispatched last, and a tiled configuration of at least 48 blocks
+ * per compute unit runs the persistent schedule; mrs_tune_get reports
+ * `chunks` as the total number of chunks (partial sums per target). */
 typedef struct {
     int32_t mode;
     int32_t targets_per_lane;
