@@ -416,7 +416,8 @@ mrs_status mrs_tune_load(mrs_context *ctx, const char *path);
  * *chunks and *tail_start (each may be NULL) receive the configuration
  * (chunks = partial sums per target; tail_start = first source of the short
  * tail chunks, n if there are none); *n_items receives the number of
- * blocks.  items (may be
+ * blocks (the schedule that runs them is reported by mrs_tune_get).  items
+ * (may be
  * NULL to query the count) receives 5 int32 per block: first target,
  * targets, first source, sources, partial-sum slot.  Errors: MRS_EINVAL for
  * n < 1 or too large, n_cu < 1, an unknown precision, a null n_items, or
