@@ -63,8 +63,12 @@ static bool split_mode(int64_t N, int) { return N <= 1024; }
 // the pair kernel: 256,000 points -1.3% FP32C and -1.5% FP64, 1,000
 // swimmers (51,000 points, 58 blocks per CU) -1.4% FP32C; the tuner's
 // one-shot evaluations: 102,400 points -1.3% and -1.1%); in shallow grids
-// it is much slower (12,800 points, 12 blocks per CU: +20%).
-constexpr int kPersistentBlocksPerCu = 48;
+// it is much slower (12,800 points, 12 blocks per CU: +20%).  The FP64
+// kernel at two targets per lane keeps four blocks per CU resident instead
+// of five, and from about six rounds of them (24 blocks per CU) the
+// persistent schedule won there too (51,200 points: -1.9% in the tuner;
+// 1,000 swimmers, 24 blocks per CU: -1.3% in interleaved A/B).
+constexpr int kPersistentBlocksPerCu = 48, kPersistentBlocksPerCuF64T2 = 24;
 
 PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
     PairCfg c;
@@ -103,8 +107,8 @@ PairCfg choose_cfg_for(const PairCfg *tuned, int64_t N, int prec, int n_cu) {
     c.K = (int)std::max<int64_t>(1, (N + c.chunk - 1) / c.chunk);
     c.k_big = c.K;
     c.tail_start = c.tail_chunk = 0;
-    if (!tuned && c.mode == PAIR_TILE && tiles * c.K >= (int64_t)kPersistentBlocksPerCu * n_cu)
-        c.sched = SCHED_PERSISTENT;
+    const int64_t deep = prec == MRS_FP64 && c.tpl == 2 ? kPersistentBlocksPerCuF64T2 : kPersistentBlocksPerCu;
+    if (!tuned && c.mode == PAIR_TILE && tiles * c.K >= deep * n_cu) c.sched = SCHED_PERSISTENT;
     if (automatic && prec == MRS_FP32C && tiles * c.K >= (int64_t)4 * n_cu) {
         const int64_t tc = std::max<int64_t>(kKahanBlock, (c.chunk / kTailDiv + kKahanBlock - 1) / kKahanBlock * kKahanBlock);
         const int64_t tail = (N * kTailPercent / 100 + tc - 1) / tc * tc;
