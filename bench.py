@@ -47,8 +47,8 @@ MEASURED_TRAFFIC = {
     ("ens12800", "fp64", "adb3c89bda2d142d", 0): (4134.13 * 2.0 + 30000.0) * 1024,
     ("ens256000", "fp32c", "4a2b01f9e8a27aa9", 1): (321384.91 * 2.0 + 264767.56) * 1024,
     ("ens256000", "fp64", "571ba5e594123b76", 1): (467335.21 * 2.0 + 396579.69) * 1024,
-    ("swim", "fp32c", "72ec18efbf0e53ad", 1): (41755.88 * 2.0 + 177654.17) * 1024,
-    ("swim", "fp64", "df10004c75444124", 0): (90352.73 * 2.0 + 148221.23) * 1024,
+    ("swim", "fp32c", "72ec18efbf0e53ad", 1): (41684.76 * 2.0 + 177658.77) * 1024,
+    ("swim", "fp64", "df10004c75444124", 1): (74857.08 * 2.0 + 148478.23) * 1024,
 }
 
 

@@ -350,7 +350,8 @@ mrs_status mrs_server_stop(mrs_server *srv);
  * configuration of a large grid
  * also splits the last ~8% of every target tile's sources into shorter
  * chunks dispatched last, and a tiled configuration of at least 48 blocks
- * per compute unit runs the persistent schedule; mrs_tune_get reports
+ * per compute unit (24 for FP64 at two targets per lane) runs the
+ * persistent schedule; mrs_tune_get reports
  * `chunks` as the total number of chunks (partial sums per target). */
 typedef struct {
     int32_t mode;
