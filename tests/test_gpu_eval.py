@@ -223,6 +223,24 @@ def test_fp32c_tail_split_config(mrs):
         mrs.mrs_context_destroy(c)
 
 
+def test_automatic_schedule_by_grid_depth(mrs):
+    """Automatic tiled configurations of grids of at least 48 blocks per CU
+    (24 for FP64 at two targets per lane) run the persistent schedule,
+    shallower ones the hardware grid; a stored configuration keeps its own
+    schedule."""
+    c = mrs.mrs_context_create(0)
+    try:
+        sched = lambda n, p: mrs.mrs_tune_get(c, n, p)["schedule"]
+        assert sched(12800, 1) == 0 and sched(12800, 0) == 0
+        assert sched(25600, 1) == 0 and sched(25600, 0) == 0
+        assert sched(51000, 1) == 1 and sched(51000, 0) == 1
+        assert sched(256000, 1) == 1 and sched(256000, 0) == 1
+        mrs.mrs_tune_set(c, 256000, 1, 0, 1, 0, 0)
+        assert sched(256000, 1) == 0
+    finally:
+        mrs.mrs_context_destroy(c)
+
+
 @pytest.mark.parametrize("tpl", [1, 2])
 def test_fp32c_near_pairs_across_filaments(mrs, tpl):
     """Filaments crossing through one small region: near pairs (r < 4 eps)
